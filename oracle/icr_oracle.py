@@ -1,0 +1,400 @@
+"""Plain FP64 CPU oracle of Iterative Charted Refinement (ICR).
+
+TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU-baseline leg
+of the benchmark import this module. The library (HIP kernels behind the C ABI)
+never calls it, and it shares no code with the library.
+
+What it computes (NIFTy.re, section "Gaussian Processes"; the paper defers the
+details of ICR to Edenhofer et al. 2022). A Gaussian-process sample s = L xi is
+drawn from standard-normal excitations xi (section "Standardization": the prior
+of every latent parameter is N(0, 1)) level by level:
+
+  * level 0: s_0 = chol(K_00) xi_0 over the n_0^d pixels of the coarsest grid;
+  * level l -> l+1: every interior coarse pixel c (all of whose 3^d neighbours
+    exist) spawns 2^d fine pixels. Their values are the GP conditional mean given
+    the 3^d window, R_l s_l[c + W], plus sqrt(D_l) times fresh excitations, with
+    R_l = K_fc K_cc^-1 and D_l = K_ff - K_fc K_cc^-1 K_cf (textbook GP
+    conditioning, Rasmussen & Williams 2006, eq. 2.19).
+
+The adjoint L^T is the exact transpose of that sweep, and the metric of a
+Gaussian likelihood in standardized coordinates is M = L^T N^-1 L + 1 (section
+"Performance of NIFTy.re compared to NIFTy": the Fisher metric plus the identity).
+
+Readings where the paper is silent (each listed in the design doc):
+  * children sit at +-delta/4 per axis around their coarse pixel, so the fine grid
+    has spacing delta/2 and n_{l+1} = 2 (n_l - 2); border coarse pixels only take
+    part in windows;
+  * windows W = {-1,0,1}^d and children {0,1}^d are ordered lexicographically with
+    the last axis fastest; xi is stored level by level, each level in C order;
+  * sqrt(D) is the lower Cholesky factor, and a pivot <= tau = 3^d eps k(0) is
+    clamped (its column set to zero and counted) instead of failing;
+  * the log-radial chart maps index coordinates (u, v) to
+    (r0 e^(g u) cos(a v), r0 e^(g u) sin(a v)).
+
+Every function here is pinned by a test in tests/test_oracle_*.py against closed
+forms, invariants or library routines; none is "parity unpinned".
+"""
+
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EPS64 = float(np.finfo(np.float64).eps)
+
+KERNELS = ("matern12", "matern32", "matern52", "sqexp")
+CHARTS = ("regular", "logradial2d")
+
+
+class NotPositiveDefinite(ValueError):
+    """A factorisation met a non-positive pivot where clamping is not allowed."""
+
+
+# ---------------------------------------------------------------------------
+# Kernels (standard stationary forms, Rasmussen & Williams 2006, section 4.2)
+# ---------------------------------------------------------------------------
+
+def kernel_values(kind: str, r, scale: float, length: float) -> np.ndarray:
+    """Covariance k(r) for Euclidean distance r; k(0) = scale**2."""
+    t = np.asarray(r, dtype=np.float64) / float(length)
+    if kind == "matern12":
+        k = np.exp(-t)
+    elif kind == "matern32":
+        a = math.sqrt(3.0) * t
+        k = (1.0 + a) * np.exp(-a)
+    elif kind == "matern52":
+        a = math.sqrt(5.0) * t
+        k = (1.0 + a + a * a / 3.0) * np.exp(-a)
+    elif kind == "sqexp":
+        k = np.exp(-0.5 * t * t)
+    else:
+        raise ValueError(f"unknown kernel {kind!r}")
+    return float(scale) ** 2 * k
+
+
+def pairwise_distance(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Euclidean distances between point sets a (..., m, dim) and b (..., n, dim)."""
+    diff = a[..., :, None, :] - b[..., None, :, :]
+    return np.sqrt(np.sum(diff * diff, axis=-1))
+
+
+# ---------------------------------------------------------------------------
+# Geometry
+# ---------------------------------------------------------------------------
+
+def level_shapes(shape0, depth: int) -> list[tuple[int, ...]]:
+    """Grid shape of every level: n_{l+1} = 2 (n_l - 2) per axis."""
+    shapes = [tuple(int(n) for n in shape0)]
+    for _ in range(depth):
+        prev = shapes[-1]
+        if min(prev) < 3:
+            raise ValueError(f"a level of shape {prev} has no interior pixel to refine")
+        shapes.append(tuple(2 * (n - 2) for n in prev))
+    return shapes
+
+
+def level_spacings(delta0, depth: int) -> list[np.ndarray]:
+    """Pixel spacing per axis at every level: delta_l = delta_0 / 2^l."""
+    d0 = np.asarray(delta0, dtype=np.float64)
+    return [d0 / 2.0 ** l for l in range(depth + 1)]
+
+
+def level_origins(delta0, depth: int) -> list[np.ndarray]:
+    """Position of pixel 0 at every level: o_0 = 0, o_{l+1} = o_l + 3/4 delta_l.
+
+    Fine pixel 0 is the lower child of coarse pixel 1, which sits at
+    o_l + delta_l - delta_l / 4.
+    """
+    spac = level_spacings(delta0, depth)
+    org = [np.zeros_like(spac[0])]
+    for l in range(depth):
+        org.append(org[-1] + 0.75 * spac[l])
+    return org
+
+
+def window_offsets(ndim: int) -> np.ndarray:
+    """The 3^d window offsets {-1,0,1}^d, lexicographic, last axis fastest."""
+    return np.array(list(itertools.product((-1, 0, 1), repeat=ndim)), dtype=np.int64)
+
+
+def child_offsets(ndim: int) -> np.ndarray:
+    """The 2^d child offsets {0,1}^d, lexicographic, last axis fastest."""
+    return np.array(list(itertools.product((0, 1), repeat=ndim)), dtype=np.int64)
+
+
+def grid_indices(shape) -> np.ndarray:
+    """All multi-indices of a grid in C order, shape (prod(shape), ndim)."""
+    return np.stack(np.meshgrid(*[np.arange(n) for n in shape], indexing="ij"),
+                    axis=-1).reshape(-1, len(shape))
+
+
+def logradial_chart(points: np.ndarray, params) -> np.ndarray:
+    """Map index-space points (u, v) to (r cos theta, r sin theta).
+
+    r = r0 exp(g u) and theta = a v with params = (r0, g, a).
+    """
+    r0, g, a = float(params[0]), float(params[1]), float(params[2])
+    r = r0 * np.exp(g * points[..., 0])
+    th = a * points[..., 1]
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=-1)
+
+
+# ---------------------------------------------------------------------------
+# Clamped Cholesky
+# ---------------------------------------------------------------------------
+
+def clamped_cholesky(a: np.ndarray, tau: float, clamp: bool = True):
+    """Lower Cholesky factor of symmetric a (..., n, n), column by column.
+
+    Column j of the Schur complement is a[j:, j] - L[j:, :j] L[j, :j]^T. A pivot
+    at or below tau makes column j of L zero (and is counted) when clamp is True,
+    else NotPositiveDefinite is raised. Returns (L, number of clamped pivots).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[-1]
+    low = np.zeros_like(a)
+    count = np.zeros(a.shape[:-2], dtype=np.int64)
+    for j in range(n):
+        col = a[..., j:, j] - (low[..., j:, :j] @ low[..., j, :j][..., None])[..., 0]
+        piv = col[..., 0]
+        bad = ~(piv > tau)
+        if np.any(bad) and not clamp:
+            raise NotPositiveDefinite(f"pivot {j} is {np.min(piv)!r} <= {tau!r}")
+        root = np.sqrt(np.where(bad, 1.0, piv))
+        low[..., j:, j] = np.where(bad[..., None], 0.0, col / root[..., None])
+        count += bad
+    return low, count
+
+
+def pivot_threshold(ndim: int, scale: float) -> float:
+    """Clamp threshold tau = 3^d eps_64 k(0)."""
+    return 3.0 ** ndim * EPS64 * float(scale) ** 2
+
+
+# ---------------------------------------------------------------------------
+# Conditioning matrices: R = K_fc K_cc^-1, D = K_ff - R K_cf, sqrt(D)
+# ---------------------------------------------------------------------------
+
+def conditional_matrices(kind, scale, length, win_pos, child_pos, tau, clamp=True):
+    """Refinement matrix and lower sqrt of the conditional covariance.
+
+    win_pos: (..., 3^d, dim) physical window positions; child_pos: (..., 2^d, dim).
+    Returns R (..., 2^d, 3^d), sqrtD (..., 2^d, 2^d), clamped-pivot counts (...).
+    """
+    k_cc = kernel_values(kind, pairwise_distance(win_pos, win_pos), scale, length)
+    k_fc = kernel_values(kind, pairwise_distance(child_pos, win_pos), scale, length)
+    k_ff = kernel_values(kind, pairwise_distance(child_pos, child_pos), scale, length)
+    try:
+        np.linalg.cholesky(k_cc)  # K_cc must be positive definite for the solve
+    except np.linalg.LinAlgError as exc:
+        raise NotPositiveDefinite("window covariance K_cc is not positive definite") from exc
+    # R K_cc = K_fc  <=>  K_cc R^T = K_cf (K_cc symmetric)
+    r_mat = np.swapaxes(np.linalg.solve(k_cc, np.swapaxes(k_fc, -1, -2)), -1, -2)
+    d_mat = k_ff - r_mat @ np.swapaxes(k_fc, -1, -2)
+    d_mat = 0.5 * (d_mat + np.swapaxes(d_mat, -1, -2))
+    sqrt_d, count = clamped_cholesky(d_mat, tau, clamp)
+    return r_mat, sqrt_d, count
+
+
+# ---------------------------------------------------------------------------
+# The ICR model
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ICRConfig:
+    """Parameters of one ICR prior (all lengths in the chart's index units)."""
+    ndim: int
+    shape0: tuple
+    depth: int
+    delta0: tuple
+    kernel: str = "matern32"
+    scale: float = 1.0
+    length: float = 0.1
+    chart: str = "regular"
+    chart_params: tuple = (0.1, math.log(10.0), 0.5 * math.pi)
+    clamp: bool = True
+
+
+@dataclass
+class ICROracle:
+    cfg: ICRConfig
+    shapes: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)
+    n_xi: int = 0
+    l00: np.ndarray | None = None
+    r_mats: list = field(default_factory=list)      # per level: (2^d,3^d) or (*n_int, 2^d, 3^d)
+    sqrt_ds: list = field(default_factory=list)     # per level: (2^d,2^d) or (*n_int, 2^d, 2^d)
+    clamped: list = field(default_factory=list)     # per level (and level 0 first)
+
+    # -- sizes ---------------------------------------------------------------
+    @property
+    def out_size(self) -> int:
+        return int(np.prod(self.shapes[-1]))
+
+    def level_slice(self, l: int) -> slice:
+        return slice(self.offsets[l], self.offsets[l] + int(np.prod(self.shapes[l])))
+
+    # -- forward -------------------------------------------------------------
+    def forward(self, xi: np.ndarray, return_levels: bool = False):
+        """s = L xi for xi of shape (..., N_xi); returns s_L (..., prod(n_L))."""
+        d = self.cfg.ndim
+        xi = np.asarray(xi, dtype=np.float64)
+        batch = xi.shape[:-1]
+        s = (xi[..., self.level_slice(0)] @ self.l00.T).reshape(batch + self.shapes[0])
+        levels = [s]
+        for l in range(self.cfg.depth):
+            xi_f = xi[..., self.level_slice(l + 1)].reshape(batch + self.shapes[l + 1])
+            s = refine(s, xi_f, self.r_mats[l], self.sqrt_ds[l], d)
+            levels.append(s)
+        flat = [v.reshape(batch + (-1,)) for v in levels]
+        return (flat[-1], flat) if return_levels else flat[-1]
+
+    # -- adjoint -------------------------------------------------------------
+    def adjoint(self, ybar: np.ndarray, return_levels: bool = False):
+        """xi_bar = L^T ybar for ybar of shape (..., prod(n_L)); returns (..., N_xi)."""
+        d = self.cfg.ndim
+        ybar = np.asarray(ybar, dtype=np.float64)
+        batch = ybar.shape[:-1]
+        out = np.zeros(batch + (self.n_xi,))
+        y = ybar.reshape(batch + self.shapes[-1])
+        cot = [None] * (self.cfg.depth + 1)
+        cot[-1] = y
+        for l in reversed(range(self.cfg.depth)):
+            xi_bar_f, y = refine_adjoint(y, self.r_mats[l], self.sqrt_ds[l], d, self.shapes[l])
+            out[..., self.level_slice(l + 1)] = xi_bar_f.reshape(batch + (-1,))
+            cot[l] = y
+        out[..., self.level_slice(0)] = y.reshape(batch + (-1,)) @ self.l00
+        if return_levels:
+            return out, [c.reshape(batch + (-1,)) for c in cot]
+        return out
+
+    # -- metric --------------------------------------------------------------
+    def metric(self, w: np.ndarray, v: np.ndarray) -> np.ndarray:
+        """M v = L^T (w * (L v)) + v, with w the inverse noise variance per pixel."""
+        return self.adjoint(np.asarray(w, dtype=np.float64) * self.forward(v)) + v
+
+    # -- dense ---------------------------------------------------------------
+    def dense(self) -> np.ndarray:
+        """Dense L (prod(n_L) x N_xi) built column by column from the forward."""
+        return self.forward(np.eye(self.n_xi)).T
+
+    def dense_adjoint(self) -> np.ndarray:
+        """Dense L^T (N_xi x prod(n_L)) built column by column from the adjoint."""
+        return self.adjoint(np.eye(self.out_size)).T
+
+
+def refine(s: np.ndarray, xi_f: np.ndarray, r_mat, sqrt_d, ndim: int) -> np.ndarray:
+    """One forward level: fine = R s[window] + sqrt(D) xi for every interior coarse pixel.
+
+    s: (..., n_c...), xi_f: (..., 2(n_c - 2)...). r_mat is (2^d, 3^d) for a stationary
+    level or (*n_int, 2^d, 3^d) per interior coarse pixel (charted); same for sqrt_d.
+    """
+    batch = s.shape[:-ndim]
+    nc = s.shape[-ndim:]
+    wins = window_offsets(ndim)
+    kids = child_offsets(ndim)
+    out = np.empty(batch + tuple(2 * (n - 2) for n in nc))
+    lead = (Ellipsis,)
+    for ib, b in enumerate(kids):
+        acc = np.zeros(batch + tuple(n - 2 for n in nc))
+        for iw, w in enumerate(wins):
+            window = s[lead + tuple(slice(1 + w[a], nc[a] - 1 + w[a]) for a in range(ndim))]
+            acc = acc + _coef(r_mat, ib, iw) * window
+        for jb, bp in enumerate(kids):
+            fresh = xi_f[lead + tuple(slice(bp[a], None, 2) for a in range(ndim))]
+            acc = acc + _coef(sqrt_d, ib, jb) * fresh
+        out[lead + tuple(slice(b[a], None, 2) for a in range(ndim))] = acc
+    return out
+
+
+def refine_adjoint(ybar_f: np.ndarray, r_mat, sqrt_d, ndim: int, nc):
+    """Transpose of `refine`: returns (xi_bar of the fine level, s_bar of the coarse level).
+
+    The coarse cotangent is accumulated by scatter-add in FP64, the plain reading of
+    the transpose.
+    """
+    batch = ybar_f.shape[:-ndim]
+    wins = window_offsets(ndim)
+    kids = child_offsets(ndim)
+    lead = (Ellipsis,)
+    blocks = [ybar_f[lead + tuple(slice(b[a], None, 2) for a in range(ndim))] for b in kids]
+    xi_bar = np.empty_like(ybar_f)
+    for jb, bp in enumerate(kids):
+        acc = sum(_coef(sqrt_d, ib, jb) * blocks[ib] for ib in range(len(kids)))
+        xi_bar[lead + tuple(slice(bp[a], None, 2) for a in range(ndim))] = acc
+    s_bar = np.zeros(batch + tuple(nc))
+    for iw, w in enumerate(wins):
+        acc = sum(_coef(r_mat, ib, iw) * blocks[ib] for ib in range(len(kids)))
+        s_bar[lead + tuple(slice(1 + w[a], nc[a] - 1 + w[a]) for a in range(ndim))] += acc
+    return xi_bar, s_bar
+
+
+def _coef(mat, i, j):
+    """Entry (i, j) of a shared matrix, or the per-pixel field of entries of a stack."""
+    return mat[..., i, j]
+
+
+# ---------------------------------------------------------------------------
+# Building a model
+# ---------------------------------------------------------------------------
+
+def _positions(cfg: ICRConfig, idx_points: np.ndarray) -> np.ndarray:
+    if cfg.chart == "regular":
+        return idx_points
+    if cfg.chart == "logradial2d":
+        if cfg.ndim != 2:
+            raise ValueError("the log-radial chart is two-dimensional")
+        return logradial_chart(idx_points, cfg.chart_params)
+    raise ValueError(f"unknown chart {cfg.chart!r}")
+
+
+def build(cfg: ICRConfig) -> ICROracle:
+    """Level sizes, level-0 Cholesky factor and per-level R, sqrt(D) in FP64."""
+    if cfg.ndim not in (1, 2, 3):
+        raise ValueError("ndim must be 1, 2 or 3")
+    if cfg.kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {cfg.kernel!r}")
+    d = cfg.ndim
+    model = ICROracle(cfg)
+    model.shapes = level_shapes(cfg.shape0, cfg.depth)
+    sizes = [int(np.prod(s)) for s in model.shapes]
+    model.offsets = [int(v) for v in np.concatenate([[0], np.cumsum(sizes)[:-1]])]
+    model.n_xi = int(sum(sizes))
+    spac = level_spacings(cfg.delta0, cfg.depth)
+    org = level_origins(cfg.delta0, cfg.depth)
+    tau = pivot_threshold(d, cfg.scale)
+
+    # level 0: dense Cholesky of the kernel over all n_0^d pixels, C order
+    x0 = _positions(cfg, org[0] + grid_indices(model.shapes[0]) * spac[0])
+    k00 = kernel_values(cfg.kernel, pairwise_distance(x0, x0), cfg.scale, cfg.length)
+    model.l00, c0 = clamped_cholesky(k00, tau, cfg.clamp)
+    model.clamped = [int(c0)]
+
+    wins = window_offsets(d).astype(np.float64)
+    kids = child_offsets(d).astype(np.float64)
+    for l in range(cfg.depth):
+        dl = spac[l]
+        if cfg.chart == "regular":
+            # stationary: one set per level, geometry relative to the coarse pixel
+            win_pos = wins * dl
+            child_pos = (kids - 0.5) * dl / 2.0
+        else:
+            n_int = tuple(n - 2 for n in model.shapes[l])
+            centre = org[l] + (grid_indices(n_int) + 1) * dl             # (P, d)
+            win_idx = centre[:, None, :] + wins[None] * dl               # (P, 3^d, d)
+            kid_idx = centre[:, None, :] + (kids[None] - 0.5) * dl / 2.0
+            win_pos = _positions(cfg, win_idx)
+            child_pos = _positions(cfg, kid_idx)
+        r_mat, sqrt_d, cnt = conditional_matrices(cfg.kernel, cfg.scale, cfg.length,
+                                                  win_pos, child_pos, tau, cfg.clamp)
+        if cfg.chart != "regular":
+            n_int = tuple(n - 2 for n in model.shapes[l])
+            r_mat = r_mat.reshape(n_int + r_mat.shape[-2:])
+            sqrt_d = sqrt_d.reshape(n_int + sqrt_d.shape[-2:])
+        model.r_mats.append(r_mat)
+        model.sqrt_ds.append(sqrt_d)
+        model.clamped.append(int(np.sum(cnt)))
+    return model
