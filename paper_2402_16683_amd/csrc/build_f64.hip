@@ -1,0 +1,366 @@
+// FP64 device build of the ICR matrices.
+//
+//  * K_00 over all level-0 pixels and its lower Cholesky factor (one workgroup,
+//    right-looking, pivots at or below tau clamped to a zero column);
+//  * per level (stationary grid) or per interior coarse pixel (chart): the window
+//    covariance K_cc, the cross covariance K_fc and the child covariance K_ff,
+//    R = K_fc K_cc^-1 through the Cholesky factor of K_cc, D = K_ff - R K_cf
+//    (symmetrised) and its clamped lower Cholesky factor sqrtD.
+// This is GP conditioning on the 3^d window (Rasmussen & Williams 2006, eq. 2.19),
+// the construction NIFTy.re's ICR model refines with (section "Gaussian Processes").
+#include "icr_internal.h"
+
+namespace icr {
+namespace {
+
+struct KernelSpec {
+  int kind;
+  double sigma2;
+  double length;
+};
+
+struct ChartSpec {
+  int chart;
+  double p0, p1, p2;
+};
+
+__device__ double kernel_value(const KernelSpec& k, double r) {
+  const double t = r / k.length;
+  double v;
+  switch (k.kind) {
+    case ICR_MATERN12: v = exp(-t); break;
+    case ICR_MATERN32: { const double a = 1.7320508075688772 * t; v = (1.0 + a) * exp(-a); break; }
+    case ICR_MATERN52: { const double a = 2.23606797749979 * t; v = (1.0 + a + a * a / 3.0) * exp(-a); break; }
+    default: v = exp(-0.5 * t * t); break;
+  }
+  return k.sigma2 * v;
+}
+
+// index-space point -> physical point (D = 2 for the log-radial chart)
+template <int D>
+__device__ void chart_map(const ChartSpec& c, const double* x, double* y) {
+  if (D == 2 && c.chart == ICR_CHART_LOGRADIAL_2D) {
+    const double r = c.p0 * exp(c.p1 * x[0]);
+    const double th = c.p2 * x[1];
+    y[0] = r * cos(th);
+    y[1] = r * sin(th);
+  } else {
+    for (int a = 0; a < D; ++a) y[a] = x[a];
+  }
+}
+
+template <int D>
+__device__ double distance(const double* a, const double* b) {
+  double s = 0.0;
+  for (int k = 0; k < D; ++k) { const double d = a[k] - b[k]; s += d * d; }
+  return sqrt(s);
+}
+
+// Conditioning matrices of one window. win: [NW][D], kid: [NC][D] physical
+// positions. Writes R [NC][NW] and sqrtD [NC][NC] (lower). Returns the number of
+// clamped pivots, or -1 if K_cc is not positive definite or a pivot of D needed
+// clamping with clamping disabled.
+template <int D>
+__device__ int condition_window(const KernelSpec& ks, const double* win, const double* kid,
+                                double tau, bool clamp, double* r_out, double* s_out) {
+  constexpr int NW = pow3(D);
+  constexpr int NC = 1 << D;
+  double lc[NW * NW];   // K_cc, factorised in place (lower)
+  double kfc[NC * NW];
+  double dm[NC * NC];
+  for (int i = 0; i < NW; ++i)
+    for (int j = 0; j <= i; ++j)
+      lc[i * NW + j] = kernel_value(ks, distance<D>(win + i * D, win + j * D));
+  for (int b = 0; b < NC; ++b)
+    for (int w = 0; w < NW; ++w)
+      kfc[b * NW + w] = kernel_value(ks, distance<D>(kid + b * D, win + w * D));
+
+  // Cholesky of K_cc, no clamping (R needs its inverse)
+  for (int j = 0; j < NW; ++j) {
+    double piv = lc[j * NW + j];
+    for (int k = 0; k < j; ++k) piv -= lc[j * NW + k] * lc[j * NW + k];
+    if (!(piv > 0.0)) return -1;
+    const double root = sqrt(piv);
+    lc[j * NW + j] = root;
+    for (int i = j + 1; i < NW; ++i) {
+      double v = lc[i * NW + j];
+      for (int k = 0; k < j; ++k) v -= lc[i * NW + k] * lc[j * NW + k];
+      lc[i * NW + j] = v / root;
+    }
+  }
+  // R[b, :] = K_cc^-1 K_cf[:, b]: forward then backward substitution
+  for (int b = 0; b < NC; ++b) {
+    double* x = r_out + b * NW;
+    for (int i = 0; i < NW; ++i) {
+      double v = kfc[b * NW + i];
+      for (int k = 0; k < i; ++k) v -= lc[i * NW + k] * x[k];
+      x[i] = v / lc[i * NW + i];
+    }
+    for (int i = NW - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < NW; ++k) v -= lc[k * NW + i] * x[k];
+      x[i] = v / lc[i * NW + i];
+    }
+  }
+  // D = K_ff - R K_cf, symmetrised
+  for (int b = 0; b < NC; ++b)
+    for (int c = 0; c < NC; ++c) {
+      double v = kernel_value(ks, distance<D>(kid + b * D, kid + c * D));
+      for (int w = 0; w < NW; ++w) v -= r_out[b * NW + w] * kfc[c * NW + w];
+      dm[b * NC + c] = v;
+    }
+  for (int b = 0; b < NC; ++b)
+    for (int c = 0; c < b; ++c) {
+      const double m = 0.5 * (dm[b * NC + c] + dm[c * NC + b]);
+      dm[b * NC + c] = m;
+      dm[c * NC + b] = m;
+    }
+  // clamped lower Cholesky of D, column by column
+  int clamped = 0;
+  for (int i = 0; i < NC * NC; ++i) s_out[i] = 0.0;
+  for (int j = 0; j < NC; ++j) {
+    double piv = dm[j * NC + j];
+    for (int k = 0; k < j; ++k) piv -= s_out[j * NC + k] * s_out[j * NC + k];
+    if (!(piv > tau)) {
+      if (!clamp) return -1;
+      ++clamped;  // column j stays zero
+      continue;
+    }
+    const double root = sqrt(piv);
+    s_out[j * NC + j] = root;
+    for (int i = j + 1; i < NC; ++i) {
+      double v = dm[i * NC + j];
+      for (int k = 0; k < j; ++k) v -= s_out[i * NC + k] * s_out[j * NC + k];
+      s_out[i * NC + j] = v / root;
+    }
+  }
+  return clamped;
+}
+
+struct LevelGeom {
+  double origin[3];   // index-space origin o_l per axis (natural axis order)
+  double spacing[3];  // delta_l per axis
+  int interior[3];    // interior coarse pixels per axis (natural order)
+  int64_t nsets;
+};
+
+// One thread per set: a stationary level has one set, a charted level one per
+// interior coarse pixel (C order).
+template <int D>
+__global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, double tau, int clamp,
+                                   double* __restrict__ r64, double* __restrict__ s64,
+                                   int32_t* __restrict__ count, int32_t* __restrict__ status) {
+  constexpr int NW = pow3(D);
+  constexpr int NC = 1 << D;
+  const int64_t set = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (set >= g.nsets) return;
+  double centre[D];
+  if (cs.chart == ICR_CHART_REGULAR) {
+    for (int a = 0; a < D; ++a) centre[a] = 0.0;  // only relative positions matter
+  } else {
+    int64_t rem = set;
+    for (int a = D - 1; a >= 0; --a) {
+      const int ca = static_cast<int>(rem % g.interior[a]) + 1;
+      rem /= g.interior[a];
+      centre[a] = g.origin[a] + ca * g.spacing[a];
+    }
+  }
+  double win[NW * D], kid[NC * D], pt[D];
+  for (int w = 0; w < NW; ++w) {
+    int rem = w;
+    for (int a = D - 1; a >= 0; --a) {
+      pt[a] = centre[a] + ((rem % 3) - 1) * g.spacing[a];
+      rem /= 3;
+    }
+    chart_map<D>(cs, pt, win + w * D);
+  }
+  for (int b = 0; b < NC; ++b) {
+    for (int a = 0; a < D; ++a) {
+      const int ba = (b >> (D - 1 - a)) & 1;
+      pt[a] = centre[a] + (ba - 0.5) * 0.5 * g.spacing[a];
+    }
+    chart_map<D>(cs, pt, kid + b * D);
+  }
+  const int n = condition_window<D>(ks, win, kid, tau, clamp != 0, r64 + set * NC * NW,
+                                    s64 + set * NC * NC);
+  if (n < 0) atomicOr(status, 1);
+  else if (n > 0) atomicAdd(count, n);
+}
+
+// K_00[i][j] = k(|x_i - x_j|) over the level-0 pixels in C order.
+template <int D>
+__global__ void build_k00_kernel(KernelSpec ks, ChartSpec cs, int n0a, int n0b, int n0c,
+                                 double d0, double d1, double d2, int64_t n, double* __restrict__ a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.y);
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int shp[3] = {n0a, n0b, n0c};
+  const double sp[3] = {d0, d1, d2};
+  double xi[D], xj[D], pi[D], pj[D];
+  int64_t ri = i, rj = j;
+  for (int ax = D - 1; ax >= 0; --ax) {
+    xi[ax] = static_cast<double>(ri % shp[ax]) * sp[ax];
+    xj[ax] = static_cast<double>(rj % shp[ax]) * sp[ax];
+    ri /= shp[ax];
+    rj /= shp[ax];
+  }
+  chart_map<D>(cs, xi, pi);
+  chart_map<D>(cs, xj, pj);
+  a[i * n + j] = kernel_value(ks, distance<D>(pi, pj));
+}
+
+// Right-looking Cholesky of the n x n matrix a (row-major, in place, lower), one
+// workgroup. A pivot at or below tau makes its column zero and is counted.
+__global__ void __launch_bounds__(1024) cholesky_level0_kernel(double* __restrict__ a, int64_t n,
+                                                               double tau, int clamp,
+                                                               int32_t* __restrict__ count,
+                                                               int32_t* __restrict__ status) {
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  int clamped = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    __syncthreads();  // the previous trailing update is complete
+    const double piv = a[j * n + j];
+    __syncthreads();  // every thread holds the pivot before column j is written
+    if (!(piv > tau)) {  // uniform across the workgroup
+      ++clamped;
+      for (int64_t i = j + tid; i < n; i += nthreads) a[i * n + j] = 0.0;
+      continue;  // a zero column leaves the trailing matrix unchanged
+    }
+    const double root = sqrt(piv);
+    const double inv = 1.0 / root;
+    for (int64_t i = j + 1 + tid; i < n; i += nthreads) a[i * n + j] *= inv;
+    if (tid == 0) a[j * n + j] = root;
+    __syncthreads();
+    // trailing update of the lower triangle: a[i][k] -= a[i][j] a[k][j], j < k <= i
+    const int tx = tid & 31, ty = tid >> 5, ny = nthreads >> 5;
+    for (int64_t i = j + 1 + ty; i < n; i += ny) {
+      const double lij = a[i * n + j];
+      for (int64_t k = j + 1 + tx; k <= i; k += 32) a[i * n + k] -= lij * a[k * n + j];
+    }
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < n * n; t += nthreads) {
+    const int64_t i = t / n, k = t % n;
+    if (k > i) a[t] = 0.0;
+  }
+  if (tid == 0) {
+    *count = clamped;
+    if (clamped > 0 && !clamp) atomicOr(status, 2);
+  }
+}
+
+template <typename TA>
+__global__ void convert_level0_kernel(const double* __restrict__ l64, int64_t n,
+                                      TA* __restrict__ lower, TA* __restrict__ upper) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  lower[i * n + j] = static_cast<TA>(l64[i * n + j]);
+  upper[i * n + j] = static_cast<TA>(l64[j * n + i]);
+}
+
+// stationary: copy [NC][NW] as is; charted: transpose to [entry][set]
+template <typename TA>
+__global__ void convert_level_kernel(const double* __restrict__ src, int64_t nsets, int entries,
+                                     int charted, TA* __restrict__ dst) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nsets * entries) return;
+  const int64_t set = t / entries;
+  const int e = static_cast<int>(t % entries);
+  const TA v = static_cast<TA>(src[t]);
+  if (charted) dst[static_cast<int64_t>(e) * nsets + set] = v;
+  else dst[t] = v;
+}
+
+KernelSpec kernel_spec(const icr_plan* p) {
+  return KernelSpec{p->cfg.kernel, p->cfg.scale * p->cfg.scale, p->cfg.length};
+}
+ChartSpec chart_spec(const icr_plan* p) {
+  return ChartSpec{p->cfg.chart, p->cfg.chart_params[0], p->cfg.chart_params[1],
+                   p->cfg.chart_params[2]};
+}
+double tau_of(const icr_plan* p) {
+  double t = 2.220446049250313e-16 * p->cfg.scale * p->cfg.scale;
+  for (int a = 0; a < p->ndim; ++a) t *= 3.0;
+  return t;
+}
+
+}  // namespace
+
+hipError_t launch_build_k00(const icr_plan* p, double* a, hipStream_t st) {
+  const int64_t n = p->n0;
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n));
+  const int* s = p->cfg.shape0;
+  const double* d = p->cfg.distances0;
+  switch (p->ndim) {
+    case 1: build_k00_kernel<1><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], 1, 1, d[0], 0, 0, n, a); break;
+    case 2: build_k00_kernel<2><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], s[1], 1, d[0], d[1], 0, n, a); break;
+    default: build_k00_kernel<3><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], s[1], s[2], d[0], d[1], d[2], n, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_level0(const icr_plan* p, double* a, int32_t* counts, int32_t* status,
+                                  hipStream_t st) {
+  const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
+  cholesky_level0_kernel<<<1, 1024, 0, st>>>(a, p->n0, tau_of(p), clamp, counts, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_level0_convert(const icr_plan* p, hipStream_t st) {
+  const int64_t n = p->n0;
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n));
+  if (p->precision == ICR_F64)
+    convert_level0_kernel<double><<<grid, 256, 0, st>>>(p->l00_64, n, static_cast<double*>(p->l00_c),
+                                                        static_cast<double*>(p->u00_c));
+  else
+    convert_level0_kernel<float><<<grid, 256, 0, st>>>(p->l00_64, n, static_cast<float*>(p->l00_c),
+                                                       static_cast<float*>(p->u00_c));
+  return hipGetLastError();
+}
+
+hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int32_t* status,
+                              hipStream_t st) {
+  const int d = p->ndim;
+  LevelGeom g;
+  for (int a = 0; a < 3; ++a) {
+    g.origin[a] = a < d ? p->origins[level][a] : 0.0;
+    g.spacing[a] = a < d ? p->spacings[level][a] : 0.0;
+    g.interior[a] = a < d ? p->shapes[level][3 - d + a] - 2 : 1;
+  }
+  g.nsets = p->lev[level].nsets;
+  const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
+  const unsigned threads = 64;
+  const unsigned blocks = static_cast<unsigned>((g.nsets + threads - 1) / threads);
+  const LevelMats& m = p->lev[level];
+  switch (d) {
+    case 1: build_level_kernel<1><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
+    case 2: build_level_kernel<2><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
+    default: build_level_kernel<3><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st) {
+  const LevelMats& m = p->lev[level];
+  const int nc = 1 << p->ndim;
+  const int nw = pow3(p->ndim);
+  const unsigned threads = 256;
+  for (int which = 0; which < 2; ++which) {
+    const int entries = which == 0 ? nc * nw : nc * nc;
+    const double* src = which == 0 ? m.r64 : m.s64;
+    void* dst = which == 0 ? m.r_c : m.s_c;
+    const int64_t total = m.nsets * entries;
+    const unsigned blocks = static_cast<unsigned>((total + threads - 1) / threads);
+    if (p->precision == ICR_F64)
+      convert_level_kernel<double><<<blocks, threads, 0, st>>>(src, m.nsets, entries, p->charted, static_cast<double*>(dst));
+    else
+      convert_level_kernel<float><<<blocks, threads, 0, st>>>(src, m.nsets, entries, p->charted, static_cast<float*>(dst));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace icr

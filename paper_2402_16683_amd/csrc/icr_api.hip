@@ -1,0 +1,431 @@
+// C ABI of the ICR library: configuration checks, the plan (level sizes, offsets,
+// device matrices), and the level-by-level drivers of the forward sweep, its
+// adjoint and the metric. Declarations and contracts are in include/icr.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "icr_internal.h"
+
+namespace icr {
+namespace {
+thread_local std::string g_error;
+}
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+}  // namespace icr
+
+namespace {
+
+using icr::kMaxLevels;
+
+icr_status fail(icr_status s, const std::string& msg) {
+  icr::set_error(msg);
+  return s;
+}
+
+#define ICR_HIP_TRY(expr)                                                                     \
+  do {                                                                                        \
+    const hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(ICR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int elem_bytes_of(int precision) {
+  return precision == ICR_F64 ? 8 : precision == ICR_F32 ? 4 : 2;
+}
+int acc_bytes_of(int precision) { return precision == ICR_F64 ? 8 : 4; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+icr_status check_config(const icr_config* c) {
+  if (!c) return fail(ICR_ERR_INVALID_ARG, "cfg is NULL");
+  if (c->ndim < 1 || c->ndim > 3) return fail(ICR_ERR_INVALID_ARG, "ndim must be 1, 2 or 3");
+  if (c->depth < 0 || c->depth > ICR_MAX_DEPTH)
+    return fail(ICR_ERR_INVALID_ARG, "depth must be in [0, " + std::to_string(ICR_MAX_DEPTH) + "]");
+  if (c->kernel < ICR_MATERN12 || c->kernel > ICR_SQEXP) return fail(ICR_ERR_INVALID_ARG, "unknown kernel");
+  if (c->chart != ICR_CHART_REGULAR && c->chart != ICR_CHART_LOGRADIAL_2D)
+    return fail(ICR_ERR_INVALID_ARG, "unknown chart");
+  if (c->chart == ICR_CHART_LOGRADIAL_2D) {
+    if (c->ndim != 2) return fail(ICR_ERR_INVALID_ARG, "the log-radial chart needs ndim == 2");
+    if (!finite_pos(c->chart_params[0]) || !std::isfinite(c->chart_params[1]) ||
+        !std::isfinite(c->chart_params[2]))
+      return fail(ICR_ERR_INVALID_ARG, "log-radial chart needs r0 > 0 and finite growth/angle");
+  }
+  if (c->precision < ICR_F64 || c->precision > ICR_BF16_F32ACC)
+    return fail(ICR_ERR_INVALID_ARG, "unknown precision");
+  if (c->flags & ~ICR_FLAG_NO_CLAMP) return fail(ICR_ERR_INVALID_ARG, "unknown flag bits");
+  if (c->reserved != 0) return fail(ICR_ERR_INVALID_ARG, "reserved must be 0");
+  if (!finite_pos(c->scale) || !finite_pos(c->length))
+    return fail(ICR_ERR_INVALID_ARG, "scale and length must be finite and > 0");
+  int64_t n0 = 1;
+  for (int a = 0; a < c->ndim; ++a) {
+    if (!finite_pos(c->distances0[a])) return fail(ICR_ERR_INVALID_ARG, "distances0 must be finite and > 0");
+    if (c->shape0[a] < 1 || c->shape0[a] > 65536) return fail(ICR_ERR_INVALID_ARG, "shape0 out of range");
+    n0 *= c->shape0[a];
+  }
+  if (n0 > 4096)
+    return fail(ICR_ERR_UNSUPPORTED, "level 0 has more than 4096 pixels (dense Cholesky limit)");
+  // every refined level needs an interior; sizes must stay addressable
+  for (int a = 0; a < c->ndim; ++a) {
+    int64_t n = c->shape0[a];
+    for (int l = 0; l < c->depth; ++l) {
+      if (n < 3) return fail(ICR_ERR_INVALID_ARG, "a refined level has fewer than 3 pixels along an axis");
+      n = 2 * (n - 2);
+      if (n > (int64_t(1) << 24)) return fail(ICR_ERR_INVALID_ARG, "level size exceeds 2^24 pixels per axis");
+    }
+  }
+  return ICR_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+bool aligned(const void* p, int el) { return (reinterpret_cast<uintptr_t>(p) % el) == 0; }
+
+void* at(const void* base, int64_t elems, int el) {
+  return static_cast<char*>(const_cast<void*>(base)) + elems * el;
+}
+
+// Adjoint sweep from the fine cotangent y (level `depth`) down to level 0.
+icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t y_bs, void* xi_bar,
+                       void* ws, int64_t ws_bs, const void* add, hipStream_t st) {
+  const int el = p->elem_bytes;
+  const int L = p->depth;
+  if (L == 0) {
+    icr::Level0Args a{y, y_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
+    return ICR_OK;
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    icr::RefineAdjArgs a;
+    a.y = l == L - 1 ? y : at(ws, p->offsets[l + 1], el);
+    a.y_bs = l == L - 1 ? y_bs : ws_bs;
+    a.xi_bar = at(xi_bar, p->offsets[l + 1], el);
+    a.xi_bar_bs = p->n_xi;
+    a.s_bar = at(ws, p->offsets[l], el);
+    a.s_bar_bs = ws_bs;
+    a.add = add ? at(add, p->offsets[l + 1], el) : nullptr;
+    a.add_bs = add ? p->n_xi : 0;
+    a.batch = batch;
+    ICR_HIP_TRY(icr::launch_refine_adj(p, l, a, st));
+  }
+  icr::Level0Args a{ws, ws_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
+  ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
+  return ICR_OK;
+}
+
+// Forward sweep; the last level goes to `out` (stride out_bs), optionally times w.
+icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* out, int64_t out_bs,
+                       void* ws, int64_t ws_bs, const void* w, int64_t w_bs, hipStream_t st) {
+  const int el = p->elem_bytes;
+  const int L = p->depth;
+  if (L == 0) {
+    icr::Level0Args a{xi, p->n_xi, out, out_bs, w, w_bs, nullptr, 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_fwd(p, a, st));
+    return ICR_OK;
+  }
+  icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch};
+  ICR_HIP_TRY(icr::launch_level0_fwd(p, a0, st));
+  for (int l = 0; l < L; ++l) {
+    icr::RefineFwdArgs a;
+    a.s_in = at(ws, p->offsets[l], el);
+    a.s_in_bs = ws_bs;
+    a.xi = at(xi, p->offsets[l + 1], el);
+    a.xi_bs = p->n_xi;
+    a.s_out = l == L - 1 ? out : at(ws, p->offsets[l + 1], el);
+    a.s_out_bs = l == L - 1 ? out_bs : ws_bs;
+    a.w = l == L - 1 ? w : nullptr;
+    a.w_bs = w_bs;
+    a.batch = batch;
+    ICR_HIP_TRY(icr::launch_refine_fwd(p, l, a, st));
+  }
+  return ICR_OK;
+}
+
+icr_status check_call(const icr_plan* p, int64_t batch) {
+  if (!p) return fail(ICR_ERR_INVALID_ARG, "plan is NULL");
+  if (batch < 0) return fail(ICR_ERR_INVALID_ARG, "batch must be >= 0");
+  return ICR_OK;
+}
+
+}  // namespace
+
+namespace icr {
+hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
+  return launch_refine_fwd_generic(p, level, a, st);
+}
+hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  return launch_refine_adj_generic(p, level, a, st);
+}
+}  // namespace icr
+
+extern "C" {
+
+int32_t icr_version(void) { return 100; }
+
+const char* icr_last_error(void) { return icr::g_error.c_str(); }
+
+icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan** out_plan) {
+  icr::clear_error();
+  if (!out_plan) return fail(ICR_ERR_INVALID_ARG, "out_plan is NULL");
+  *out_plan = nullptr;
+  const icr_status cs = check_config(cfg);
+  if (cs != ICR_OK) return cs;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+  icr_plan* p = new (std::nothrow) icr_plan;
+  if (!p) return fail(ICR_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
+  p->cfg = *cfg;
+  p->ndim = cfg->ndim;
+  p->depth = cfg->depth;
+  p->precision = cfg->precision;
+  p->charted = cfg->chart != ICR_CHART_REGULAR;
+  p->elem_bytes = elem_bytes_of(cfg->precision);
+  const int d = p->ndim;
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int a = 0; a < 3; ++a) p->shapes[l][a] = 1;
+  for (int a = 0; a < d; ++a) {
+    int n = cfg->shape0[a];
+    for (int l = 0; l <= p->depth; ++l) {
+      p->shapes[l][3 - d + a] = n;
+      n = 2 * (n - 2);
+    }
+  }
+  int64_t off = 0;
+  for (int l = 0; l <= p->depth; ++l) {
+    p->offsets[l] = off;
+    off += int64_t(p->shapes[l][0]) * p->shapes[l][1] * p->shapes[l][2];
+  }
+  p->offsets[p->depth + 1] = off;
+  p->n_xi = off;
+  p->n_out = off - p->offsets[p->depth];
+  p->n0 = p->offsets[1] - p->offsets[0];
+  for (int a = 0; a < 3; ++a) {
+    double delta = a < d ? cfg->distances0[a] : 0.0, origin = 0.0;
+    for (int l = 0; l <= p->depth; ++l) {
+      p->spacings[l][a] = delta;
+      p->origins[l][a] = origin;
+      origin += 0.75 * delta;
+      delta *= 0.5;
+    }
+  }
+  for (int l = 0; l < kMaxLevels; ++l) p->clamped[l] = 0;
+
+  // one pool: level-0 factors, per-level matrices, status words
+  const int ab = acc_bytes_of(p->precision);
+  const int nc = 1 << d, nw = icr::pow3(d);
+  size_t bytes = 0;
+  const size_t off_l64 = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * 8);
+  const size_t off_lc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
+  const size_t off_uc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
+  size_t off_lev[ICR_MAX_DEPTH][4];
+  for (int l = 0; l < p->depth; ++l) {
+    int64_t nsets = 1;
+    if (p->charted)
+      for (int a = 0; a < d; ++a) nsets *= p->shapes[l][3 - d + a] - 2;
+    p->lev[l].nsets = nsets;
+    off_lev[l][0] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * 8);
+    off_lev[l][1] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * 8);
+    off_lev[l][2] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * ab);
+    off_lev[l][3] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * ab);
+  }
+  const size_t off_status = bytes; bytes = align_up(bytes + sizeof(int32_t) * (kMaxLevels + 1));
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->pool, bytes);
+  if (e != hipSuccess) {
+    delete p;
+    if (e == hipErrorOutOfMemory) return fail(ICR_ERR_OUT_OF_MEMORY, "device allocation of the plan failed");
+    return fail(ICR_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  p->pool_bytes = static_cast<int64_t>(bytes);
+  char* base = static_cast<char*>(p->pool);
+  p->l00_64 = reinterpret_cast<double*>(base + off_l64);
+  p->l00_c = base + off_lc;
+  p->u00_c = base + off_uc;
+  for (int l = 0; l < p->depth; ++l) {
+    p->lev[l].r64 = reinterpret_cast<double*>(base + off_lev[l][0]);
+    p->lev[l].s64 = reinterpret_cast<double*>(base + off_lev[l][1]);
+    p->lev[l].r_c = base + off_lev[l][2];
+    p->lev[l].s_c = base + off_lev[l][3];
+  }
+  int32_t* status = reinterpret_cast<int32_t*>(base + off_status);
+  int32_t* counts = status + 1;
+
+  auto bail = [&](icr_status s, const std::string& msg) {
+    (void)hipFree(p->pool);
+    delete p;
+    return fail(s, msg);
+  };
+#define BUILD_TRY(expr)                                                                   \
+  do {                                                                                    \
+    const hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return bail(ICR_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+  BUILD_TRY(hipMemsetAsync(status, 0, sizeof(int32_t) * (kMaxLevels + 1), st));
+  BUILD_TRY(icr::launch_build_k00(p, p->l00_64, st));
+  BUILD_TRY(icr::launch_cholesky_level0(p, p->l00_64, counts + 0, status, st));
+  BUILD_TRY(icr::launch_level0_convert(p, st));
+  for (int l = 0; l < p->depth; ++l) {
+    BUILD_TRY(icr::launch_build_level(p, l, counts + 1 + l, status, st));
+    BUILD_TRY(icr::launch_level_convert(p, l, st));
+  }
+  int32_t host_status[kMaxLevels + 1];
+  BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
+  BUILD_TRY(hipStreamSynchronize(st));
+#undef BUILD_TRY
+  for (int l = 0; l <= p->depth; ++l) p->clamped[l] = host_status[1 + l];
+  if (host_status[0] & 2)
+    return bail(ICR_ERR_NOT_PD, "K_00 is not positive definite (a pivot needed clamping; clamping disabled)");
+  if (host_status[0] & 1)
+    return bail(ICR_ERR_NOT_PD,
+                "a window covariance K_cc is not positive definite, or a pivot of D needed "
+                "clamping with clamping disabled");
+  *out_plan = p;
+  return ICR_OK;
+}
+
+icr_status icr_plan_get_info(const icr_plan* p, icr_plan_info* info) {
+  icr::clear_error();
+  if (!p || !info) return fail(ICR_ERR_INVALID_ARG, "plan or info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  const int d = p->ndim;
+  info->ndim = d;
+  info->depth = p->depth;
+  info->precision = p->precision;
+  info->chart = p->cfg.chart;
+  info->elem_bytes = p->elem_bytes;
+  for (int l = 0; l <= p->depth; ++l) {
+    info->clamped_pivots[l] = p->clamped[l];
+    for (int a = 0; a < 3; ++a) info->level_shapes[l][a] = a < d ? p->shapes[l][3 - d + a] : 1;
+    info->level_offsets[l] = p->offsets[l];
+  }
+  info->level_offsets[p->depth + 1] = p->n_xi;
+  info->n_xi = p->n_xi;
+  info->n_out = p->n_out;
+  info->workspace_elems = p->n_xi - p->n_out;
+  info->metric_workspace_elems = p->n_xi;
+  info->device_bytes = p->pool_bytes;
+  return ICR_OK;
+}
+
+icr_status icr_plan_copy_level0(const icr_plan* p, double* l00) {
+  icr::clear_error();
+  if (!p || !l00) return fail(ICR_ERR_INVALID_ARG, "plan or l00 is NULL");
+  ICR_HIP_TRY(hipMemcpy(l00, p->l00_64, size_t(p->n0) * p->n0 * 8, hipMemcpyDeviceToHost));
+  return ICR_OK;
+}
+
+icr_status icr_plan_copy_refinement(const icr_plan* p, int32_t level, double* r, double* sqrtd) {
+  icr::clear_error();
+  if (!p) return fail(ICR_ERR_INVALID_ARG, "plan is NULL");
+  if (level < 0 || level >= p->depth) return fail(ICR_ERR_INVALID_ARG, "level out of range");
+  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
+  const icr::LevelMats& m = p->lev[level];
+  if (r) ICR_HIP_TRY(hipMemcpy(r, m.r64, size_t(m.nsets) * nc * nw * 8, hipMemcpyDeviceToHost));
+  if (sqrtd) ICR_HIP_TRY(hipMemcpy(sqrtd, m.s64, size_t(m.nsets) * nc * nc * 8, hipMemcpyDeviceToHost));
+  return ICR_OK;
+}
+
+icr_status icr_plan_set_level0(icr_plan* p, const double* l00, void* hip_stream) {
+  icr::clear_error();
+  if (!p || !l00) return fail(ICR_ERR_INVALID_ARG, "plan or l00 is NULL");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  ICR_HIP_TRY(hipMemcpyAsync(p->l00_64, l00, size_t(p->n0) * p->n0 * 8, hipMemcpyHostToDevice, st));
+  ICR_HIP_TRY(icr::launch_level0_convert(p, st));
+  ICR_HIP_TRY(hipStreamSynchronize(st));
+  return ICR_OK;
+}
+
+icr_status icr_plan_set_refinement(icr_plan* p, int32_t level, const double* r, const double* sqrtd,
+                                   void* hip_stream) {
+  icr::clear_error();
+  if (!p || !r || !sqrtd) return fail(ICR_ERR_INVALID_ARG, "plan, r or sqrtd is NULL");
+  if (level < 0 || level >= p->depth) return fail(ICR_ERR_INVALID_ARG, "level out of range");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
+  const icr::LevelMats& m = p->lev[level];
+  ICR_HIP_TRY(hipMemcpyAsync(m.r64, r, size_t(m.nsets) * nc * nw * 8, hipMemcpyHostToDevice, st));
+  ICR_HIP_TRY(hipMemcpyAsync(m.s64, sqrtd, size_t(m.nsets) * nc * nc * 8, hipMemcpyHostToDevice, st));
+  ICR_HIP_TRY(icr::launch_level_convert(p, level, st));
+  ICR_HIP_TRY(hipStreamSynchronize(st));
+  return ICR_OK;
+}
+
+icr_status icr_forward(const icr_plan* p, int64_t batch, const void* xi, void* s, void* workspace,
+                       void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  const int el = p->elem_bytes;
+  if (!xi || !s || (p->depth > 0 && !workspace)) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned(xi, el) || !aligned(s, el) || (workspace && !aligned(workspace, el)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t nx = size_t(batch) * p->n_xi * el, ns = size_t(batch) * p->n_out * el;
+  const size_t nw = p->depth > 0 ? size_t(batch) * (p->n_xi - p->n_out) * el : 0;
+  if (overlaps(xi, nx, s, ns) || overlaps(xi, nx, workspace, nw) || overlaps(s, ns, workspace, nw))
+    return fail(ICR_ERR_INVALID_ARG, "xi, s and workspace overlap");
+  return run_forward(p, batch, xi, s, p->n_out, workspace, p->n_xi - p->n_out, nullptr, 0,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
+icr_status icr_adjoint(const icr_plan* p, int64_t batch, const void* s_bar, void* xi_bar,
+                       void* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  const int el = p->elem_bytes;
+  if (!s_bar || !xi_bar || (p->depth > 0 && !workspace)) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned(s_bar, el) || !aligned(xi_bar, el) || (workspace && !aligned(workspace, el)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t nx = size_t(batch) * p->n_xi * el, ns = size_t(batch) * p->n_out * el;
+  const size_t nw = p->depth > 0 ? size_t(batch) * (p->n_xi - p->n_out) * el : 0;
+  if (overlaps(xi_bar, nx, s_bar, ns) || overlaps(xi_bar, nx, workspace, nw) ||
+      overlaps(s_bar, ns, workspace, nw))
+    return fail(ICR_ERR_INVALID_ARG, "s_bar, xi_bar and workspace overlap");
+  return run_adjoint(p, batch, s_bar, p->n_out, xi_bar, workspace, p->n_xi - p->n_out, nullptr,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
+icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                            const void* v, void* out, void* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  const int el = p->elem_bytes;
+  const int ab = acc_bytes_of(p->precision);
+  if (!w || !v || !out || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(v, el) || !aligned(out, el) || !aligned(workspace, el) || !aligned(w, ab))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t nx = size_t(batch) * p->n_xi * el;
+  if (overlaps(v, nx, out, nx) || overlaps(v, nx, workspace, nx) || overlaps(out, nx, workspace, nx))
+    return fail(ICR_ERR_INVALID_ARG, "v, out and workspace overlap");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t ws_bs = p->n_xi;
+  // forward into the workspace; the final level (times w) lands at offsets[depth]
+  icr_status r = run_forward(p, batch, v, at(workspace, p->offsets[p->depth], el), ws_bs, workspace,
+                             ws_bs, w, w_batch_stride, st);
+  if (r != ICR_OK) return r;
+  return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
+                     v, st);
+}
+
+icr_status icr_plan_destroy(icr_plan* p) {
+  icr::clear_error();
+  if (!p) return ICR_OK;
+  const hipError_t e = p->pool ? hipFree(p->pool) : hipSuccess;
+  delete p;
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+  return ICR_OK;
+}
+
+}  // extern "C"

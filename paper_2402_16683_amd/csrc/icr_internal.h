@@ -1,0 +1,131 @@
+// Internal declarations shared by the ICR library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "icr.h"
+
+namespace icr {
+
+constexpr int kMaxLevels = ICR_MAX_DEPTH + 1;
+
+constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
+
+// bfloat16 storage: the upper 16 bits of an IEEE float.
+using bf16_t = uint16_t;
+
+// ---------------------------------------------------------------------------
+// Storage <-> arithmetic conversions
+// ---------------------------------------------------------------------------
+template <typename TS> struct Acc;
+template <> struct Acc<double> { using type = double; };
+template <> struct Acc<float> { using type = float; };
+template <> struct Acc<bf16_t> { using type = float; };
+
+__device__ __forceinline__ double load_acc(const double* p) { return *p; }
+__device__ __forceinline__ float load_acc(const float* p) { return *p; }
+__device__ __forceinline__ float load_acc(const bf16_t* p) {
+  return __uint_as_float(static_cast<uint32_t>(*p) << 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+__device__ __forceinline__ void store_acc(double* p, double v) { *p = v; }
+__device__ __forceinline__ void store_acc(float* p, float v) { *p = v; }
+__device__ __forceinline__ bf16_t f32_to_bf16(float v) {
+  // round to nearest even (gfx950 converts in hardware)
+  return __builtin_bit_cast(bf16_t, static_cast<__bf16>(v));
+}
+__device__ __forceinline__ void store_acc(bf16_t* p, float v) { *p = f32_to_bf16(v); }
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct LevelMats {
+  double* r64 = nullptr;  // [nsets][2^d][3^d]
+  double* s64 = nullptr;  // [nsets][2^d][2^d], lower triangular
+  void* r_c = nullptr;    // arithmetic type; stationary: [2^d][3^d]; charted: [2^d*3^d][nsets]
+  void* s_c = nullptr;    // arithmetic type; stationary: [2^d][2^d]; charted: [2^d*2^d][nsets]
+  void* sector_c = nullptr;  // stationary FP32 only: reflection-sector coefficients (see refine_fast)
+  int64_t nsets = 0;
+};
+
+}  // namespace icr
+
+struct icr_plan {
+  icr_config cfg;
+  int ndim = 0;
+  int depth = 0;
+  int precision = 0;
+  int charted = 0;
+  int device = 0;
+  int shapes[icr::kMaxLevels][3];  // level shapes, axes beyond ndim are 1 (stored leading)
+  int64_t offsets[icr::kMaxLevels + 1];
+  int64_t n_xi = 0, n_out = 0, n0 = 0;
+  int elem_bytes = 0;
+  double origins[icr::kMaxLevels][3];
+  double spacings[icr::kMaxLevels][3];
+  double* l00_64 = nullptr;  // [n0][n0] lower Cholesky factor of K_00
+  void* l00_c = nullptr;     // arithmetic type, row-major lower
+  void* u00_c = nullptr;     // arithmetic type, row-major upper (= L00^T)
+  icr::LevelMats lev[ICR_MAX_DEPTH];
+  int32_t clamped[icr::kMaxLevels];
+  void* pool = nullptr;      // the one device allocation the plan owns
+  int64_t pool_bytes = 0;
+};
+
+namespace icr {
+
+// error reporting (thread-local message)
+void set_error(const std::string& msg);
+void clear_error();
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each returns hipSuccess or the launch error)
+// ---------------------------------------------------------------------------
+
+// FP64 build
+hipError_t launch_build_k00(const icr_plan* p, double* a, hipStream_t st);
+hipError_t launch_cholesky_level0(const icr_plan* p, double* a, int32_t* counts, int32_t* status,
+                                  hipStream_t st);
+hipError_t launch_level0_convert(const icr_plan* p, hipStream_t st);
+hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int32_t* status,
+                              hipStream_t st);
+hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st);
+
+// level 0 apply: out = L00 in (forward) / U00 in (+ add) (adjoint); w optional
+struct Level0Args {
+  const void* in; int64_t in_bs;
+  void* out; int64_t out_bs;
+  const void* w; int64_t w_bs;    // forward only: out *= w
+  const void* add; int64_t add_bs;  // adjoint only: out += add
+  int64_t batch;
+};
+hipError_t launch_level0_fwd(const icr_plan* p, const Level0Args& a, hipStream_t st);
+hipError_t launch_level0_adj(const icr_plan* p, const Level0Args& a, hipStream_t st);
+
+// one refinement level
+struct RefineFwdArgs {
+  const void* s_in; int64_t s_in_bs;   // coarse field, level l
+  const void* xi; int64_t xi_bs;       // excitations of level l+1
+  void* s_out; int64_t s_out_bs;       // fine field, level l+1
+  const void* w; int64_t w_bs;         // optional: s_out *= w (arithmetic type)
+  int64_t batch;
+};
+struct RefineAdjArgs {
+  const void* y; int64_t y_bs;          // fine cotangent, level l+1
+  void* xi_bar; int64_t xi_bar_bs;      // excitation cotangent, level l+1
+  void* s_bar; int64_t s_bar_bs;        // coarse cotangent, level l
+  const void* add; int64_t add_bs;      // optional: xi_bar += add (storage type)
+  int64_t batch;
+};
+hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st);
+hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
+hipError_t launch_refine_fwd_generic(const icr_plan* p, int level, const RefineFwdArgs& a,
+                                     hipStream_t st);
+hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
+                                     hipStream_t st);
+
+}  // namespace icr

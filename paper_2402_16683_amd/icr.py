@@ -1,0 +1,318 @@
+"""Python binding of the ICR C ABI (include/icr.h): argument marshalling only.
+
+Every computation runs in libicr.so's HIP kernels. PyTorch supplies device
+memory (tensors) and streams. The functions carry the C names:
+
+    plan = icr_build_matrices(cfg)                 # FP64 build on the device
+    s    = icr_forward(plan, xi)                   # s = L xi
+    xib  = icr_adjoint(plan, s_bar)                # xi_bar = L^T s_bar
+    out  = icr_metric_apply(plan, w, v)            # L^T (w * L v) + v
+    icr_plan_destroy(plan)
+
+Tensors are CUDA (HIP) tensors, contiguous, batch outermost, of the plan's
+storage dtype (float64 / float32 / bfloat16). A missing library raises: there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libicr.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "icr.h")
+
+ICR_MAX_DEPTH = 15
+
+STATUS = {0: "ICR_OK", 1: "ICR_ERR_INVALID_ARG", 2: "ICR_ERR_NOT_PD", 3: "ICR_ERR_HIP",
+          4: "ICR_ERR_OUT_OF_MEMORY", 5: "ICR_ERR_UNSUPPORTED"}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
+KERNELS = {"matern12": 0, "matern32": 1, "matern52": 2, "sqexp": 3}
+CHARTS = {"regular": 0, "logradial2d": 1}
+FLAG_NO_CLAMP = 1
+
+
+class IcrConfig(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("shape0", ctypes.c_int32 * 3), ("depth", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("chart", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("distances0", ctypes.c_double * 3), ("scale", ctypes.c_double),
+                ("length", ctypes.c_double), ("chart_params", ctypes.c_double * 4)]
+
+
+class IcrPlanInfo(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("depth", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("chart", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
+                ("clamped_pivots", ctypes.c_int32 * (ICR_MAX_DEPTH + 1)),
+                ("level_shapes", (ctypes.c_int32 * 3) * (ICR_MAX_DEPTH + 1)),
+                ("level_offsets", ctypes.c_int64 * (ICR_MAX_DEPTH + 2)),
+                ("n_xi", ctypes.c_int64), ("n_out", ctypes.c_int64),
+                ("workspace_elems", ctypes.c_int64), ("metric_workspace_elems", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class ICRError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libicr.so (built in-tree by build()); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2402_16683_amd.build`")
+    # A process must hold one HIP runtime. PyTorch ships its own libamdhip64 with
+    # the same SONAME as ROCm's; loading torch first makes libicr.so bind to it
+    # instead of pulling in a second runtime that would not see torch's device.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    sigs = {
+        "icr_build_matrices": [ctypes.POINTER(IcrConfig), vp, ctypes.POINTER(vp)],
+        "icr_plan_get_info": [vp, ctypes.POINTER(IcrPlanInfo)],
+        "icr_plan_copy_level0": [vp, vp],
+        "icr_plan_copy_refinement": [vp, i32, vp, vp],
+        "icr_plan_set_level0": [vp, vp, vp],
+        "icr_plan_set_refinement": [vp, i32, vp, vp, vp],
+        "icr_forward": [vp, i64, vp, vp, vp, vp],
+        "icr_adjoint": [vp, i64, vp, vp, vp, vp],
+        "icr_metric_apply": [vp, i64, vp, i64, vp, vp, vp, vp],
+        "icr_plan_destroy": [vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.icr_last_error.argtypes = []
+    lib.icr_last_error.restype = ctypes.c_char_p
+    lib.icr_version.argtypes = []
+    lib.icr_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def declared_functions(header: str = HEADER) -> list[str]:
+    """Names of the functions include/icr.h declares."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(icr_[a-z0-9_]+)\s*\(", text)))
+
+
+def icr_last_error() -> str:
+    return load_library().icr_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise ICRError(status, icr_last_error())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_config(ndim, shape0, depth, distances0, kernel="matern32", scale=1.0, length=0.1,
+                chart="regular", chart_params=(0.1, math.log(10.0), 0.5 * math.pi),
+                precision="f32", clamp=True) -> IcrConfig:
+    c = IcrConfig()
+    c.ndim = ndim
+    for a in range(3):
+        c.shape0[a] = int(shape0[a]) if a < ndim else 1
+        c.distances0[a] = float(distances0[a]) if a < ndim else 1.0
+    c.depth = depth
+    c.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    c.chart = CHARTS[chart] if isinstance(chart, str) else int(chart)
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.flags = 0 if clamp else FLAG_NO_CLAMP
+    c.reserved = 0
+    c.scale = scale
+    c.length = length
+    for k in range(4):
+        c.chart_params[k] = float(chart_params[k]) if k < len(chart_params) else 0.0
+    return c
+
+
+class Plan:
+    """Owns an icr_plan*; freed by icr_plan_destroy (or when garbage collected)."""
+
+    def __init__(self, handle: ctypes.c_void_p, cfg: IcrConfig):
+        self.handle = handle
+        self.cfg = cfg
+        self.info = icr_plan_get_info(self)
+
+    @property
+    def dtype(self):
+        import torch
+        return {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[self.cfg.precision]
+
+    @property
+    def acc_dtype(self):
+        import torch
+        return torch.float64 if self.cfg.precision == 0 else torch.float32
+
+    def __del__(self):
+        try:
+            if self.handle:
+                icr_plan_destroy(self)
+        except Exception:
+            pass
+
+
+def icr_build_matrices(cfg: IcrConfig, stream=None) -> Plan:
+    lib = load_library()
+    out = ctypes.c_void_p()
+    _check(lib.icr_build_matrices(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out)))
+    return Plan(out, cfg)
+
+
+def icr_plan_get_info(plan: Plan) -> dict:
+    info = IcrPlanInfo()
+    _check(load_library().icr_plan_get_info(plan.handle, ctypes.byref(info)))
+    depth = info.depth
+    return dict(
+        ndim=info.ndim, depth=depth, precision=info.precision, chart=info.chart,
+        elem_bytes=info.elem_bytes,
+        clamped_pivots=[info.clamped_pivots[l] for l in range(depth + 1)],
+        level_shapes=[tuple(info.level_shapes[l][a] for a in range(info.ndim)) for l in range(depth + 1)],
+        level_offsets=[info.level_offsets[l] for l in range(depth + 2)],
+        n_xi=info.n_xi, n_out=info.n_out, workspace_elems=info.workspace_elems,
+        metric_workspace_elems=info.metric_workspace_elems, device_bytes=info.device_bytes)
+
+
+def icr_plan_copy_level0(plan: Plan) -> np.ndarray:
+    n0 = plan.info["level_offsets"][1]
+    out = np.empty((n0, n0), dtype=np.float64)
+    _check(load_library().icr_plan_copy_level0(plan.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def icr_plan_copy_refinement(plan: Plan, level: int):
+    d = plan.info["ndim"]
+    nsets = 1
+    if plan.info["chart"] != 0:
+        for n in plan.info["level_shapes"][level]:
+            nsets *= n - 2
+    r = np.empty((nsets, 2 ** d, 3 ** d), dtype=np.float64)
+    s = np.empty((nsets, 2 ** d, 2 ** d), dtype=np.float64)
+    _check(load_library().icr_plan_copy_refinement(plan.handle, level, r.ctypes.data_as(ctypes.c_void_p),
+                                                   s.ctypes.data_as(ctypes.c_void_p)))
+    if plan.info["chart"] == 0:
+        return r[0], s[0]
+    return r, s
+
+
+def icr_plan_set_level0(plan: Plan, l00: np.ndarray, stream=None):
+    n0 = plan.info["level_offsets"][1]
+    a = np.ascontiguousarray(l00, dtype=np.float64)
+    if a.shape != (n0, n0):
+        raise ValueError(f"l00 must be ({n0}, {n0})")
+    _check(load_library().icr_plan_set_level0(plan.handle, a.ctypes.data_as(ctypes.c_void_p),
+                                              _stream_handle(stream)))
+
+
+def icr_plan_set_refinement(plan: Plan, level: int, r: np.ndarray, sqrtd: np.ndarray, stream=None):
+    d = plan.info["ndim"]
+    nsets = 1
+    if plan.info["chart"] != 0:
+        for n in plan.info["level_shapes"][level]:
+            nsets *= n - 2
+    ra = np.ascontiguousarray(np.reshape(r, (nsets, 2 ** d, 3 ** d)), dtype=np.float64)
+    sa = np.ascontiguousarray(np.reshape(sqrtd, (nsets, 2 ** d, 2 ** d)), dtype=np.float64)
+    _check(load_library().icr_plan_set_refinement(plan.handle, level, ra.ctypes.data_as(ctypes.c_void_p),
+                                                  sa.ctypes.data_as(ctypes.c_void_p),
+                                                  _stream_handle(stream)))
+
+
+def _batch_of(t, n):
+    if t.dim() == 1:
+        if t.numel() != n:
+            raise ValueError(f"expected {n} elements, got {t.numel()}")
+        return 1
+    if t.dim() != 2 or t.shape[1] != n:
+        raise ValueError(f"expected shape (batch, {n}), got {tuple(t.shape)}")
+    return t.shape[0]
+
+
+def _check_tensor(t, plan, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != plan.dtype:
+        raise ValueError(f"{name} must be {plan.dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _empty(shape, plan, dtype=None):
+    import torch
+    return torch.empty(shape, dtype=dtype or plan.dtype, device="cuda")
+
+
+def workspace_for(plan: Plan, batch: int, metric: bool = False):
+    n = plan.info["metric_workspace_elems" if metric else "workspace_elems"]
+    return _empty((batch, max(n, 1)), plan)
+
+
+def icr_forward(plan: Plan, xi, s=None, workspace=None, stream=None):
+    _check_tensor(xi, plan, "xi")
+    batch = _batch_of(xi, plan.info["n_xi"])
+    if s is None:
+        s = _empty(xi.shape[:-1] + (plan.info["n_out"],), plan)
+    _check_tensor(s, plan, "s")
+    if workspace is None:
+        workspace = workspace_for(plan, batch)
+    _check(load_library().icr_forward(plan.handle, batch, xi.data_ptr(), s.data_ptr(),
+                                      workspace.data_ptr(), _stream_handle(stream)))
+    return s
+
+
+def icr_adjoint(plan: Plan, s_bar, xi_bar=None, workspace=None, stream=None):
+    _check_tensor(s_bar, plan, "s_bar")
+    batch = _batch_of(s_bar, plan.info["n_out"])
+    if xi_bar is None:
+        xi_bar = _empty(s_bar.shape[:-1] + (plan.info["n_xi"],), plan)
+    _check_tensor(xi_bar, plan, "xi_bar")
+    if workspace is None:
+        workspace = workspace_for(plan, batch)
+    _check(load_library().icr_adjoint(plan.handle, batch, s_bar.data_ptr(), xi_bar.data_ptr(),
+                                      workspace.data_ptr(), _stream_handle(stream)))
+    return xi_bar
+
+
+def icr_metric_apply(plan: Plan, w, v, out=None, workspace=None, stream=None):
+    _check_tensor(v, plan, "v")
+    batch = _batch_of(v, plan.info["n_xi"])
+    if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
+        raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
+    w_stride = 0 if w.dim() == 1 else w.shape[-1]
+    if out is None:
+        out = _empty(v.shape, plan)
+    _check_tensor(out, plan, "out")
+    if workspace is None:
+        workspace = workspace_for(plan, batch, metric=True)
+    _check(load_library().icr_metric_apply(plan.handle, batch, w.data_ptr(), w_stride, v.data_ptr(),
+                                           out.data_ptr(), workspace.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def icr_plan_destroy(plan: Plan):
+    if plan.handle:
+        h, plan.handle = plan.handle, None
+        _check(load_library().icr_plan_destroy(h))
+
+
+def icr_version() -> int:
+    return int(load_library().icr_version())

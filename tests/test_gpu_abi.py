@@ -1,0 +1,104 @@
+"""Device-side behaviour of the C ABI: error paths write nothing, batch 0 is a no-op,
+factorisation failures are reported, plan info matches the level sizes, per-sample
+metric weights and non-default streams."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import icr_oracle as O
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+BASE = C.case(2, (6, 7), 2, (0.1, 0.12), "matern32", 0.3, name="abi_2d")
+
+
+def _plan(c=BASE, precision=None):
+    return C.gpu_plan(c, precision)
+
+
+def test_plan_info_matches_the_level_sizes():
+    plan = _plan()
+    model = C.oracle_model(BASE)
+    info = plan.info
+    assert info["level_shapes"] == model.shapes
+    assert info["level_offsets"][:-1] == model.offsets
+    assert info["n_xi"] == model.n_xi and info["n_out"] == model.out_size
+    assert info["workspace_elems"] == model.n_xi - model.out_size
+    assert info["metric_workspace_elems"] == model.n_xi
+    assert info["elem_bytes"] == 4 and info["device_bytes"] > 0
+
+
+def test_argument_errors_write_nothing():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    lib = B.load_library()
+    plan = _plan()
+    info = plan.info
+    xi = torch.zeros((2, info["n_xi"]), dtype=torch.float32, device="cuda")
+    s = torch.full((2, info["n_out"]), 7.0, dtype=torch.float32, device="cuda")
+    ws = torch.full((2, info["workspace_elems"]), 7.0, dtype=torch.float32, device="cuda")
+    h = plan.handle
+    # misaligned, NULL, overlapping, negative batch
+    assert lib.icr_forward(h, 2, xi.data_ptr() + 2, s.data_ptr(), ws.data_ptr(), None) == 1
+    assert "aligned" in B.icr_last_error()
+    assert lib.icr_forward(h, 2, None, s.data_ptr(), ws.data_ptr(), None) == 1
+    assert lib.icr_forward(h, 2, xi.data_ptr(), xi.data_ptr() + 4, ws.data_ptr(), None) == 1
+    assert "overlap" in B.icr_last_error()
+    assert lib.icr_forward(h, -1, xi.data_ptr(), s.data_ptr(), ws.data_ptr(), None) == 1
+    assert lib.icr_adjoint(h, 2, s.data_ptr(), xi.data_ptr(), None, None) == 1
+    w = torch.ones(info["n_out"], dtype=torch.float32, device="cuda")
+    assert lib.icr_metric_apply(h, 2, w.data_ptr(), 3, xi.data_ptr(), xi.data_ptr(), ws.data_ptr(), None) == 1
+    # batch 0 is a no-op
+    assert lib.icr_forward(h, 0, xi.data_ptr(), s.data_ptr(), ws.data_ptr(), None) == 0
+    torch.cuda.synchronize()
+    assert bool((s == 7.0).all()) and bool((ws == 7.0).all())
+
+
+def test_factorisation_failures_are_reported():
+    from paper_2402_16683_amd import icr as B
+    se = C.case(2, (5, 5), 1, (0.2, 0.2), "sqexp", 8.0, name="se_long")
+    plan = C.gpu_plan(se)                       # clamps in K_00 and in D
+    assert plan.info["clamped_pivots"][0] > 0 and plan.info["clamped_pivots"][1] > 0
+    with pytest.raises(B.ICRError) as e:
+        C.gpu_plan(dict(se, clamp=False))
+    assert e.value.status == 2
+    with pytest.raises(B.ICRError) as e:
+        C.gpu_plan(dict(se, length=50.0))       # K_cc itself singular: never clamped
+    assert e.value.status == 2 and "K_cc" in str(e.value)
+
+
+def test_per_sample_metric_weights_and_streams():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan = _plan()
+    model = C.oracle_model(BASE)
+    info = plan.info
+    v = W.standard_normal(info["n_xi"], seed=3, batch=3)
+    w = np.stack([W.bernoulli_mask(info["n_out"], 0.7, seed=10 + k) * (k + 1) for k in range(3)])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        out = B.icr_metric_apply(plan, torch.from_numpy(w).float().cuda(), C.to_device(v, plan),
+                                 stream=stream)
+    stream.synchronize()
+    ref = np.stack([model.metric(w[k], C.stored_values(v[k], "f32")) for k in range(3)])
+    rms, _ = C.rel_errors(C.to_numpy(out), ref)
+    assert rms <= 1e-5
+
+
+def test_large_batch_is_split_across_launches():
+    """More samples than one launch grid row holds (65535) on a tiny prior."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = C.case(1, (3,), 1, (0.3,), "matern52", 0.5, name="tiny_1d")
+    plan = C.gpu_plan(c)
+    model = C.oracle_model(c)
+    nb = 70000
+    xi = W.standard_normal(plan.info["n_xi"], seed=4, batch=nb)
+    s = B.icr_forward(plan, C.to_device(xi, plan))
+    torch.cuda.synchronize()
+    rms, _ = C.rel_errors(C.to_numpy(s), model.forward(C.stored_values(xi, "f32")))
+    assert rms <= 1e-5

@@ -1,0 +1,109 @@
+"""The device FP64 build checked by what fixes it, not elementwise equality:
+
+  * R K_cc = K_fc to the residual of a backward-stable solve, eps |K_cc| |R|;
+  * sqrtD sqrtD^T = K_ff - R K_cf (with the device's own R) up to the clamp
+    threshold, sqrtD lower with a non-negative diagonal;
+  * the effect of R on typical windows (GP samples c ~ N(0, K_cc)) matches the
+    oracle's R: sqrt(tr(dR K_cc dR^T) / tr(R K_cc R^T)), which stays small even
+    where cond(K_cc) ~ 1e14 makes R itself ill-determined;
+  * L00 L00^T = K_00, and L00 equals the oracle's where K_00 is well conditioned.
+The kernel matrices K_cc, K_fc, K_ff, K_00 come from the oracle's kernel and
+positions.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import icr_oracle as O
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+CASES = [
+    C.from_workload("icr1d_m32_12to260", name="1d_m32_full"),
+    C.from_workload("icr2d_se_16to1540_b16", name="2d_se_full"),
+    C.from_workload("icr3d_m52_10to388", name="3d_m52_full"),
+    C.from_workload("icr2d_chart_24to1284", depth=4, name="2d_chart_24to324"),
+    C.case(1, (7,), 6, (0.1,), "sqexp", 0.4, name="1d_se_deep"),
+    C.case(3, (4, 5, 6), 2, (0.2, 0.15, 0.1), "matern12", 0.3, name="3d_m12_ragged"),
+]
+
+
+def _window_geometry(c, model, level):
+    """Physical window / child positions of every set of a level (oracle geometry)."""
+    d = c["ndim"]
+    spac = O.level_spacings(c["delta0"], c["depth"])[level]
+    org = O.level_origins(c["delta0"], c["depth"])[level]
+    wins = O.window_offsets(d).astype(float)
+    kids = O.child_offsets(d).astype(float)
+    if c["chart"] == "regular":
+        return (wins * spac)[None], ((kids - 0.5) * spac / 2)[None]
+    n_int = tuple(n - 2 for n in model.shapes[level])
+    centre = org + (O.grid_indices(n_int) + 1) * spac
+    wp = O.logradial_chart(centre[:, None, :] + wins[None] * spac, c["chart_params"])
+    kp = O.logradial_chart(centre[:, None, :] + (kids[None] - 0.5) * spac / 2, c["chart_params"])
+    return wp, kp
+
+
+@pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
+def test_refinement_matrices_by_residuals_and_effect(c):
+    from paper_2402_16683_amd import icr as B
+    model = C.oracle_model(c)
+    plan = C.gpu_plan(c)
+    tau = O.pivot_threshold(c["ndim"], c["scale"])
+    for l in range(c["depth"]):
+        r_gpu, s_gpu = B.icr_plan_copy_refinement(plan, l)
+        r_gpu = r_gpu.reshape(-1, 2 ** c["ndim"], 3 ** c["ndim"])
+        s_gpu = s_gpu.reshape(-1, 2 ** c["ndim"], 2 ** c["ndim"])
+        wp, kp = _window_geometry(c, model, l)
+        k = lambda a, b: O.kernel_values(c["kernel"], O.pairwise_distance(a, b), c["scale"], c["length"])
+        kcc, kfc, kff = k(wp, wp), k(kp, wp), k(kp, kp)
+        # backward-stable solve: residual ~ eps |K_cc| |R|
+        res = np.abs(r_gpu @ kcc - kfc).max(axis=(-1, -2))
+        bound = 1e3 * EPS * np.abs(kcc).max(axis=(-1, -2)) * np.abs(r_gpu).sum(axis=-1).max(axis=-1)
+        assert np.all(res <= bound), f"level {l}: R residual {res.max():.3g} > {bound.min():.3g}"
+        d_gpu = kff - r_gpu @ np.swapaxes(kfc, -1, -2)
+        d_err = np.abs(s_gpu @ np.swapaxes(s_gpu, -1, -2) - d_gpu).max()
+        assert d_err <= 10 * tau + 100 * EPS * c["scale"] ** 2, f"level {l}: sqrtD residual {d_err:.3g}"
+        assert np.allclose(np.triu(s_gpu, 1), 0.0) and np.all(np.diagonal(s_gpu, axis1=-2, axis2=-1) >= 0)
+        r_ora = np.reshape(model.r_mats[l], r_gpu.shape)
+        dr = r_gpu - r_ora
+        num = np.einsum("sbw,swv,sbv->s", dr, kcc, dr)
+        den = np.einsum("sbw,swv,sbv->s", r_ora, kcc, r_ora)
+        eff = np.sqrt(np.max(num / den))
+        assert eff <= 1e-9, f"level {l}: effect of R differs by {eff:.3g}"
+        s_ora = np.reshape(model.sqrt_ds[l], s_gpu.shape)
+        cov_gpu = s_gpu @ np.swapaxes(s_gpu, -1, -2)
+        cov_ora = s_ora @ np.swapaxes(s_ora, -1, -2)
+        assert np.abs(cov_gpu - cov_ora).max() <= 10 * tau + 1e3 * EPS * c["scale"] ** 2
+
+
+@pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
+def test_level0_factor(c):
+    from paper_2402_16683_amd import icr as B
+    model = C.oracle_model(c)
+    plan = C.gpu_plan(c)
+    l00 = B.icr_plan_copy_level0(plan)
+    assert np.allclose(np.triu(l00, 1), 0.0)
+    pos = O.grid_indices(c["shape0"]) * np.asarray(c["delta0"])
+    if c["chart"] != "regular":
+        pos = O.logradial_chart(pos, c["chart_params"])
+    k00 = O.kernel_values(c["kernel"], O.pairwise_distance(pos, pos), c["scale"], c["length"])
+    n = k00.shape[0]
+    assert np.abs(l00 @ l00.T - k00).max() <= 1e3 * n * EPS * c["scale"] ** 2
+    if np.linalg.cond(k00) < 1e6:
+        assert np.abs(l00 - model.l00).max() <= 1e3 * n * EPS * np.linalg.cond(k00)
+    assert plan.info["clamped_pivots"][0] == model.clamped[0]
+
+
+def test_clamp_counts_on_the_squared_exponential_workload():
+    """The 2-D squared-exponential workload's last level is numerically indefinite;
+    both builds clamp there and nowhere above it."""
+    c = C.from_workload("icr2d_se_16to1540_b16")
+    model = C.oracle_model(c)
+    plan = C.gpu_plan(c)
+    got = plan.info["clamped_pivots"]
+    assert got[:-1] == model.clamped[:-1] == [0] * c["depth"]
+    assert got[-1] > 0 and model.clamped[-1] > 0
