@@ -1,0 +1,229 @@
+"""Benchmark of the ICR hot path on one MI355X: forward + adjoint throughput.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision f32|bf16]
+
+One step is icr_forward followed by icr_adjoint over one batch of the workload
+(every level, level 0 included) with inputs resident in HBM. Buffers rotate over
+two sets (> 2 GB for the 3-D workload) so timed passes stream from HBM rather
+than the 256 MB Infinity Cache. Prints one JSON line:
+
+  value        fine pixels per second, batch * n_L^d / (time of one step)
+  roofline     the dominant kernel (the last level's forward or adjoint) timed alone
+               with HIP events in the same launch configuration: algorithmic bytes
+               per launch / average duration, against the 8 TB/s HBM peak
+  cpu_baseline the FP64 oracle on the host, one sample of the same workload,
+               forward + adjoint, one thread
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="icr3d_m52_10to388")
+    ap.add_argument("--precision", default=None, help="f32 or bf16 (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the sources of the sweep kernels, to tie counter files to a build."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_16683_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag: str, digest: str):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if recorded for this build."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel_tag)
+    if not rec or rec.get("source_digest") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl: dict, quiet: bool):
+    """The FP64 oracle, one sample of the workload, forward + adjoint, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import icr_oracle as O
+    model = O.build(O.ICRConfig(ndim=wl["ndim"], shape0=wl["shape0"], depth=wl["depth"],
+                                delta0=wl["delta0"], kernel=wl["kernel"], scale=wl["scale"],
+                                length=wl["length"], chart=wl["chart"],
+                                chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966))))
+    xi = W.standard_normal(model.n_xi, seed=0)
+    y = W.standard_normal(model.out_size, seed=1)
+    log(f"cpu baseline: oracle forward+adjoint on {model.shapes[-1]} ...", quiet)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        model.forward(xi)
+        model.adjoint(y)
+        dt = time.perf_counter() - t0
+    return {"value": model.out_size / dt, "unit": "fine px/s", "cores": 1, "kind": "oracle",
+            "sample": f"one sample of the full workload ({'x'.join(map(str, model.shapes[-1]))} final "
+                      f"pixels), forward + adjoint, numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2402_16683_amd import icr as B
+
+    torch.cuda.set_device(0)
+    wl = dict(W.WORKLOADS[args.workload])
+    prec = args.precision or wl["precision"]
+    batch = wl["batch"]
+    cfg = B.make_config(wl["ndim"], wl["shape0"], wl["depth"], wl["delta0"], kernel=wl["kernel"],
+                        scale=wl["scale"], length=wl["length"], chart=wl["chart"],
+                        chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966)),
+                        precision=prec)
+    t0 = time.perf_counter()
+    plan = B.icr_build_matrices(cfg)
+    build_s = time.perf_counter() - t0
+    info = plan.info
+    L = info["depth"]
+    el = info["elem_bytes"]
+    n_xi, n_out = info["n_xi"], info["n_out"]
+    offs = info["level_offsets"]
+    n_prev = offs[L] - offs[L - 1]
+    log(f"workload {args.workload} {prec}: levels {info['level_shapes']}, batch {batch}, "
+        f"build {build_s * 1e3:.1f} ms", args.quiet)
+
+    # two rotating sets of every buffer, inputs drawn once on the host
+    sets = []
+    xi_host = torch.from_numpy(W.standard_normal_f32(n_xi, seed=0, batch=batch))
+    y_host = torch.from_numpy(W.standard_normal_f32(n_out, seed=1, batch=batch))
+    for _ in range(2):
+        sets.append(dict(
+            xi=xi_host.to("cuda").to(plan.dtype), y=y_host.to("cuda").to(plan.dtype),
+            s=torch.empty((batch, n_out), dtype=plan.dtype, device="cuda"),
+            xib=torch.empty((batch, n_xi), dtype=plan.dtype, device="cuda"),
+            wsf=torch.empty((batch, info["workspace_elems"]), dtype=plan.dtype, device="cuda"),
+            wsa=torch.empty((batch, info["workspace_elems"]), dtype=plan.dtype, device="cuda")))
+    torch.cuda.synchronize()
+
+    def step(k):
+        b = sets[k % 2]
+        B.icr_forward(plan, b["xi"], b["s"], b["wsf"])
+        B.icr_adjoint(plan, b["y"], b["xib"], b["wsa"])
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(args.steps):
+        step(k)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    ms_per_step = wall * 1e3 / args.steps
+    q = np.quantile(per, [0.16, 0.5, 0.84])
+
+    # dominant kernels: the last level's forward and adjoint, timed launch by launch
+    def time_launches(fn, n):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for k in range(n):
+            evs[k][0].record()
+            fn(k)
+            evs[k][1].record()
+        torch.cuda.synchronize()
+        return statistics.mean(a.elapsed_time(b) for a, b in evs)
+
+    def fwd_last(k):
+        b = sets[k % 2]
+        B.icr_forward_level(plan, L - 1, b["wsf"][:, offs[L - 1]:offs[L]], b["xi"][:, offs[L]:], b["s"])
+
+    def adj_last(k):
+        b = sets[k % 2]
+        B.icr_adjoint_level(plan, L - 1, b["y"], b["xib"][:, offs[L]:], b["wsa"][:, offs[L - 1]:offs[L]])
+
+    n_launch = max(args.steps, 10)
+    for k in range(4):
+        fwd_last(k)
+        adj_last(k)
+    fwd_ms = time_launches(fwd_last, n_launch)
+    adj_ms = time_launches(adj_last, n_launch)
+    launch_bytes = batch * (2 * n_out + n_prev) * el   # fine read + fine write + coarse
+    dom, dom_ms = ("refine_adj_last", adj_ms) if adj_ms >= fwd_ms else ("refine_fwd_last", fwd_ms)
+    achieved = launch_bytes / (dom_ms * 1e-3) / 1e9
+    digest = kernel_source_digest()
+    tag = f"{dom}:{args.workload}:{prec}"
+
+    step_bytes = 2 * batch * (n_xi + n_out) * el
+    value = batch * n_out / (ms_per_step * 1e-3)
+    out = {
+        "metric": "ICR fine-pixels/s fwd+adj",
+        "value": value,
+        "unit": "fine px/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16-storage/f32"}.get(prec, prec),
+        "data": "synthetic: seeded N(0,1) excitations and cotangents",
+        "config": {"workload": args.workload, "ndim": wl["ndim"], "shape0": list(wl["shape0"]),
+                   "depth": L, "final_shape": list(info["level_shapes"][-1]), "kernel": wl["kernel"],
+                   "length": wl["length"], "batch": batch, "precision": prec},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(tag, digest),
+                     "kernel": dom, "launch_ms": dom_ms, "alg_bytes_per_launch": launch_bytes,
+                     "fwd_last_ms": fwd_ms, "adj_last_ms": adj_ms},
+        "step": {"alg_bytes": step_bytes,
+                 "hbm_frac": step_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                 "ms_p16_p50_p84": [float(v) for v in q], "build_ms": build_s * 1e3},
+        "source_digest": digest,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.quiet)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

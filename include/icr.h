@@ -191,6 +191,26 @@ icr_status icr_metric_apply(const icr_plan* plan, int64_t batch, const void* w,
                             int64_t w_batch_stride, const void* v, void* out,
                             void* workspace, void* hip_stream);
 
+/*
+ * One level of the sweep, for callers that pipeline or shard levels themselves
+ * (icr_forward and icr_adjoint are these calls in sequence). Strides are elements
+ * between consecutive samples and must be >= the level's size.
+ *   level >= 0: refinement level -> level+1.
+ *     forward:  s_fine = R s_coarse[window] + sqrtD xi_fine;
+ *     adjoint:  xi_bar_fine = sqrtD^T y_fine, s_bar_coarse = gathered R^T y_fine.
+ *   level == -1: level 0. forward: s_fine = L00 xi_fine (s_coarse unused, may be
+ *     NULL); adjoint: xi_bar_fine = L00^T y_fine (s_bar_coarse unused).
+ * Same conventions as icr_forward (asynchronous, no allocation, no overlap).
+ */
+icr_status icr_forward_level(const icr_plan* plan, int32_t level, int64_t batch,
+                             const void* s_coarse, int64_t coarse_stride,
+                             const void* xi_fine, int64_t xi_stride,
+                             void* s_fine, int64_t fine_stride, void* hip_stream);
+icr_status icr_adjoint_level(const icr_plan* plan, int32_t level, int64_t batch,
+                             const void* y_fine, int64_t y_stride,
+                             void* xi_bar_fine, int64_t xi_bar_stride,
+                             void* s_bar_coarse, int64_t coarse_stride, void* hip_stream);
+
 /* Free the plan's device memory. NULL is a no-op. Not safe while calls using the
  * plan are still running on a stream. */
 icr_status icr_plan_destroy(icr_plan* plan);

@@ -4,7 +4,8 @@ The library libicr.so (HIP kernels behind the C ABI in include/icr.h) does all
 the work; this package binds it with ctypes and wraps it for PyTorch autograd.
 """
 
-from .icr import (ICRError, IcrConfig, Plan, icr_adjoint, icr_build_matrices, icr_forward,  # noqa: F401
+from .icr import (ICRError, IcrConfig, Plan, icr_adjoint, icr_adjoint_level,  # noqa: F401
+                  icr_build_matrices, icr_forward, icr_forward_level,
                   icr_last_error, icr_metric_apply, icr_plan_copy_level0,
                   icr_plan_copy_refinement, icr_plan_destroy, icr_plan_set_level0,
                   icr_plan_set_refinement, icr_plan_get_info, icr_version,

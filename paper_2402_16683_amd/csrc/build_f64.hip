@@ -273,6 +273,54 @@ __global__ void convert_level_kernel(const double* __restrict__ src, int64_t nse
   else dst[t] = v;
 }
 
+// Reflection-sector form of a stationary R. Per axis, the window (s_-1, s_0, s_+1)
+// maps to even/odd channels (e, m, o) = (s_-1 + s_+1, s_0, s_+1 - s_-1) and the two
+// children (o_0, o_1) to (S, D) = (o_0 + o_1, o_1 - o_0). A kernel that is invariant
+// under reflecting any axis (every radial kernel on a regular grid) gives an R for
+// which M = Q R P^-1 only couples sector sigma (S or D per axis) with channels t
+// whose axes carry (e or m) where sigma is S and o where sigma is D: 3^d non-zeros
+// instead of 2^d 3^d. Then R = B C P with C = M / 2^d on that pattern and B the
+// per-axis butterfly o_0 = S - D, o_1 = S + D. One thread per channel t writes C[t],
+// the largest off-pattern |M[., t]| and the on-pattern |M[sigma(t), t]|.
+template <int D>
+__global__ void sector_kernel(const double* __restrict__ r64, double* __restrict__ out) {
+  constexpr int NW = pow3(D);
+  constexpr int NC = 1 << D;
+  const int t = threadIdx.x;
+  if (t >= NW) return;
+  // P^-1 rows w in {-1,0,1} (index w+1), columns t in {e, m, o}
+  const double pinv[3][3] = {{0.5, 0.0, -0.5}, {0.0, 1.0, 0.0}, {0.5, 0.0, 0.5}};
+  int ta[D];
+  {
+    int rem = t;
+    for (int a = D - 1; a >= 0; --a) { ta[a] = rem % 3; rem /= 3; }
+  }
+  int own = 0;
+  for (int a = 0; a < D; ++a) own = (own << 1) | (ta[a] == 2 ? 1 : 0);
+  double off = 0.0, on = 0.0, coef = 0.0;
+  for (int sg = 0; sg < NC; ++sg) {
+    double m = 0.0;
+    for (int b = 0; b < NC; ++b) {
+      double q = 1.0;
+      for (int a = 0; a < D; ++a) {
+        const int sa = (sg >> (D - 1 - a)) & 1, ba = (b >> (D - 1 - a)) & 1;
+        q *= (sa == 1 && ba == 0) ? -1.0 : 1.0;   // Q = [[1, 1], [-1, 1]]
+      }
+      for (int w = 0; w < NW; ++w) {
+        double pv = 1.0;
+        int rem = w;
+        for (int a = D - 1; a >= 0; --a) { pv *= pinv[rem % 3][ta[a]]; rem /= 3; }
+        if (pv != 0.0) m += q * r64[b * NW + w] * pv;
+      }
+    }
+    if (sg == own) { on = fabs(m); coef = m / NC; }
+    else off = fmax(off, fabs(m));
+  }
+  out[t] = coef;
+  out[NW + t] = off;
+  out[2 * NW + t] = on;
+}
+
 KernelSpec kernel_spec(const icr_plan* p) {
   return KernelSpec{p->cfg.kernel, p->cfg.scale * p->cfg.scale, p->cfg.length};
 }
@@ -361,6 +409,16 @@ hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st) {
+  const LevelMats& m = p->lev[level];
+  switch (p->ndim) {
+    case 1: sector_kernel<1><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
+    case 2: sector_kernel<2><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
+    default: sector_kernel<3><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace icr

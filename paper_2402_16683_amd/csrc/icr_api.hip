@@ -154,13 +154,40 @@ icr_status check_call(const icr_plan* p, int64_t batch) {
   return ICR_OK;
 }
 
+// Host copies of a stationary level's FP32 matrices and its sector form (the fast
+// kernels take them by value). Synchronous; called at build and after set_refinement.
+icr_status refresh_host_copies(icr_plan* p, int level) {
+  icr::LevelMats& m = p->lev[level];
+  m.sector_ok = false;
+  m.sector_asym = 1.0;
+  if (p->charted || p->precision == ICR_F64) return ICR_OK;
+  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
+  ICR_HIP_TRY(hipMemcpy(m.h_r, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost));
+  ICR_HIP_TRY(hipMemcpy(m.h_s, m.s_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
+  double sec[3 * 27];
+  ICR_HIP_TRY(hipMemcpy(sec, m.sector64, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost));
+  double off = 0.0, on = 0.0;
+  for (int t = 0; t < nw; ++t) {
+    m.h_sector[t] = static_cast<float>(sec[t]);
+    off = std::fmax(off, sec[nw + t]);
+    on = std::fmax(on, sec[2 * nw + t]);
+  }
+  m.sector_asym = on > 0.0 ? off / on : 1.0;
+  m.sector_ok = std::isfinite(m.sector_asym) && m.sector_asym <= icr::kSectorTolerance;
+  return ICR_OK;
+}
+
 }  // namespace
 
 namespace icr {
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (try_refine3_fwd_sector(p, level, a, st, &e)) return e;
   return launch_refine_fwd_generic(p, level, a, st);
 }
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (try_refine3_adj_sector(p, level, a, st, &e)) return e;
   return launch_refine_adj_generic(p, level, a, st);
 }
 }  // namespace icr
@@ -224,7 +251,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   const size_t off_l64 = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * 8);
   const size_t off_lc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
   const size_t off_uc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
-  size_t off_lev[ICR_MAX_DEPTH][4];
+  size_t off_lev[ICR_MAX_DEPTH][5];
   for (int l = 0; l < p->depth; ++l) {
     int64_t nsets = 1;
     if (p->charted)
@@ -234,6 +261,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][1] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * 8);
     off_lev[l][2] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * ab);
     off_lev[l][3] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * ab);
+    off_lev[l][4] = bytes; bytes = align_up(bytes + size_t(3) * nw * 8);
   }
   const size_t off_status = bytes; bytes = align_up(bytes + sizeof(int32_t) * (kMaxLevels + 1));
 
@@ -254,6 +282,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     p->lev[l].s64 = reinterpret_cast<double*>(base + off_lev[l][1]);
     p->lev[l].r_c = base + off_lev[l][2];
     p->lev[l].s_c = base + off_lev[l][3];
+    p->lev[l].sector64 = reinterpret_cast<double*>(base + off_lev[l][4]);
   }
   int32_t* status = reinterpret_cast<int32_t*>(base + off_status);
   int32_t* counts = status + 1;
@@ -276,12 +305,21 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   for (int l = 0; l < p->depth; ++l) {
     BUILD_TRY(icr::launch_build_level(p, l, counts + 1 + l, status, st));
     BUILD_TRY(icr::launch_level_convert(p, l, st));
+    if (!p->charted) BUILD_TRY(icr::launch_sector(p, l, st));
   }
   int32_t host_status[kMaxLevels + 1];
   BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
   BUILD_TRY(hipStreamSynchronize(st));
 #undef BUILD_TRY
   for (int l = 0; l <= p->depth; ++l) p->clamped[l] = host_status[1 + l];
+  for (int l = 0; l < p->depth; ++l) {
+    const icr_status hs = refresh_host_copies(p, l);
+    if (hs != ICR_OK) {
+      (void)hipFree(p->pool);
+      delete p;
+      return hs;
+    }
+  }
   if (host_status[0] & 2)
     return bail(ICR_ERR_NOT_PD, "K_00 is not positive definite (a pivot needed clamping; clamping disabled)");
   if (host_status[0] & 1)
@@ -355,8 +393,9 @@ icr_status icr_plan_set_refinement(icr_plan* p, int32_t level, const double* r, 
   ICR_HIP_TRY(hipMemcpyAsync(m.r64, r, size_t(m.nsets) * nc * nw * 8, hipMemcpyHostToDevice, st));
   ICR_HIP_TRY(hipMemcpyAsync(m.s64, sqrtd, size_t(m.nsets) * nc * nc * 8, hipMemcpyHostToDevice, st));
   ICR_HIP_TRY(icr::launch_level_convert(p, level, st));
+  if (!p->charted) ICR_HIP_TRY(icr::launch_sector(p, level, st));
   ICR_HIP_TRY(hipStreamSynchronize(st));
-  return ICR_OK;
+  return refresh_host_copies(p, level);
 }
 
 icr_status icr_forward(const icr_plan* p, int64_t batch, const void* xi, void* s, void* workspace,
@@ -417,6 +456,70 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   if (r != ICR_OK) return r;
   return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
                      v, st);
+}
+
+icr_status icr_forward_level(const icr_plan* p, int32_t level, int64_t batch, const void* s_coarse,
+                             int64_t coarse_stride, const void* xi_fine, int64_t xi_stride,
+                             void* s_fine, int64_t fine_stride, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK) return cs;
+  if (level < -1 || level >= p->depth) return fail(ICR_ERR_INVALID_ARG, "level out of range");
+  if (batch == 0) return ICR_OK;
+  const int el = p->elem_bytes;
+  const int64_t nf = p->offsets[level + 2] - p->offsets[level + 1];
+  const int64_t nc = level >= 0 ? p->offsets[level + 1] - p->offsets[level] : 0;
+  if (!xi_fine || !s_fine || (level >= 0 && !s_coarse)) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (xi_stride < nf || fine_stride < nf || (level >= 0 && coarse_stride < nc))
+    return fail(ICR_ERR_INVALID_ARG, "stride smaller than the level size");
+  if (!aligned(xi_fine, el) || !aligned(s_fine, el) || (s_coarse && !aligned(s_coarse, el)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t bx = size_t((batch - 1) * xi_stride + nf) * el, bf = size_t((batch - 1) * fine_stride + nf) * el;
+  const size_t bc = level >= 0 ? size_t((batch - 1) * coarse_stride + nc) * el : 0;
+  if (overlaps(s_fine, bf, xi_fine, bx) || overlaps(s_fine, bf, s_coarse, bc))
+    return fail(ICR_ERR_INVALID_ARG, "s_fine overlaps an input");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (level < 0) {
+    icr::Level0Args a{xi_fine, xi_stride, s_fine, fine_stride, nullptr, 0, nullptr, 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_fwd(p, a, st));
+    return ICR_OK;
+  }
+  icr::RefineFwdArgs a{s_coarse, coarse_stride, xi_fine, xi_stride, s_fine, fine_stride, nullptr, 0, batch};
+  ICR_HIP_TRY(icr::launch_refine_fwd(p, level, a, st));
+  return ICR_OK;
+}
+
+icr_status icr_adjoint_level(const icr_plan* p, int32_t level, int64_t batch, const void* y_fine,
+                             int64_t y_stride, void* xi_bar_fine, int64_t xi_bar_stride,
+                             void* s_bar_coarse, int64_t coarse_stride, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK) return cs;
+  if (level < -1 || level >= p->depth) return fail(ICR_ERR_INVALID_ARG, "level out of range");
+  if (batch == 0) return ICR_OK;
+  const int el = p->elem_bytes;
+  const int64_t nf = p->offsets[level + 2] - p->offsets[level + 1];
+  const int64_t nc = level >= 0 ? p->offsets[level + 1] - p->offsets[level] : 0;
+  if (!y_fine || !xi_bar_fine || (level >= 0 && !s_bar_coarse)) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (y_stride < nf || xi_bar_stride < nf || (level >= 0 && coarse_stride < nc))
+    return fail(ICR_ERR_INVALID_ARG, "stride smaller than the level size");
+  if (!aligned(y_fine, el) || !aligned(xi_bar_fine, el) || (s_bar_coarse && !aligned(s_bar_coarse, el)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t by = size_t((batch - 1) * y_stride + nf) * el, bx = size_t((batch - 1) * xi_bar_stride + nf) * el;
+  const size_t bc = level >= 0 ? size_t((batch - 1) * coarse_stride + nc) * el : 0;
+  if (overlaps(xi_bar_fine, bx, y_fine, by) || overlaps(s_bar_coarse, bc, y_fine, by) ||
+      overlaps(s_bar_coarse, bc, xi_bar_fine, bx))
+    return fail(ICR_ERR_INVALID_ARG, "buffers overlap");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (level < 0) {
+    icr::Level0Args a{y_fine, y_stride, xi_bar_fine, xi_bar_stride, nullptr, 0, nullptr, 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
+    return ICR_OK;
+  }
+  icr::RefineAdjArgs a{y_fine, y_stride, xi_bar_fine, xi_bar_stride, s_bar_coarse, coarse_stride,
+                       nullptr, 0, batch};
+  ICR_HIP_TRY(icr::launch_refine_adj(p, level, a, st));
+  return ICR_OK;
 }
 
 icr_status icr_plan_destroy(icr_plan* p) {

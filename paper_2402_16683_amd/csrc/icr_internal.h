@@ -48,9 +48,20 @@ struct LevelMats {
   double* s64 = nullptr;  // [nsets][2^d][2^d], lower triangular
   void* r_c = nullptr;    // arithmetic type; stationary: [2^d][3^d]; charted: [2^d*3^d][nsets]
   void* s_c = nullptr;    // arithmetic type; stationary: [2^d][2^d]; charted: [2^d*2^d][nsets]
-  void* sector_c = nullptr;  // stationary FP32 only: reflection-sector coefficients (see refine_fast)
   int64_t nsets = 0;
+  // Stationary levels: host copies of the FP32 matrices, passed to the fast kernels by
+  // value, and the reflection-sector form of R (see sector_kernel in build_f64.hip).
+  double* sector64 = nullptr;  // device scratch: [3^d] coefficients, [3^d] off-pattern, [3^d] on-pattern
+  float h_r[8 * 27];
+  float h_s[8 * 8];
+  float h_sector[27];
+  double sector_asym = 1.0;    // max off-pattern / max on-pattern entry of Q R P^-1
+  bool sector_ok = false;      // R is reflection-symmetric to FP32 precision
 };
+
+// R is applied in the reflection-sector basis only when its asymmetric part is below
+// FP32 rounding of R itself.
+constexpr double kSectorTolerance = 1e-7;
 
 }  // namespace icr
 
@@ -94,6 +105,7 @@ hipError_t launch_level0_convert(const icr_plan* p, hipStream_t st);
 hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int32_t* status,
                               hipStream_t st);
 hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st);
+hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st);
 
 // level 0 apply: out = L00 in (forward) / U00 in (+ add) (adjoint); w optional
 struct Level0Args {
@@ -125,6 +137,12 @@ hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& 
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
 hipError_t launch_refine_fwd_generic(const icr_plan* p, int level, const RefineFwdArgs& a,
                                      hipStream_t st);
+// Specialised kernels: return false (launching nothing) when the level or the buffers
+// do not qualify; otherwise launch and report the launch status in *err.
+bool try_refine3_fwd_sector(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st,
+                            hipError_t* err);
+bool try_refine3_adj_sector(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st,
+                            hipError_t* err);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);
 

@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_forward": [vp, i64, vp, vp, vp, vp],
         "icr_adjoint": [vp, i64, vp, vp, vp, vp],
         "icr_metric_apply": [vp, i64, vp, i64, vp, vp, vp, vp],
+        "icr_forward_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
+        "icr_adjoint_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_plan_destroy": [vp],
     }
     for name, args in sigs.items():
@@ -306,6 +308,34 @@ def icr_metric_apply(plan: Plan, w, v, out=None, workspace=None, stream=None):
     _check(load_library().icr_metric_apply(plan.handle, batch, w.data_ptr(), w_stride, v.data_ptr(),
                                            out.data_ptr(), workspace.data_ptr(), _stream_handle(stream)))
     return out
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stride(t):
+    return 0 if t is None else (t.stride(0) if t.dim() > 1 else t.numel())
+
+
+def icr_forward_level(plan: Plan, level: int, s_coarse, xi_fine, s_fine, stream=None):
+    """One forward level on (batch, size) views; level -1 is the level-0 factor."""
+    batch = xi_fine.shape[0] if xi_fine.dim() > 1 else 1
+    _check(load_library().icr_forward_level(plan.handle, level, batch, _ptr(s_coarse), _stride(s_coarse),
+                                            _ptr(xi_fine), xi_fine.stride(0) if xi_fine.dim() > 1 else xi_fine.numel(),
+                                            _ptr(s_fine), s_fine.stride(0) if s_fine.dim() > 1 else s_fine.numel(),
+                                            _stream_handle(stream)))
+    return s_fine
+
+
+def icr_adjoint_level(plan: Plan, level: int, y_fine, xi_bar_fine, s_bar_coarse, stream=None):
+    """One adjoint level on (batch, size) views; level -1 is the level-0 factor."""
+    batch = y_fine.shape[0] if y_fine.dim() > 1 else 1
+    st = lambda t: 0 if t is None else (t.stride(0) if t.dim() > 1 else t.numel())
+    _check(load_library().icr_adjoint_level(plan.handle, level, batch, _ptr(y_fine), st(y_fine),
+                                            _ptr(xi_bar_fine), st(xi_bar_fine), _ptr(s_bar_coarse),
+                                            st(s_bar_coarse), _stream_handle(stream)))
+    return xi_bar_fine
 
 
 def icr_plan_destroy(plan: Plan):

@@ -25,6 +25,8 @@ CASES = [
     C.from_workload("icr1d_m32_12to260", precision="bf16", name="1d_m32_full_bf16"),
     C.from_workload("icr2d_se_16to1540_b16", depth=4, batch=2, name="2d_se_16to196_b2_f32"),
     C.from_workload("icr2d_se_16to1540_b16", depth=3, precision="f64", name="2d_se_16to100_f64"),
+    C.from_workload("icr3d_m52_10to388", name="3d_m52_full_f32"),
+    C.from_workload("icr3d_m52_10to388", precision="bf16", name="3d_m52_full_bf16"),
     C.from_workload("icr3d_m52_10to388", depth=3, name="3d_m52_10to52_f32"),
     C.from_workload("icr3d_m52_10to388", depth=2, precision="bf16", name="3d_m52_10to28_bf16"),
     C.from_workload("icr3d_m52_10to388", depth=2, precision="f64", name="3d_m52_10to28_f64"),
