@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--precision", default=None, help="f32 or bf16 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--levels", action="store_true", help="also time every level's kernels")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
 
 
@@ -192,6 +195,44 @@ def main():
     digest = kernel_source_digest()
     tag = f"{dom}:{args.workload}:{prec}"
 
+    levels = None
+    if args.levels:
+        levels = []
+        for l in range(-1, L):
+            lo, hi = offs[l + 1], offs[l + 2]
+            if l < 0:
+                f = lambda k: B.icr_forward_level(plan, -1, None, sets[k % 2]["xi"][:, :hi],
+                                                  sets[k % 2]["wsf"][:, :hi])
+                g = lambda k: B.icr_adjoint_level(plan, -1, sets[k % 2]["wsa"][:, :hi],
+                                                  sets[k % 2]["xib"][:, :hi], None)
+            else:
+                def f(k, l=l, lo=lo, hi=hi):
+                    b = sets[k % 2]
+                    out = b["s"] if l == L - 1 else b["wsf"][:, lo:hi]
+                    B.icr_forward_level(plan, l, b["wsf"][:, offs[l]:lo], b["xi"][:, lo:hi], out)
+
+                def g(k, l=l, lo=lo, hi=hi):
+                    b = sets[k % 2]
+                    yin = b["y"] if l == L - 1 else b["wsa"][:, lo:hi]
+                    B.icr_adjoint_level(plan, l, yin, b["xib"][:, lo:hi], b["wsa"][:, offs[l]:lo])
+            levels.append({"level": l, "fwd_ms": time_launches(f, 20), "adj_ms": time_launches(g, 20),
+                           "fine_elems": batch * (hi - lo)})
+    copy_gbs = None
+    if not args.copy_probe:
+        # on-box streaming reference: a 1 GiB device-to-device copy (read + write)
+        csrc = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        cdst = torch.empty_like(csrc)
+        for _ in range(2):
+            cdst.copy_(csrc)
+        copy_ms = time_launches(lambda k: cdst.copy_(csrc), 10)
+        copy_gbs = 2 * csrc.numel() * 4 / (copy_ms * 1e-3) / 1e9
+        del csrc, cdst
+    else:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     step_bytes = 2 * batch * (n_xi + n_out) * el
     value = batch * n_out / (ms_per_step * 1e-3)
     out = {
@@ -214,12 +255,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(tag, digest),
                      "kernel": dom, "launch_ms": dom_ms, "alg_bytes_per_launch": launch_bytes,
-                     "fwd_last_ms": fwd_ms, "adj_last_ms": adj_ms},
+                     "fwd_last_ms": fwd_ms, "adj_last_ms": adj_ms,
+                     "copy_reference_gbs": copy_gbs},
         "step": {"alg_bytes": step_bytes,
                  "hbm_frac": step_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
                  "ms_p16_p50_p84": [float(v) for v in q], "build_ms": build_s * 1e3},
         "source_digest": digest,
     }
+    if levels is not None:
+        out["levels"] = levels
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.quiet)
     print(json.dumps(out), flush=True)

@@ -20,7 +20,7 @@
 // (Q), scaled per channel (C^T) and sent back through P^T one axis at a time. The
 // z stage accumulates in registers while marching along z; the y and x stages need
 // the neighbouring blocks' contributions, which are exchanged through LDS inside a
-// 16 x 16 tile of block pairs whose outer ring (halo) is recomputed by each tile.
+// tile of block pairs whose outer ring (halo) is recomputed by each tile.
 // Every coarse cotangent is summed by one thread in a fixed order.
 #include "icr_internal.h"
 
@@ -53,6 +53,45 @@ template <> struct Io<bf16_t> {
   static __device__ __forceinline__ void st1(bf16_t* p, float v) { *p = f32_to_bf16(v); }
 };
 
+// Workgroups are handed to the 8 XCDs round-robin (workgroup w runs on XCD w % 8),
+// and each XCD has its own L2. Renumber so that XCD k works through a contiguous
+// range of logical tiles: neighbouring tiles, which read each other's halo, then
+// share an L2 and run at about the same time.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+  const int per = n / kXcds;
+  return w < per * kXcds ? (w % kXcds) * per + w / kXcds : w;
+}
+
+// Streams that are read or written exactly once bypass cache retention.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+template <typename TS>
+__device__ __forceinline__ float4 ld4_stream(const TS* p);
+template <>
+__device__ __forceinline__ float4 ld4_stream<float>(const float* p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ float4 ld4_stream<bf16_t>(const bf16_t* p) {
+  const nt_u2 u = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+}
+template <typename TS>
+__device__ __forceinline__ void st4_stream(TS* p, float4 v);
+template <>
+__device__ __forceinline__ void st4_stream<float>(float* p, float4 v) {
+  const nt_f4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_f4*>(p));
+}
+template <>
+__device__ __forceinline__ void st4_stream<bf16_t>(bf16_t* p, float4 v) {
+  const nt_u2 w = {pack_bf16(v.x, v.y), pack_bf16(v.z, v.w)};
+  __builtin_nontemporal_store(w, reinterpret_cast<nt_u2*>(p));
+}
+
 // sector coefficients C (27, already divided by 8) and the lower sqrtD packed by rows
 struct Sector3 {
   float c[27];
@@ -61,17 +100,29 @@ struct Sector3 {
 
 __device__ __forceinline__ int sd(int b, int bp) { return b * (b + 1) / 2 + bp; }
 
-// x and y even/odd stages of one coarse plane for the pixel pair (2q+1, 2q+2) of
-// row y: T[k][ty * 3 + tx], channels e, m, o = 0, 1, 2.
+// The four coarse values x = 2q .. 2q+3 of rows y-1, y, y+1 of one plane.
+struct Raw3 {
+  float2 a[3], b[3];
+};
 template <typename TS>
-__device__ __forceinline__ void plane_stage(const TS* __restrict__ plane, int y, int nx, int q,
-                                            float (&T)[2][9]) {
+__device__ __forceinline__ Raw3 plane_load(const TS* __restrict__ plane, int y, int nx, int q) {
+  Raw3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const TS* row = plane + static_cast<int64_t>(y - 1 + i) * nx + 2 * q;
+    r.a[i] = Io<TS>::ld2(row);
+    r.b[i] = Io<TS>::ld2(row + 2);
+  }
+  return r;
+}
+
+// x and y even/odd stages of one coarse plane for the pixel pair (2q+1, 2q+2):
+// T[k][ty * 3 + tx], channels e, m, o = 0, 1, 2.
+__device__ __forceinline__ void plane_stage(const Raw3& raw, float (&T)[2][9]) {
   float X[3][2][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const TS* row = plane + static_cast<int64_t>(y - 1 + r) * nx + 2 * q;
-    const float2 a = Io<TS>::ld2(row);
-    const float2 b = Io<TS>::ld2(row + 2);
+    const float2 a = raw.a[r], b = raw.b[r];
     X[r][0][0] = a.x + b.x; X[r][0][1] = a.y; X[r][0][2] = b.x - a.x;
     X[r][1][0] = a.y + b.y; X[r][1][1] = b.x; X[r][1][2] = b.y - a.y;
   }
@@ -125,38 +176,54 @@ struct Fwd3Geom {
   int rows;        // ny - 2 interior rows
   int zchunk;      // interior coarse planes per workgroup
   int nfy, nfx;    // fine rows per plane, fine row length
+  int xy_blocks;   // workgroups per chunk of planes
+  int nwg;         // workgroups per sample
 };
 
-template <typename TS>
+// The z loop is unrolled by two with ping-pong load buffers, and every load goes to a
+// clamped in-bounds address: loaded registers are never copied or loaded under a
+// branch, so the next step's loads stay in flight while the current step computes.
+template <typename TS, bool kW>
 __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, Sector3 k) {
-  const int tid = blockIdx.x * 256 + threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, g.nwg);
+  const int tid = (tile % g.xy_blocks) * 256 + threadIdx.x;
   if (tid >= g.rows * g.pairs) return;
   const int yi = tid / g.pairs;
   const int q = tid - yi * g.pairs;
   const int y = yi + 1;
-  const int zb = 1 + blockIdx.y * g.zchunk;
+  const int zb = 1 + (tile / g.xy_blocks) * g.zchunk;
   const int ze = min(zb + g.zchunk, g.nz - 1);
-  const int64_t b = blockIdx.z;
+  const int64_t b = blockIdx.y;
   const TS* sc = static_cast<const TS*>(a.s_in) + b * a.s_in_bs;
   const TS* xi = static_cast<const TS*>(a.xi) + b * a.xi_bs;
   TS* so = static_cast<TS*>(a.s_out) + b * a.s_out_bs;
-  const float* w = a.w ? static_cast<const float*>(a.w) + b * a.w_bs : nullptr;
+  const float* w = kW ? static_cast<const float*>(a.w) + b * a.w_bs : nullptr;
   const int64_t cplane = static_cast<int64_t>(g.ny) * g.nx;
+  const int64_t fplane = static_cast<int64_t>(g.nfy) * g.nfx;
+  const int64_t frow = static_cast<int64_t>(2 * (y - 1)) * g.nfx + 4 * q;
 
-  float T0[2][9], T1[2][9], T2[2][9];
-  plane_stage<TS>(sc + (zb - 1) * cplane, y, g.nx, q, T0);
-  plane_stage<TS>(sc + zb * cplane, y, g.nx, q, T1);
-  for (int z = zb; z < ze; ++z) {
-    plane_stage<TS>(sc + (z + 1) * cplane, y, g.nx, q, T2);
-    int64_t off[2][2];
-    float4 xr[2][2];
+  struct Step {
+    Raw3 raw;            // coarse plane z + 1
+    float4 xr[2][2];     // excitations of the pair's children in plane z
+    float4 wr[2][2];     // metric weights (kW)
+  };
+  auto fine_off = [&](int z, int bz, int by) {
+    return (2 * (z - 1) + bz) * fplane + frow + by * g.nfx;
+  };
+  auto load_step = [&](int z, Step& st) {
+    const int zc = min(z, ze - 1);
+    st.raw = plane_load<TS>(sc + (zc + 1) * cplane, y, g.nx, q);
 #pragma unroll
     for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
       for (int by = 0; by < 2; ++by) {
-        off[bz][by] = (static_cast<int64_t>(2 * (z - 1) + bz) * g.nfy + 2 * (y - 1) + by) * g.nfx + 4 * q;
-        xr[bz][by] = Io<TS>::ld4(xi + off[bz][by]);
+        st.xr[bz][by] = ld4_stream<TS>(xi + fine_off(zc, bz, by));
+        if (kW) st.wr[bz][by] = *reinterpret_cast<const float4*>(w + fine_off(zc, bz, by));
       }
+  };
+  float T0[2][9], T1[2][9], T2[2][9];
+  auto compute_step = [&](int z, const Step& st) {
+    plane_stage(st.raw, T2);
     float o[2][8];
     sector_forward(T0[0], T1[0], T2[0], k, o[0]);
     sector_forward(T0[1], T1[1], T2[1], k, o[1]);
@@ -167,8 +234,8 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
       for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
         for (int by = 0; by < 2; ++by) {
-          x[bz * 4 + by * 2] = p == 0 ? xr[bz][by].x : xr[bz][by].z;
-          x[bz * 4 + by * 2 + 1] = p == 0 ? xr[bz][by].y : xr[bz][by].w;
+          x[bz * 4 + by * 2] = p == 0 ? st.xr[bz][by].x : st.xr[bz][by].z;
+          x[bz * 4 + by * 2 + 1] = p == 0 ? st.xr[bz][by].y : st.xr[bz][by].w;
         }
 #pragma unroll
       for (int c = 0; c < 8; ++c)
@@ -181,26 +248,38 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
       for (int by = 0; by < 2; ++by) {
         const int h = bz * 4 + by * 2;
         float4 v = make_float4(o[0][h], o[0][h + 1], o[1][h], o[1][h + 1]);
-        if (w) {
-          const float4 ww = *reinterpret_cast<const float4*>(w + off[bz][by]);
+        if (kW) {
+          const float4 ww = st.wr[bz][by];
           v.x *= ww.x; v.y *= ww.y; v.z *= ww.z; v.w *= ww.w;
         }
-        Io<TS>::st4(so + off[bz][by], v);
+        st4_stream<TS>(so + fine_off(z, bz, by), v);
       }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
       for (int j = 0; j < 9; ++j) { T0[p][j] = T1[p][j]; T1[p][j] = T2[p][j]; }
+  };
+
+  plane_stage(plane_load<TS>(sc + (zb - 1) * cplane, y, g.nx, q), T0);
+  plane_stage(plane_load<TS>(sc + zb * cplane, y, g.nx, q), T1);
+  // two steps in flight: a ring of three buffers, unrolled so no buffer is copied
+  Step sa, sb2, sc2;
+  load_step(zb, sa);
+  load_step(zb + 1, sb2);
+  for (int z = zb; z < ze; z += 3) {
+    load_step(z + 2, sc2);
+    compute_step(z, sa);
+    if (z + 1 >= ze) break;
+    load_step(z + 3, sa);
+    compute_step(z + 1, sb2);
+    if (z + 2 >= ze) break;
+    load_step(z + 4, sb2);
+    compute_step(z + 2, sc2);
   }
 }
 
 // ----------------------------------------------------------------------------- adjoint
 
-constexpr int kTP = 16;          // tile width in block pairs, halo included
-constexpr int kTR = 16;          // tile height in block rows, halo included
-constexpr int kOP = kTP - 2;     // owned pairs per tile
-constexpr int kOR = kTR - 2;     // owned rows per tile
-constexpr int kAdjThreads = kTP * kTR;
 
 struct Adj3Geom {
   int nz, ny, nx;   // coarse shape
@@ -208,27 +287,57 @@ struct Adj3Geom {
   int xtiles;       // tiles along x
   int zchunk;       // coarse planes per workgroup
   int nfy, nfx;
+  int xy_tiles;     // tiles per chunk of planes
+  int nwg;          // workgroups per sample
 };
 
-template <typename TS>
-__global__ void __launch_bounds__(kAdjThreads) refine3_adj_sector(Adj3Geom g, RefineAdjArgs a, Sector3 k) {
+// Tile: kTP block pairs (x) by kTR block rows (y), halo ring included.
+template <typename TS, bool kAdd, int kTP, int kTR>
+__global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, RefineAdjArgs a, Sector3 k) {
+  constexpr int kOP = kTP - 2;     // owned pairs per tile
+  constexpr int kOR = kTR - 2;     // owned rows per tile
+  constexpr int kAdjThreads = kTP * kTR;
   __shared__ float ldy[12][kAdjThreads];
   __shared__ float ldx[2][kAdjThreads];
   const int t = threadIdx.x;
   const int i = t % kTP, j = t / kTP;
-  const int xt = blockIdx.x % g.xtiles, yt = blockIdx.x / g.xtiles;
+  const int tile = xcd_tile(blockIdx.x, g.nwg);
+  const int xy = tile % g.xy_tiles;
+  const int xt = xy % g.xtiles, yt = xy / g.xtiles;
   const int P = xt * kOP + i - 1;      // block pair: blocks x = 2P+1, 2P+2
   const int yb = yt * kOR + j - 1;     // block row = coarse row
-  const int z0 = blockIdx.y * g.zchunk;
+  const int z0 = (tile / g.xy_tiles) * g.zchunk;
   const int z1 = min(z0 + g.zchunk, g.nz);
-  const int64_t b = blockIdx.z;
+  const int64_t b = blockIdx.y;
   const bool pair_ok = P >= 0 && P < g.pairs;
   const bool blocks_ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
   const bool owner = i >= 1 && i <= kOP && j >= 1 && j <= kOR && pair_ok && yb >= 0 && yb < g.ny;
   const TS* y = static_cast<const TS*>(a.y) + b * a.y_bs;
   TS* xb = static_cast<TS*>(a.xi_bar) + b * a.xi_bar_bs;
   TS* sb = static_cast<TS*>(a.s_bar) + b * a.s_bar_bs;
-  const TS* add = a.add ? static_cast<const TS*>(a.add) + b * a.add_bs : nullptr;
+  const TS* add = kAdd ? static_cast<const TS*>(a.add) + b * a.add_bs : nullptr;
+  // loads always use an in-bounds address (clamped block coordinates); blocks outside
+  // the interior are zeroed after the load
+  const int Pc = min(max(P, 0), g.pairs - 1);
+  const int ybc = min(max(yb, 1), g.ny - 2);
+  const int64_t fplane = static_cast<int64_t>(g.nfy) * g.nfx;
+  const int64_t frow = static_cast<int64_t>(2 * (ybc - 1)) * g.nfx + 4 * Pc;
+  auto fine_off = [&](int zc, int bz, int by) { return (2 * (zc - 1) + bz) * fplane + frow + by * g.nfx; };
+
+  struct Plane {
+    float4 r[2][2];   // cotangent rows of the pair's blocks
+    float4 v[2][2];   // metric: values added to xi_bar (kAdd)
+  };
+  auto load_plane_y = [&](int zb, Plane& pl) {
+    const int zc = min(max(zb, 1), g.nz - 2);
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        pl.r[bz][by] = Io<TS>::ld4(y + fine_off(zc, bz, by));
+        if (kAdd) pl.v[bz][by] = Io<TS>::ld4(add + fine_off(zc, bz, by));
+      }
+  };
 
   float A0[2][9], A1[2][9];
 #pragma unroll
@@ -236,50 +345,42 @@ __global__ void __launch_bounds__(kAdjThreads) refine3_adj_sector(Adj3Geom g, Re
 #pragma unroll
     for (int h = 0; h < 9; ++h) { A0[p][h] = 0.0f; A1[p][h] = 0.0f; }
 
-  for (int zb = z0 - 1; zb <= z1; ++zb) {
+  auto process = [&](int zb, const Plane& pl) {
+    const bool ok = blocks_ok && zb >= 1 && zb <= g.nz - 2;
     float yv[2][8];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
-      for (int c = 0; c < 8; ++c) yv[p][c] = 0.0f;
-    if (blocks_ok && zb >= 1 && zb <= g.nz - 2) {
-      int64_t off[2][2];
-      float4 r[2][2];
+      for (int by = 0; by < 2; ++by) {
+        const float4 r = pl.r[bz][by];
+        yv[0][bz * 4 + by * 2] = ok ? r.x : 0.0f;
+        yv[0][bz * 4 + by * 2 + 1] = ok ? r.y : 0.0f;
+        yv[1][bz * 4 + by * 2] = ok ? r.z : 0.0f;
+        yv[1][bz * 4 + by * 2 + 1] = ok ? r.w : 0.0f;
+      }
+    if (ok && owner && zb >= z0 && zb < z1) {
+      float xo[2][8];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int cp = 0; cp < 8; ++cp) {
+          float v = 0.0f;
+#pragma unroll
+          for (int c = cp; c < 8; ++c) v = fmaf(k.s[sd(c, cp)], yv[p][c], v);
+          xo[p][cp] = v;
+        }
 #pragma unroll
       for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
         for (int by = 0; by < 2; ++by) {
-          off[bz][by] = (static_cast<int64_t>(2 * (zb - 1) + bz) * g.nfy + 2 * (yb - 1) + by) * g.nfx + 4 * P;
-          r[bz][by] = Io<TS>::ld4(y + off[bz][by]);
-          yv[0][bz * 4 + by * 2] = r[bz][by].x;
-          yv[0][bz * 4 + by * 2 + 1] = r[bz][by].y;
-          yv[1][bz * 4 + by * 2] = r[bz][by].z;
-          yv[1][bz * 4 + by * 2 + 1] = r[bz][by].w;
+          const int h = bz * 4 + by * 2;
+          float4 v = make_float4(xo[0][h], xo[0][h + 1], xo[1][h], xo[1][h + 1]);
+          if (kAdd) {
+            const float4 av = pl.v[bz][by];
+            v.x += av.x; v.y += av.y; v.z += av.z; v.w += av.w;
+          }
+          st4_stream<TS>(xb + fine_off(zb, bz, by), v);
         }
-      if (owner && zb >= z0 && zb < z1) {
-        float xo[2][8];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-          for (int cp = 0; cp < 8; ++cp) {
-            float v = 0.0f;
-#pragma unroll
-            for (int c = cp; c < 8; ++c) v = fmaf(k.s[sd(c, cp)], yv[p][c], v);
-            xo[p][cp] = v;
-          }
-#pragma unroll
-        for (int bz = 0; bz < 2; ++bz)
-#pragma unroll
-          for (int by = 0; by < 2; ++by) {
-            const int h = bz * 4 + by * 2;
-            float4 v = make_float4(xo[0][h], xo[0][h + 1], xo[1][h], xo[1][h + 1]);
-            if (add) {
-              const float4 av = Io<TS>::ld4(add + off[bz][by]);
-              v.x += av.x; v.y += av.y; v.z += av.z; v.w += av.w;
-            }
-            Io<TS>::st4(xb + off[bz][by], v);
-          }
-      }
     }
     // sectors (Q), channels (C^T) and the z stage of P^T
     float G[2][9];
@@ -350,6 +451,22 @@ __global__ void __launch_bounds__(kAdjThreads) refine3_adj_sector(Adj3Geom g, Re
         if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, lx1);
       }
     }
+  };
+
+  // Block planes z0-1 .. z1 (coarse plane zb - 1 is finished while plane zb is read),
+  // three planes in flight: a ring of three buffers, unrolled so no buffer is copied.
+  Plane pa, pb, pc;
+  load_plane_y(z0 - 1, pa);
+  load_plane_y(z0, pb);
+  for (int zb = z0 - 1; zb <= z1; zb += 3) {
+    load_plane_y(zb + 2, pc);
+    process(zb, pa);
+    if (zb + 1 > z1) break;
+    load_plane_y(zb + 3, pa);
+    process(zb + 1, pb);
+    if (zb + 2 > z1) break;
+    load_plane_y(zb + 4, pb);
+    process(zb + 2, pc);
   }
 }
 
@@ -366,8 +483,23 @@ bool sector_eligible(const icr_plan* p, int level) {
   return nf < (int64_t(1) << 31);
 }
 
-int64_t pick_chunks(int64_t xy_blocks, int planes, int64_t target) {
-  int64_t n = (target + xy_blocks - 1) / xy_blocks;
+// Workgroups of `kernel` that the device holds at once (occupancy x compute units).
+int64_t resident_workgroups(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1 || cus < 1)
+    return 1024;
+  return int64_t(per_cu) * cus;
+}
+
+// Split `planes` into chunks so that all workgroups of a launch (xy tiles x chunks x
+// batch) fit in one resident round: a partial second round would run almost alone
+// and double the time of the launch, and fewer, longer chunks recompute fewer halo
+// planes. Beyond one round (huge levels or batches) each workgroup takes one chunk.
+int64_t pick_chunks(int64_t xy_blocks, int planes, int64_t batch, int64_t slots) {
+  int64_t n = slots / (xy_blocks * batch);
   if (n < 1) n = 1;
   if (n > planes) n = planes;
   return n;
@@ -387,9 +519,13 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
   g.nfy = p->shapes[level + 1][1];
   g.nfx = p->shapes[level + 1][2];
   const int64_t xy_blocks = (int64_t(g.rows) * g.pairs + 255) / 256;
-  const int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, 2048);
+  static const int64_t slots =
+      resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false>), 256);
+  const int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
   g.zchunk = static_cast<int>((g.nz - 2 + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz - 2 + g.zchunk - 1) / g.zchunk;
+  g.xy_blocks = static_cast<int>(xy_blocks);
+  g.nwg = static_cast<int>(xy_blocks * nchunks);
   for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
     RefineFwdArgs c = a;
     c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
@@ -397,17 +533,18 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
     c.xi = static_cast<const TS*>(a.xi) + b0 * a.xi_bs;
     c.s_out = static_cast<TS*>(a.s_out) + b0 * a.s_out_bs;
     if (a.w) c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
-    const dim3 grid(static_cast<unsigned>(xy_blocks), static_cast<unsigned>(nchunks),
-                    static_cast<unsigned>(c.batch));
-    refine3_fwd_sector<TS><<<grid, 256, 0, st>>>(g, c, k);
+    const dim3 grid(static_cast<unsigned>(g.nwg), static_cast<unsigned>(c.batch));
+    if (a.w) refine3_fwd_sector<TS, true><<<grid, 256, 0, st>>>(g, c, k);
+    else refine3_fwd_sector<TS, false><<<grid, 256, 0, st>>>(g, c, k);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <typename TS>
-hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+template <typename TS, int kTP, int kTR>
+hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  constexpr int kOP = kTP - 2, kOR = kTR - 2;
   const LevelMats& m = p->lev[level];
   Sector3 k;
   for (int t = 0; t < 27; ++t) k.c[t] = m.h_sector[t];
@@ -421,9 +558,13 @@ hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipS
   g.nfy = p->shapes[level + 1][1];
   g.nfx = p->shapes[level + 1][2];
   const int64_t xy_blocks = int64_t(g.xtiles) * ytiles;
-  const int64_t chunks = pick_chunks(xy_blocks, g.nz, 1024);
+  static const int64_t slots =
+      resident_workgroups(reinterpret_cast<const void*>(refine3_adj_sector<TS, false, kTP, kTR>), kTP * kTR);
+  const int64_t chunks = pick_chunks(xy_blocks, g.nz, a.batch < 65535 ? a.batch : 65535, slots);
   g.zchunk = static_cast<int>((g.nz + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz + g.zchunk - 1) / g.zchunk;
+  g.xy_tiles = static_cast<int>(xy_blocks);
+  g.nwg = static_cast<int>(xy_blocks * nchunks);
   for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
     RefineAdjArgs c = a;
     c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
@@ -431,13 +572,21 @@ hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipS
     c.xi_bar = static_cast<TS*>(a.xi_bar) + b0 * a.xi_bar_bs;
     c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
     if (a.add) c.add = static_cast<const TS*>(a.add) + b0 * a.add_bs;
-    const dim3 grid(static_cast<unsigned>(xy_blocks), static_cast<unsigned>(nchunks),
-                    static_cast<unsigned>(c.batch));
-    refine3_adj_sector<TS><<<grid, kAdjThreads, 0, st>>>(g, c, k);
+    const dim3 grid(static_cast<unsigned>(g.nwg), static_cast<unsigned>(c.batch));
+    if (a.add) refine3_adj_sector<TS, true, kTP, kTR><<<grid, kTP * kTR, 0, st>>>(g, c, k);
+    else refine3_adj_sector<TS, false, kTP, kTR><<<grid, kTP * kTR, 0, st>>>(g, c, k);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// 16 block pairs (x) by 32 block rows (y): one 512-thread workgroup per CU at this
+// register budget; measured fastest of 16x16, 32x8, 64x4, 32x16, 16x32 and 64x8 on
+// the 388^3 level.
+template <typename TS>
+hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  return adj_launch_tile<TS, 16, 32>(p, level, a, st);
 }
 
 }  // namespace
