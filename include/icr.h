@@ -192,6 +192,24 @@ icr_status icr_metric_apply(const icr_plan* plan, int64_t batch, const void* w,
                             void* workspace, void* hip_stream);
 
 /*
+ * Conjugate gradients on the metric M = L^T (w * L .) + 1 for `batch` independent right-
+ * hand sides, entirely on the device: step sizes stay in device memory, so the whole
+ * run is enqueued without host round trips. CG is how MGVI/geoVI draw samples (section
+ * "Variational Inference"); this runs exactly `iterations` steps from x_0 = 0 (no early
+ * exit), the i-th step being the textbook update alpha = r.r/p.Mp, x += alpha p,
+ * r -= alpha Mp, p = r + (r'.r'/r.r) p. Dots accumulate in FP64 in a fixed order.
+ *   w, w_batch_stride as for icr_metric_apply.
+ *   b         [batch][n_xi] right-hand sides; x [batch][n_xi] receives the solution.
+ *   residual_norms  optional device array [batch][iterations + 1] (double): |r_k|.
+ *   workspace device scratch of icr_cg_workspace_bytes(plan, batch) bytes, 256-byte aligned.
+ * FP64 and FP32 plans only (ICR_ERR_UNSUPPORTED for BF16 storage).
+ */
+icr_status icr_cg_workspace_bytes(const icr_plan* plan, int64_t batch, int64_t* bytes);
+icr_status icr_cg_metric(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
+                         const void* b, void* x, int32_t iterations, double* residual_norms,
+                         void* workspace, void* hip_stream);
+
+/*
  * One level of the sweep, for callers that pipeline or shard levels themselves
  * (icr_forward and icr_adjoint are these calls in sequence). Strides are elements
  * between consecutive samples and must be >= the level's size.

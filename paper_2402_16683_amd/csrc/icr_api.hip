@@ -154,6 +154,18 @@ icr_status check_call(const icr_plan* p, int64_t batch) {
   return ICR_OK;
 }
 
+// The metric as CG applies it: v -> L^T (w * L v) + v on `batch` samples.
+hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v,
+                         void* out, void* ws, hipStream_t st) {
+  const int el = p->elem_bytes;
+  const int64_t bs = p->n_xi;
+  if (run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), bs, ws, bs, w, w_bs, st) != ICR_OK)
+    return hipErrorLaunchFailure;
+  if (run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), bs, out, ws, bs, v, st) != ICR_OK)
+    return hipErrorLaunchFailure;
+  return hipSuccess;
+}
+
 // Host copies of a stationary level's FP32 matrices and its sector form (the fast
 // kernels take them by value). Synchronous; called at build and after set_refinement.
 icr_status refresh_host_copies(icr_plan* p, int level) {
@@ -456,6 +468,39 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   if (r != ICR_OK) return r;
   return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
                      v, st);
+}
+
+icr_status icr_cg_workspace_bytes(const icr_plan* p, int64_t batch, int64_t* bytes) {
+  icr::clear_error();
+  if (!p || !bytes || batch < 0) return fail(ICR_ERR_INVALID_ARG, "plan or bytes is NULL, or batch < 0");
+  *bytes = icr::cg_workspace_bytes(p, batch);
+  return ICR_OK;
+}
+
+icr_status icr_cg_metric(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                         const void* b, void* x, int32_t iterations, double* residual_norms,
+                         void* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK) return cs;
+  if (p->precision == ICR_BF16_F32ACC) return fail(ICR_ERR_UNSUPPORTED, "CG needs an FP64 or FP32 plan");
+  if (iterations < 0) return fail(ICR_ERR_INVALID_ARG, "iterations must be >= 0");
+  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "CG takes at most 65535 right-hand sides per call");
+  if (batch == 0) return ICR_OK;
+  const int el = p->elem_bytes;
+  if (!w || !b || !x || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(b, el) || !aligned(x, el) || !aligned(w, el) || !aligned(workspace, 256) ||
+      (residual_norms && !aligned(residual_norms, 8)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned (workspace needs 256 bytes)");
+  const size_t nx = size_t(batch) * p->n_xi * el;
+  const size_t nw = size_t(icr::cg_workspace_bytes(p, batch));
+  if (overlaps(b, nx, x, nx) || overlaps(b, nx, workspace, nw) || overlaps(x, nx, workspace, nw))
+    return fail(ICR_ERR_INVALID_ARG, "b, x and workspace overlap");
+  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, b, x, iterations, residual_norms, workspace,
+                             static_cast<hipStream_t>(hip_stream), metric_for_cg));
+  return ICR_OK;
 }
 
 icr_status icr_forward_level(const icr_plan* p, int32_t level, int64_t batch, const void* s_coarse,

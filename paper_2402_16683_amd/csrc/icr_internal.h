@@ -63,6 +63,13 @@ struct LevelMats {
 // FP32 rounding of R itself.
 constexpr double kSectorTolerance = 1e-7;
 
+// conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1
+int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
+hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
+                     void* x, int32_t iterations, double* norms, void* workspace, hipStream_t st,
+                     hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*,
+                                          void*, hipStream_t));
+
 }  // namespace icr
 
 struct icr_plan {
@@ -145,5 +152,12 @@ bool try_refine3_adj_sector(const icr_plan* p, int level, const RefineAdjArgs& a
                             hipError_t* err);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);
+
+// conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1
+int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
+hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
+                     void* x, int32_t iterations, double* norms, void* workspace, hipStream_t st,
+                     hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*,
+                                          void*, hipStream_t));
 
 }  // namespace icr

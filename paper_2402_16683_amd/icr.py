@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_adjoint": [vp, i64, vp, vp, vp, vp],
         "icr_metric_apply": [vp, i64, vp, i64, vp, vp, vp, vp],
         "icr_forward_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
+        "icr_cg_workspace_bytes": [vp, i64, ctypes.POINTER(i64)],
+        "icr_cg_metric": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
         "icr_adjoint_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_plan_destroy": [vp],
     }
@@ -336,6 +338,34 @@ def icr_adjoint_level(plan: Plan, level: int, y_fine, xi_bar_fine, s_bar_coarse,
                                             _ptr(xi_bar_fine), st(xi_bar_fine), _ptr(s_bar_coarse),
                                             st(s_bar_coarse), _stream_handle(stream)))
     return xi_bar_fine
+
+
+def icr_cg_workspace_bytes(plan: Plan, batch: int) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().icr_cg_workspace_bytes(plan.handle, batch, ctypes.byref(out)))
+    return out.value
+
+
+def icr_cg_metric(plan: Plan, w, b, iterations: int, x=None, residual_norms=False, workspace=None,
+                  stream=None):
+    """Solve (L^T W L + 1) x = b by `iterations` CG steps on the device (x_0 = 0).
+
+    Returns x, or (x, norms) with norms[batch][iterations + 1] = |r_k| when asked."""
+    import torch
+    _check_tensor(b, plan, "b")
+    batch = _batch_of(b, plan.info["n_xi"])
+    if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
+        raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
+    w_stride = 0 if w.dim() == 1 else w.shape[-1]
+    if x is None:
+        x = _empty(b.shape, plan)
+    _check_tensor(x, plan, "x")
+    if workspace is None:
+        workspace = torch.empty(icr_cg_workspace_bytes(plan, batch), dtype=torch.uint8, device="cuda")
+    norms = torch.empty((batch, iterations + 1), dtype=torch.float64, device="cuda") if residual_norms else None
+    _check(load_library().icr_cg_metric(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(), x.data_ptr(),
+                                        iterations, _ptr(norms), workspace.data_ptr(), _stream_handle(stream)))
+    return (x, norms) if residual_norms else x
 
 
 def icr_plan_destroy(plan: Plan):
