@@ -1,0 +1,88 @@
+/*
+ * icr_server.h - served ICR: continuous batching of forward / adjoint / metric requests
+ * on one GPU (the serving mode of the ICR library declared in icr.h).
+ *
+ * Requests against registered plans are queued; a worker thread groups pending requests
+ * with the same (plan, op), oldest first, into batches of a power of two up to max_batch,
+ * admits a batch only when its device buffers fit in the server's fixed HBM arena
+ * (first fit), and launches it on a free stream: gather the requests' inputs into a
+ * contiguous batch, run the batched sweep (a hipGraph captured once per (plan, op, batch
+ * size) when use_graphs is set), scatter the outputs, record a completion event. Requests
+ * that arrive while others run are admitted as streams and memory free up, so batches of
+ * different priors overlap on the device. max_batch = 1, n_streams = 1, use_graphs = 0 is
+ * the one-launch-per-request baseline.
+ *
+ * Conventions: as in icr.h (status codes, icr_last_error, caller-owned device buffers).
+ * The server allocates its arena once at creation; nothing is allocated per request
+ * except when a new graph is captured (from the arena). A request's buffers must stay
+ * valid and untouched until icr_server_query reports it done. Results are identical
+ * whether a request runs alone or in a batch (each sample is computed by the same
+ * kernels in the same order).
+ */
+#ifndef ICR_SERVER_H
+#define ICR_SERVER_H
+
+#include <stdint.h>
+
+#include "icr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum icr_op {
+  ICR_OP_FORWARD = 0,  /* in: xi [n_xi]     out: s [n_out]       */
+  ICR_OP_ADJOINT = 1,  /* in: s_bar [n_out] out: xi_bar [n_xi]   */
+  ICR_OP_METRIC = 2    /* in: v [n_xi], w [n_out]  out: [n_xi]   */
+} icr_op;
+
+typedef struct icr_server_config {
+  int64_t hbm_budget_bytes;  /* size of the arena batches and captured graphs live in */
+  int32_t max_batch;         /* 1..64 requests per launch */
+  int32_t n_streams;         /* 1..16 batches in flight at once */
+  int32_t use_graphs;        /* replay captured hipGraphs for the batched sweep */
+  int32_t reserved;          /* must be 0 */
+} icr_server_config;
+
+typedef struct icr_server_statistics {
+  int64_t completed;
+  int64_t pending;
+  int64_t batches;             /* launches */
+  int64_t batched_requests;    /* requests over all launches */
+  int64_t graph_captures;
+  int64_t admissions_deferred; /* batches that had to wait for (or shrink to fit) memory */
+  int64_t arena_bytes;
+  int64_t arena_in_use;
+} icr_server_statistics;
+
+typedef struct icr_server icr_server;
+
+/* Create a server on the current device (arena, streams, worker thread). */
+icr_status icr_server_create(const icr_server_config* cfg, icr_server** out);
+
+/* Register a plan (it must outlive the server); returns its id. */
+icr_status icr_server_register_plan(icr_server* server, const icr_plan* plan, int32_t* plan_id);
+
+/* Queue one request (a single sample). `w` (metric only) is [n_out] in the plan's
+ * arithmetic type. ICR_ERR_OUT_OF_MEMORY if a single request cannot fit the arena. */
+icr_status icr_server_submit(icr_server* server, int32_t plan_id, int32_t op, const void* in, void* out,
+                             const void* w, int64_t* request_id);
+
+/* State of a request; times are host steady-clock seconds (submit, launch of its batch,
+ * observed completion). */
+icr_status icr_server_query(icr_server* server, int64_t request_id, int32_t* done, double* t_submit,
+                            double* t_launch, double* t_done, int32_t* batch_size);
+
+/* Wait until no request is pending or in flight (timeout_s <= 0: no limit). */
+icr_status icr_server_drain(icr_server* server, double timeout_s);
+
+icr_status icr_server_stats(icr_server* server, icr_server_statistics* stats);
+
+/* Stop the worker, wait for in-flight work, free the arena, graphs and streams. */
+icr_status icr_server_destroy(icr_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICR_SERVER_H */

@@ -1,0 +1,622 @@
+// Served ICR: a request server with continuous batching.
+//
+// Callers submit forward / adjoint / metric requests against plans registered with the
+// server; each request brings its own device input and output buffers. A worker thread
+//   1. retires batches whose completion event has fired (records the completion time,
+//      returns their memory to the arena, or marks their captured graph free),
+//   2. forms batches from pending requests with the same (plan, op), oldest first, up to
+//      the largest power of two <= min(pending, max_batch),
+//   3. admits a batch only if its buffers fit in the fixed HBM arena (first fit), and
+//      launches it on a stream with no batch in flight: gather the requests' inputs into a
+//      contiguous batch, run the batched sweep (replaying a hipGraph captured once per
+//      (plan, op, batch size) when graphs are enabled), scatter the outputs, record an event.
+// Requests that arrive while others run join the queue and are admitted as streams and
+// memory free up, so batches of different priors overlap on the device. With
+// max_batch = 1, one stream and no graphs the same server is the one-launch-per-request
+// baseline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "icr_internal.h"
+#include "icr_server.h"
+
+namespace {
+
+constexpr int kMaxBatch = 64;
+constexpr size_t kAlign = 256;
+
+double now_s() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+struct PtrTable {
+  const void* p[kMaxBatch];
+};
+
+// rows[r] (n elements each) <-> contiguous [k][n]; 16-byte vectors when aligned
+__global__ void gather_rows(PtrTable src, void* __restrict__ dst, int64_t bytes_per_row, int vec) {
+  const int r = blockIdx.y;
+  const char* s = static_cast<const char*>(src.p[r]);
+  char* d = static_cast<char*>(dst) + r * bytes_per_row;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (vec) {
+    const int64_t n = bytes_per_row / 16;
+    for (int64_t i = t0; i < n; i += stride)
+      reinterpret_cast<uint4*>(d)[i] = reinterpret_cast<const uint4*>(s)[i];
+  } else {
+    for (int64_t i = t0; i < bytes_per_row; i += stride) d[i] = s[i];
+  }
+}
+
+__global__ void scatter_rows(const void* __restrict__ src, PtrTable dst, int64_t bytes_per_row, int vec) {
+  const int r = blockIdx.y;
+  const char* s = static_cast<const char*>(src) + r * bytes_per_row;
+  char* d = static_cast<char*>(const_cast<void*>(dst.p[r]));
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (vec) {
+    const int64_t n = bytes_per_row / 16;
+    for (int64_t i = t0; i < n; i += stride)
+      reinterpret_cast<uint4*>(d)[i] = reinterpret_cast<const uint4*>(s)[i];
+  } else {
+    for (int64_t i = t0; i < bytes_per_row; i += stride) d[i] = s[i];
+  }
+}
+
+// First-fit allocator over one device arena.
+class Arena {
+ public:
+  bool init(size_t bytes) {
+    if (hipMalloc(&base_, bytes) != hipSuccess) return false;
+    size_ = bytes;
+    free_[0] = bytes;
+    return true;
+  }
+  ~Arena() {
+    if (base_) (void)hipFree(base_);
+  }
+  void* alloc(size_t bytes) {
+    bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_[off] = bytes;
+        in_use_ += bytes;
+        return static_cast<char*>(base_) + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(void* p) {
+    const size_t off = static_cast<char*>(p) - static_cast<char*>(base_);
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t start = off, len = u->second;
+    used_.erase(u);
+    in_use_ -= len;
+    auto next = free_.lower_bound(start);
+    if (next != free_.end() && next->first == start + len) {
+      len += next->second;
+      free_.erase(next);
+    }
+    auto prev = free_.lower_bound(start);
+    if (prev != free_.begin()) {
+      --prev;
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  size_t capacity() const { return size_; }
+  size_t in_use() const { return in_use_; }
+
+ private:
+  void* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  std::map<size_t, size_t> used_;
+};
+
+struct PlanEntry {
+  const icr_plan* plan;
+  int64_t n_xi, n_out;
+  int elem, acc;
+};
+
+struct Request {
+  int32_t plan_id;
+  int32_t op;
+  const void* in;
+  void* out;
+  const void* w;
+  double t_submit = 0.0, t_launch = 0.0, t_done = 0.0;
+  int32_t batch_size = 0;
+  bool done = false;
+};
+
+// Device buffers of one batch: [k][n_in] inputs, [k][n_out_op] outputs, [k][n_out] w,
+// the sweep workspace.
+struct Buffers {
+  void* in = nullptr;
+  void* out = nullptr;
+  void* w = nullptr;
+  void* ws = nullptr;
+  size_t bytes = 0;
+};
+
+struct Graph {
+  hipGraphExec_t exec = nullptr;
+  Buffers buf;
+  bool busy = false;
+  double last_used = 0.0;
+};
+
+struct Batch {
+  std::vector<int64_t> ids;
+  int32_t plan_id = 0, op = 0;
+  int stream = -1;
+  hipEvent_t done = nullptr;
+  Buffers buf;          // owned when no graph is used
+  Graph* graph = nullptr;
+};
+
+}  // namespace
+
+struct icr_server {
+  icr_server_config cfg{};
+  Arena arena;
+  std::vector<PlanEntry> plans;
+  std::unordered_map<int64_t, Request> requests;
+  std::deque<int64_t> pending;
+  std::vector<hipStream_t> streams;
+  std::vector<Batch*> inflight;  // per stream
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::tuple<int, int, int>, std::vector<Graph*>> graphs;
+  int64_t next_id = 1;
+  int64_t completed = 0, batches = 0, batched_requests = 0, graph_captures = 0, admissions_deferred = 0;
+  std::string error;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::atomic<bool> stop{false};
+  std::thread worker;
+  int device = 0;
+};
+
+namespace {
+
+size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int64_t in_elems(const PlanEntry& pe, int op) { return op == ICR_OP_ADJOINT ? pe.n_out : pe.n_xi; }
+int64_t out_elems(const PlanEntry& pe, int op) { return op == ICR_OP_FORWARD ? pe.n_out : pe.n_xi; }
+int64_t ws_elems(const PlanEntry& pe, int op) { return op == ICR_OP_METRIC ? pe.n_xi : pe.n_xi - pe.n_out; }
+
+size_t batch_bytes(const PlanEntry& pe, int op, int k) {
+  size_t b = up(size_t(k) * in_elems(pe, op) * pe.elem) + up(size_t(k) * out_elems(pe, op) * pe.elem) +
+             up(size_t(k) * std::max<int64_t>(ws_elems(pe, op), 1) * pe.elem);
+  if (op == ICR_OP_METRIC) b += up(size_t(k) * pe.n_out * pe.acc);
+  return b;
+}
+
+bool carve(icr_server* s, const PlanEntry& pe, int op, int k, Buffers* b) {
+  const size_t total = batch_bytes(pe, op, k);
+  char* p = static_cast<char*>(s->arena.alloc(total));
+  if (!p) return false;
+  b->bytes = total;
+  b->in = p; p += up(size_t(k) * in_elems(pe, op) * pe.elem);
+  b->out = p; p += up(size_t(k) * out_elems(pe, op) * pe.elem);
+  b->ws = p; p += up(size_t(k) * std::max<int64_t>(ws_elems(pe, op), 1) * pe.elem);
+  b->w = op == ICR_OP_METRIC ? p : nullptr;
+  return true;
+}
+
+// the batched sweep on contiguous buffers
+icr_status sweep(const PlanEntry& pe, int op, int k, const Buffers& b, hipStream_t st) {
+  switch (op) {
+    case ICR_OP_FORWARD: return icr_forward(pe.plan, k, b.in, b.out, b.ws, st);
+    case ICR_OP_ADJOINT: return icr_adjoint(pe.plan, k, b.in, b.out, b.ws, st);
+    default: return icr_metric_apply(pe.plan, k, b.w, pe.n_out, b.in, b.out, b.ws, st);
+  }
+}
+
+hipError_t copy_rows(const std::vector<const void*>& ptrs, void* contiguous, int64_t bytes_per_row, bool gather,
+                     hipStream_t st) {
+  PtrTable t{};
+  bool vec = bytes_per_row % 16 == 0 && (reinterpret_cast<uintptr_t>(contiguous) % 16) == 0;
+  for (size_t r = 0; r < ptrs.size(); ++r) {
+    t.p[r] = ptrs[r];
+    vec = vec && (reinterpret_cast<uintptr_t>(ptrs[r]) % 16) == 0;
+  }
+  const int64_t units = vec ? bytes_per_row / 16 : bytes_per_row;
+  const unsigned gx = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((units + 255) / 256, 1), 1024));
+  const dim3 grid(gx, static_cast<unsigned>(ptrs.size()));
+  if (gather) gather_rows<<<grid, 256, 0, st>>>(t, contiguous, bytes_per_row, vec ? 1 : 0);
+  else scatter_rows<<<grid, 256, 0, st>>>(contiguous, t, bytes_per_row, vec ? 1 : 0);
+  return hipGetLastError();
+}
+
+Graph* find_graph(icr_server* s, const PlanEntry& pe, int plan_id, int op, int k, hipStream_t st, bool* oom) {
+  auto& list = s->graphs[std::make_tuple(plan_id, op, k)];
+  for (Graph* g : list)
+    if (!g->busy) return g;
+  // capture a new instance with its own buffers
+  Graph* g = new Graph;
+  if (!carve(s, pe, op, k, &g->buf)) {
+    // evict idle graphs of other keys, least recently used first
+    std::vector<std::pair<double, std::tuple<int, int, int>>> idle;
+    for (auto& kv : s->graphs)
+      for (Graph* h : kv.second)
+        if (!h->busy) idle.push_back({h->last_used, kv.first});
+    std::sort(idle.begin(), idle.end());
+    for (auto& cand : idle) {
+      auto& l2 = s->graphs[cand.second];
+      for (size_t i = 0; i < l2.size(); ++i) {
+        if (!l2[i]->busy && l2[i]->last_used == cand.first) {
+          (void)hipGraphExecDestroy(l2[i]->exec);
+          s->arena.release(l2[i]->buf.in);
+          delete l2[i];
+          l2.erase(l2.begin() + i);
+          break;
+        }
+      }
+      if (carve(s, pe, op, k, &g->buf)) break;
+    }
+    if (!g->buf.in) {
+      delete g;
+      *oom = true;
+      return nullptr;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    s->arena.release(g->buf.in);
+    delete g;
+    return nullptr;
+  }
+  const icr_status rs = sweep(pe, op, k, g->buf, st);
+  const hipError_t ec = hipStreamEndCapture(st, &graph);
+  if (rs != ICR_OK || ec != hipSuccess || hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    s->arena.release(g->buf.in);
+    delete g;
+    return nullptr;
+  }
+  (void)hipGraphDestroy(graph);
+  ++s->graph_captures;
+  list.push_back(g);
+  return g;
+}
+
+// Launch one batch on stream `si`; returns false if it could not be admitted (memory).
+bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
+  const Request& r0 = s->requests[ids[0]];
+  const PlanEntry& pe = s->plans[r0.plan_id];
+  const int op = r0.op;
+  const int k = static_cast<int>(ids.size());
+  hipStream_t st = s->streams[si];
+  Batch* b = new Batch;
+  b->ids = ids;
+  b->plan_id = r0.plan_id;
+  b->op = op;
+  b->stream = si;
+  Buffers buf;
+  if (s->cfg.use_graphs) {
+    bool oom = false;
+    b->graph = find_graph(s, pe, r0.plan_id, op, k, st, &oom);
+    if (!b->graph) {
+      delete b;
+      if (!oom) s->error = "graph capture failed";
+      return false;
+    }
+    buf = b->graph->buf;
+  } else {
+    if (!carve(s, pe, op, k, &b->buf)) {
+      delete b;
+      return false;
+    }
+    buf = b->buf;
+  }
+  std::vector<const void*> in_ptrs, out_ptrs, w_ptrs;
+  for (int64_t id : ids) {
+    const Request& r = s->requests[id];
+    in_ptrs.push_back(r.in);
+    out_ptrs.push_back(r.out);
+    w_ptrs.push_back(r.w);
+  }
+  hipError_t e = copy_rows(in_ptrs, buf.in, in_elems(pe, op) * pe.elem, true, st);
+  if (e == hipSuccess && op == ICR_OP_METRIC) e = copy_rows(w_ptrs, buf.w, pe.n_out * pe.acc, true, st);
+  if (e == hipSuccess) {
+    if (b->graph) e = hipGraphLaunch(b->graph->exec, st);
+    else if (sweep(pe, op, k, buf, st) != ICR_OK) e = hipErrorLaunchFailure;
+  }
+  if (e == hipSuccess) e = copy_rows(out_ptrs, buf.out, out_elems(pe, op) * pe.elem, false, st);
+  if (s->event_pool.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    s->event_pool.push_back(ev);
+  }
+  b->done = s->event_pool.back();
+  s->event_pool.pop_back();
+  if (e == hipSuccess && b->done) e = hipEventRecord(b->done, st);
+  if (e != hipSuccess) s->error = std::string("batch launch: ") + hipGetErrorString(e);
+  if (b->graph) {
+    b->graph->busy = true;
+    b->graph->last_used = now_s();
+  }
+  const double t = now_s();
+  for (int64_t id : ids) {
+    s->requests[id].t_launch = t;
+    s->requests[id].batch_size = k;
+  }
+  s->inflight[si] = b;
+  ++s->batches;
+  s->batched_requests += k;
+  return true;
+}
+
+void retire(icr_server* s) {
+  for (size_t si = 0; si < s->inflight.size(); ++si) {
+    Batch* b = s->inflight[si];
+    if (!b) continue;
+    if (b->done && hipEventQuery(b->done) == hipErrorNotReady) continue;
+    const double t = now_s();
+    for (int64_t id : b->ids) {
+      Request& r = s->requests[id];
+      r.t_done = t;
+      r.done = true;
+      ++s->completed;
+    }
+    if (b->graph) b->graph->busy = false;
+    else if (b->buf.in) s->arena.release(b->buf.in);
+    if (b->done) s->event_pool.push_back(b->done);
+    delete b;
+    s->inflight[si] = nullptr;
+  }
+}
+
+// Form and launch batches on free streams; oldest pending request first.
+void schedule(icr_server* s) {
+  for (size_t si = 0; si < s->inflight.size() && !s->pending.empty(); ++si) {
+    if (s->inflight[si]) continue;
+    const int64_t head = s->pending.front();
+    const Request& rh = s->requests[head];
+    std::vector<int64_t> ids;
+    for (int64_t id : s->pending) {
+      const Request& r = s->requests[id];
+      if (r.plan_id == rh.plan_id && r.op == rh.op) ids.push_back(id);
+      if (static_cast<int>(ids.size()) >= s->cfg.max_batch) break;
+    }
+    size_t k = 1;
+    while (k * 2 <= ids.size()) k *= 2;
+    ids.resize(k);
+    bool admitted = false;
+    while (!ids.empty()) {
+      if (launch_batch(s, static_cast<int>(si), ids)) {
+        admitted = true;
+        break;
+      }
+      ++s->admissions_deferred;
+      if (ids.size() == 1) break;
+      ids.resize(ids.size() / 2);  // a smaller batch may fit
+    }
+    if (!admitted) break;  // wait for memory to free up; keep arrival order
+    for (int64_t id : ids) {
+      auto it = std::find(s->pending.begin(), s->pending.end(), id);
+      if (it != s->pending.end()) s->pending.erase(it);
+    }
+  }
+}
+
+void worker_loop(icr_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop.load()) {
+    retire(s);
+    schedule(s);
+    bool busy = false;
+    for (Batch* b : s->inflight) busy = busy || b != nullptr;
+    if (!busy && s->pending.empty()) {
+      s->cv.wait_for(lk, std::chrono::milliseconds(2));
+    } else {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+icr_status icr_server_create(const icr_server_config* cfg, icr_server** out) {
+  icr::clear_error();
+  if (!cfg || !out) {
+    icr::set_error("cfg or out is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch || cfg->n_streams < 1 || cfg->n_streams > 16 ||
+      cfg->hbm_budget_bytes < int64_t(kAlign)) {
+    icr::set_error("max_batch must be 1..64, n_streams 1..16, hbm_budget_bytes >= 256");
+    return ICR_ERR_INVALID_ARG;
+  }
+  icr_server* s = new icr_server;
+  s->cfg = *cfg;
+  (void)hipGetDevice(&s->device);
+  if (!s->arena.init(static_cast<size_t>(cfg->hbm_budget_bytes))) {
+    delete s;
+    icr::set_error("could not allocate the server's HBM arena");
+    return ICR_ERR_OUT_OF_MEMORY;
+  }
+  for (int i = 0; i < cfg->n_streams; ++i) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      icr::set_error("hipStreamCreate failed");
+      return ICR_ERR_HIP;
+    }
+    s->streams.push_back(st);
+  }
+  s->inflight.assign(cfg->n_streams, nullptr);
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return ICR_OK;
+}
+
+icr_status icr_server_register_plan(icr_server* s, const icr_plan* plan, int32_t* plan_id) {
+  icr::clear_error();
+  if (!s || !plan || !plan_id) {
+    icr::set_error("server, plan or plan_id is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  PlanEntry pe{plan, plan->n_xi, plan->n_out, plan->elem_bytes, plan->precision == ICR_F64 ? 8 : 4};
+  s->plans.push_back(pe);
+  *plan_id = static_cast<int32_t>(s->plans.size() - 1);
+  return ICR_OK;
+}
+
+icr_status icr_server_submit(icr_server* s, int32_t plan_id, int32_t op, const void* in, void* out,
+                             const void* w, int64_t* request_id) {
+  icr::clear_error();
+  if (!s || !in || !out || !request_id) {
+    icr::set_error("server, in, out or request_id is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  if (op < ICR_OP_FORWARD || op > ICR_OP_METRIC || (op == ICR_OP_METRIC && !w)) {
+    icr::set_error("unknown op, or a metric request without w");
+    return ICR_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (plan_id < 0 || plan_id >= static_cast<int32_t>(s->plans.size())) {
+    icr::set_error("unknown plan_id");
+    return ICR_ERR_INVALID_ARG;
+  }
+  const PlanEntry& pe = s->plans[plan_id];
+  if (batch_bytes(pe, op, 1) > s->arena.capacity()) {
+    icr::set_error("request needs more memory than the server's HBM budget");
+    return ICR_ERR_OUT_OF_MEMORY;
+  }
+  Request r;
+  r.plan_id = plan_id;
+  r.op = op;
+  r.in = in;
+  r.out = out;
+  r.w = w;
+  r.t_submit = now_s();
+  const int64_t id = s->next_id++;
+  s->requests[id] = r;
+  s->pending.push_back(id);
+  *request_id = id;
+  s->cv.notify_one();
+  return ICR_OK;
+}
+
+icr_status icr_server_query(icr_server* s, int64_t request_id, int32_t* done, double* t_submit,
+                            double* t_launch, double* t_done, int32_t* batch_size) {
+  icr::clear_error();
+  if (!s || !done) {
+    icr::set_error("server or done is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(request_id);
+  if (it == s->requests.end()) {
+    icr::set_error("unknown request_id");
+    return ICR_ERR_INVALID_ARG;
+  }
+  const Request& r = it->second;
+  *done = r.done ? 1 : 0;
+  if (t_submit) *t_submit = r.t_submit;
+  if (t_launch) *t_launch = r.t_launch;
+  if (t_done) *t_done = r.t_done;
+  if (batch_size) *batch_size = r.batch_size;
+  return ICR_OK;
+}
+
+icr_status icr_server_drain(icr_server* s, double timeout_s) {
+  icr::clear_error();
+  if (!s) {
+    icr::set_error("server is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  const double t0 = now_s();
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      bool busy = !s->pending.empty();
+      for (Batch* b : s->inflight) busy = busy || b != nullptr;
+      if (!s->error.empty()) {
+        icr::set_error(s->error);
+        return ICR_ERR_HIP;
+      }
+      if (!busy) return ICR_OK;
+    }
+    if (timeout_s > 0 && now_s() - t0 > timeout_s) {
+      icr::set_error("drain timed out");
+      return ICR_ERR_HIP;
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+}
+
+icr_status icr_server_stats(icr_server* s, icr_server_statistics* st) {
+  icr::clear_error();
+  if (!s || !st) {
+    icr::set_error("server or stats is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->completed = s->completed;
+  st->pending = static_cast<int64_t>(s->pending.size());
+  st->batches = s->batches;
+  st->batched_requests = s->batched_requests;
+  st->graph_captures = s->graph_captures;
+  st->admissions_deferred = s->admissions_deferred;
+  st->arena_bytes = static_cast<int64_t>(s->arena.capacity());
+  st->arena_in_use = static_cast<int64_t>(s->arena.in_use());
+  return ICR_OK;
+}
+
+icr_status icr_server_destroy(icr_server* s) {
+  icr::clear_error();
+  if (!s) return ICR_OK;
+  s->stop.store(true);
+  s->cv.notify_one();
+  if (s->worker.joinable()) s->worker.join();
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (Batch* b : s->inflight) delete b;
+  for (auto& kv : s->graphs)
+    for (Graph* g : kv.second) {
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      delete g;
+    }
+  for (hipEvent_t e : s->event_pool)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+  return ICR_OK;
+}
+
+}  // extern "C"

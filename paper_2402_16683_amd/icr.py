@@ -106,11 +106,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     return lib
 
 
-def declared_functions(header: str = HEADER) -> list[str]:
-    """Names of the functions include/icr.h declares."""
-    text = open(header).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(icr_[a-z0-9_]+)\s*\(", text)))
+def declared_functions(headers=None) -> list[str]:
+    """Names of the functions the headers under include/ declare."""
+    import glob
+    headers = headers or sorted(glob.glob(os.path.join(os.path.dirname(HEADER), "*.h")))
+    names = set()
+    for h in headers:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(icr_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def icr_last_error() -> str:

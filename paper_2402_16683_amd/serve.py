@@ -1,0 +1,231 @@
+"""Served ICR: binding of the request server (include/icr_server.h) and a driver that
+plays a Poisson stream of mixed forward / adjoint / metric requests through it.
+
+The server (C++ in libicr.so) does the batching, admission and launching; this module
+only marshals arguments, draws the synthetic request stream and summarises latencies.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import icr as B
+
+OPS = {"forward": 0, "adjoint": 1, "metric": 2}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("completed", "pending", "batches", "batched_requests",
+                                              "graph_captures", "admissions_deferred", "arena_bytes",
+                                              "arena_in_use")]
+
+
+def _lib():
+    lib = B.load_library()
+    if not getattr(lib, "_server_bound", False):
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sigs = {
+            "icr_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
+            "icr_server_register_plan": [vp, vp, ctypes.POINTER(i32)],
+            "icr_server_submit": [vp, i32, i32, vp, vp, vp, ctypes.POINTER(i64)],
+            "icr_server_query": [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(dbl), ctypes.POINTER(i32)],
+            "icr_server_drain": [vp, dbl],
+            "icr_server_stats": [vp, ctypes.POINTER(ServerStats)],
+            "icr_server_destroy": [vp],
+        }
+        for name, args in sigs.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib._server_bound = True
+    return lib
+
+
+class Server:
+    """An icr_server: continuous batching of ICR requests on the current device."""
+
+    def __init__(self, hbm_budget_bytes: int, max_batch: int = 16, n_streams: int = 4, use_graphs: bool = True):
+        cfg = ServerConfig(hbm_budget_bytes, max_batch, n_streams, 1 if use_graphs else 0, 0)
+        self.handle = ctypes.c_void_p()
+        B._check(_lib().icr_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
+        self.plans = []
+
+    def register(self, plan: B.Plan) -> int:
+        pid = ctypes.c_int32()
+        B._check(_lib().icr_server_register_plan(self.handle, plan.handle, ctypes.byref(pid)))
+        self.plans.append(plan)
+        return pid.value
+
+    def submit(self, plan_id: int, op: str, inp, out, w=None) -> int:
+        rid = ctypes.c_int64()
+        B._check(_lib().icr_server_submit(self.handle, plan_id, OPS[op], inp.data_ptr(), out.data_ptr(),
+                                          None if w is None else w.data_ptr(), ctypes.byref(rid)))
+        return rid.value
+
+    def query(self, rid: int):
+        done, ts, tl, td, bs = (ctypes.c_int32(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double(),
+                                ctypes.c_int32())
+        B._check(_lib().icr_server_query(self.handle, rid, ctypes.byref(done), ctypes.byref(ts), ctypes.byref(tl),
+                                         ctypes.byref(td), ctypes.byref(bs)))
+        return bool(done.value), ts.value, tl.value, td.value, bs.value
+
+    def drain(self, timeout_s: float = 0.0):
+        B._check(_lib().icr_server_drain(self.handle, timeout_s))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        B._check(_lib().icr_server_stats(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            B._check(_lib().icr_server_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- workload
+
+@dataclass
+class Prior:
+    ndim: int
+    n0: int
+    depth: int
+    kernel: str
+    length: float
+
+    @property
+    def delta0(self) -> float:
+        # final-grid extent 1: delta_L = 1 / n_L, delta_0 = 2^L / n_L
+        n = self.n0
+        for _ in range(self.depth):
+            n = 2 * (n - 2)
+        return 2.0 ** self.depth / n
+
+
+def draw_priors(n_priors: int, seed: int) -> list:
+    """A pool of priors mixing 1-D (level-0 8-64, 4-10 levels), 2-D (8-32, 4-7 levels) and
+    3-D (6-12, 3-5 levels) with Matern-3/2 or -5/2 kernels and log-uniform length scales in
+    [0.05, 0.3]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_priors):
+        d = 1 + i % 3
+        lo, hi, dlo, dhi = {1: (8, 64, 4, 10), 2: (8, 32, 4, 7), 3: (6, 12, 3, 5)}[d]
+        out.append(Prior(d, int(rng.integers(lo, hi + 1)), int(rng.integers(dlo, dhi + 1)),
+                         "matern32" if rng.random() < 0.5 else "matern52",
+                         float(math.exp(rng.uniform(math.log(0.05), math.log(0.3))))))
+    return out
+
+
+@dataclass
+class Stream:
+    arrivals: np.ndarray   # seconds from the start
+    prior: np.ndarray      # index into the pool
+    op: np.ndarray         # 0 forward, 1 adjoint, 2 metric
+    seeds: np.ndarray
+
+
+def draw_stream(n_requests: int, n_priors: int, rate: float, seed: int) -> Stream:
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_requests) if rate > 0 else np.zeros(n_requests)
+    return Stream(np.cumsum(gaps), rng.integers(0, n_priors, n_requests), rng.integers(0, 3, n_requests),
+                  rng.integers(0, 2 ** 31, n_requests))
+
+
+@dataclass
+class Slots:
+    """Per-prior ring of request buffers (inputs drawn once, outputs per slot)."""
+    xi: list = field(default_factory=list)
+    ybar: list = field(default_factory=list)
+    w: list = field(default_factory=list)
+    out_s: list = field(default_factory=list)
+    out_x: list = field(default_factory=list)
+    last: list = field(default_factory=list)
+
+
+def build_pool(priors, precision="f32", slots=8, seed=11):
+    import torch
+    plans, pool = [], []
+    for k, pr in enumerate(priors):
+        cfg = B.make_config(pr.ndim, (pr.n0,) * pr.ndim, pr.depth, (pr.delta0,) * pr.ndim, kernel=pr.kernel,
+                            length=pr.length, precision=precision)
+        plan = B.icr_build_matrices(cfg)
+        plans.append(plan)
+        n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed + k)
+        sl = Slots()
+        for _ in range(slots):
+            sl.xi.append(torch.randn(n_xi, device="cuda", generator=g).to(plan.dtype))
+            sl.ybar.append(torch.randn(n_out, device="cuda", generator=g).to(plan.dtype))
+            sl.w.append((torch.rand(n_out, device="cuda", generator=g) < 0.7).to(plan.acc_dtype) * 100.0)
+            sl.out_s.append(torch.empty(n_out, dtype=plan.dtype, device="cuda"))
+            sl.out_x.append(torch.empty(n_xi, dtype=plan.dtype, device="cuda"))
+            sl.last.append(None)
+        pool.append(sl)
+    torch.cuda.synchronize()
+    return plans, pool
+
+
+def run_stream(server: Server, plans, pool, stream: Stream, pace: bool = True):
+    """Submit the stream at its arrival times; returns per-request latency (s), batch size
+    and the wall time of the run."""
+    ids_for = [server.register(p) for p in plans]
+    names = ("forward", "adjoint", "metric")
+    n = len(stream.op)
+    rids = np.zeros(n, dtype=np.int64)
+    lag = np.zeros(n)
+    counters = [0] * len(plans)
+    t0 = time.perf_counter()
+    for i in range(n):
+        k = int(stream.prior[i])
+        sl = pool[k]
+        j = counters[k] % len(sl.xi)
+        counters[k] += 1
+        if sl.last[j] is not None:       # the slot's previous request must be finished
+            while not server.query(sl.last[j])[0]:
+                time.sleep(20e-6)
+        if pace:
+            target = t0 + stream.arrivals[i]
+            while time.perf_counter() < target:
+                pass
+        op = names[int(stream.op[i])]
+        if op == "forward":
+            rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_s[j])
+        elif op == "adjoint":
+            rid = server.submit(ids_for[k], op, sl.ybar[j], sl.out_x[j])
+        else:
+            rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_x[j], sl.w[j])
+        lag[i] = max(0.0, time.perf_counter() - (t0 + stream.arrivals[i])) if pace else 0.0
+        sl.last[j] = rid
+        rids[i] = rid
+    server.drain(600.0)
+    wall = time.perf_counter() - t0
+    lat = np.zeros(n)
+    bs = np.zeros(n, dtype=np.int64)
+    for i, rid in enumerate(rids):
+        done, ts, _, td, b = server.query(int(rid))
+        lat[i] = (td - ts) + lag[i]
+        bs[i] = b
+    return lat, bs, wall
+
+
+def fine_pixels(plans, stream: Stream) -> int:
+    return int(sum(plans[int(k)].info["n_out"] for k in stream.prior))

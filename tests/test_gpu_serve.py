@@ -1,0 +1,139 @@
+"""Served mode: continuous batching must not change any result.
+
+Each request's output from the server (batched with others, replayed hipGraphs, several
+streams in flight, admission under a memory budget) is compared with the same request
+computed alone by a direct batch-1 call. Every sample is computed by the same kernels in
+the same order whatever the batch, so the comparison is bitwise. Graph replays are
+checked over two rounds with eager work and synchronisation in between.
+"""
+
+import numpy as np
+import pytest
+
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+POOL = [
+    C.case(1, (20,), 5, (0.05,), "matern32", 0.2, name="s1"),
+    C.case(2, (12, 12), 4, (0.03, 0.03), "matern52", 0.15, name="s2"),
+    C.case(3, (8, 8, 8), 3, (0.06, 0.06, 0.06), "matern52", 0.2, name="s3"),
+    C.case(3, (7, 9, 8), 2, (0.05, 0.06, 0.07), "matern32", 0.3, name="s4"),
+    C.case(2, (9, 10), 3, (0.04, 0.05), "matern32", 0.1, precision="bf16", name="s5"),
+]
+
+
+def _plans():
+    return [C.gpu_plan(c) for c in POOL]
+
+
+def _requests(plans, n, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        k = int(rng.integers(0, len(plans)))
+        op = ("forward", "adjoint", "metric")[int(rng.integers(0, 3))]
+        p = plans[k]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed * 100003 + i)
+        n_in = p.info["n_out"] if op == "adjoint" else p.info["n_xi"]
+        n_out = p.info["n_out"] if op == "forward" else p.info["n_xi"]
+        inp = torch.randn(n_in, device="cuda", generator=g).to(p.dtype)
+        w = (torch.rand(p.info["n_out"], device="cuda", generator=g) < 0.7).to(p.acc_dtype) * 100.0
+        reqs.append(dict(k=k, op=op, inp=inp, w=w, out=torch.full((n_out,), float("nan"), dtype=p.dtype,
+                                                                  device="cuda")))
+    return reqs
+
+
+def _alone(plan, r):
+    from paper_2402_16683_amd import icr as B
+    if r["op"] == "forward":
+        return B.icr_forward(plan, r["inp"][None])[0]
+    if r["op"] == "adjoint":
+        return B.icr_adjoint(plan, r["inp"][None])[0]
+    return B.icr_metric_apply(plan, r["w"], r["inp"][None])[0]
+
+
+def _serve(server, plans, reqs):
+    ids = [server.register(p) for p in plans]
+    rids = []
+    for r in reqs:
+        rids.append(server.submit(ids[r["k"]], r["op"], r["inp"], r["out"], r["w"] if r["op"] == "metric" else None))
+    server.drain(120.0)
+    return [server.query(rid) for rid in rids]
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_results_in_the_mix_equal_results_alone(graphs):
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    server = Server(hbm_budget_bytes=1 << 30, max_batch=8, n_streams=4, use_graphs=graphs)
+    for rnd in range(2):
+        reqs = _requests(plans, 150, seed=rnd + 1)
+        info = _serve(server, plans, reqs)
+        assert all(q[0] for q in info)
+        torch.cuda.synchronize()
+        for r in reqs:
+            alone = _alone(plans[r["k"]], r)
+            torch.cuda.synchronize()
+            assert torch.equal(r["out"], alone), (r["k"], r["op"])
+    st = server.stats()
+    assert st["completed"] == 300 and st["pending"] == 0
+    assert st["batches"] < 300                     # requests were batched
+    if graphs:
+        assert 0 < st["graph_captures"] <= st["batches"]
+    server.close()
+
+
+def test_admission_under_a_tight_budget():
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    from paper_2402_16683_amd import icr as B
+    plans = _plans()
+    biggest = max(p.info["n_xi"] * 4 * 4 for p in plans)   # about two metric requests of the largest prior
+    server = Server(hbm_budget_bytes=2 * biggest, max_batch=8, n_streams=4, use_graphs=False)
+    reqs = _requests(plans, 80, seed=7)
+    info = _serve(server, plans, reqs)
+    assert all(q[0] for q in info)
+    st = server.stats()
+    assert st["admissions_deferred"] > 0 and st["arena_in_use"] == 0
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(plans[r["k"]], r))
+    # a request that can never fit is refused at submission
+    tiny = Server(hbm_budget_bytes=4096, max_batch=4, n_streams=1, use_graphs=False)
+    pid = tiny.register(plans[2])
+    with pytest.raises(B.ICRError) as e:
+        tiny.submit(pid, "forward", reqs[0]["inp"], reqs[0]["out"])
+    assert e.value.status == 4
+    tiny.close()
+    server.close()
+
+
+def test_plain_mode_runs_one_request_per_launch():
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    server = Server(hbm_budget_bytes=1 << 28, max_batch=1, n_streams=1, use_graphs=False)
+    reqs = _requests(plans, 40, seed=9)
+    info = _serve(server, plans, reqs)
+    assert all(q[0] and q[4] == 1 for q in info)
+    assert server.stats()["batches"] == 40
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(plans[r["k"]], r))
+    server.close()
+
+
+def test_poisson_stream_driver_reports_latencies():
+    from paper_2402_16683_amd import serve as S
+    priors = S.draw_priors(6, seed=5)
+    for pr in priors:                      # keep the test small: shallow copies of the mix
+        pr.depth = min(pr.depth, 3 if pr.ndim == 3 else 4)
+    plans, pool = S.build_pool(priors, slots=4)
+    stream = S.draw_stream(200, len(priors), rate=20000.0, seed=3)
+    server = S.Server(hbm_budget_bytes=1 << 30, max_batch=8, n_streams=4, use_graphs=True)
+    lat, bs, wall = S.run_stream(server, plans, pool, stream)
+    assert np.all(lat > 0) and np.all(bs >= 1) and wall > 0
+    assert server.stats()["completed"] == 200
+    server.close()
