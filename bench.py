@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--levels", action="store_true", help="also time every level's kernels")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the served-mode stream (0: skip the served measurement)")
+    ap.add_argument("--serve-priors", type=int, default=24)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -100,6 +103,55 @@ def cpu_baseline(wl: dict, quiet: bool):
     return {"value": model.out_size / dt, "unit": "fine px/s", "cores": 1, "kind": "oracle",
             "sample": f"one sample of the full workload ({'x'.join(map(str, model.shapes[-1]))} final "
                       f"pixels), forward + adjoint, numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
+    """Mixed 1-D/2-D/3-D forward/adjoint/metric requests on a pool of priors: the
+    one-launch-per-request capacity, then a Poisson stream at 0.8x that rate through the
+    served form (continuous batching, hipGraphs, 4 streams) and through the plain form."""
+    import torch
+
+    from paper_2402_16683_amd import serve as S
+    budget = 8 << 30
+    priors = S.draw_priors(n_priors, seed=5)
+    t0 = time.perf_counter()
+    plans, pool = S.build_pool(priors, slots=8)
+    build_s = time.perf_counter() - t0
+    log(f"served: {n_priors} priors built in {build_s:.1f} s", quiet)
+    base = S.draw_stream(n_requests, n_priors, rate=0.0, seed=6)
+    plain = S.Server(budget, max_batch=1, n_streams=1, use_graphs=False)
+    pid = S.register_all(plain, plans)
+    S.run_stream(plain, pid, pool, S.draw_stream(min(200, n_requests), n_priors, 0.0, seed=7), pace=False)
+    _, _, wall = S.run_stream(plain, pid, pool, base, pace=False)
+    capacity = n_requests / wall
+    rate = 0.8 * capacity
+    stream = S.draw_stream(n_requests, n_priors, rate=rate, seed=6)
+    out = {"requests": n_requests, "priors": n_priors, "plain_capacity_req_per_s": capacity,
+           "arrival_rate_req_per_s": rate, "hbm_budget_bytes": budget, "build_s": build_s}
+    px = S.fine_pixels(plans, stream)
+    servers = {"served": S.Server(budget, max_batch=16, n_streams=4, use_graphs=True), "plain": plain}
+    for name, srv in servers.items():
+        ids = pid if srv is plain else S.register_all(srv, plans)
+        if srv is not plain:   # capture this server's graphs before timing
+            S.run_stream(srv, ids, pool, S.draw_stream(min(500, n_requests), n_priors, 0.0, seed=8), pace=False)
+        before = srv.stats()
+        lat, bs, wall = S.run_stream(srv, ids, pool, stream)
+        st = srv.stats()
+        out[name] = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "fine_px_per_s": px / wall, "requests_per_s": n_requests / wall,
+                     "mean_batch": float(bs.mean()), "launches": st["batches"] - before["batches"],
+                     "graph_captures": st["graph_captures"]}
+        log(f"served: {name} p50 {out[name]['p50_ms']:.3f} ms p99 {out[name]['p99_ms']:.3f} ms "
+            f"{out[name]['fine_px_per_s']:.3g} px/s", quiet)
+    # saturation: the stream back to back
+    sat = servers["served"]
+    _, bs, wall = S.run_stream(sat, S.register_all(sat, plans), pool, base, pace=False)
+    out["served_saturated_req_per_s"] = n_requests / wall
+    for srv in servers.values():
+        srv.close()
+    del plans, pool
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -264,6 +316,8 @@ def main():
     }
     if levels is not None:
         out["levels"] = levels
+    if args.serve_requests > 0 and not args.copy_probe:
+        out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.quiet)
     print(json.dumps(out), flush=True)

@@ -184,15 +184,21 @@ def build_pool(priors, precision="f32", slots=8, seed=11):
     return plans, pool
 
 
-def run_stream(server: Server, plans, pool, stream: Stream, pace: bool = True):
+def register_all(server: Server, plans) -> list:
+    return [server.register(p) for p in plans]
+
+
+def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True):
     """Submit the stream at its arrival times; returns per-request latency (s), batch size
-    and the wall time of the run."""
-    ids_for = [server.register(p) for p in plans]
+    and the wall time of the run. `plan_ids` are the pool's ids in this server."""
+    ids_for = list(plan_ids)
     names = ("forward", "adjoint", "metric")
     n = len(stream.op)
     rids = np.zeros(n, dtype=np.int64)
     lag = np.zeros(n)
-    counters = [0] * len(plans)
+    for sl in pool:
+        sl.last = [None] * len(sl.xi)
+    counters = [0] * len(pool)
     t0 = time.perf_counter()
     for i in range(n):
         k = int(stream.prior[i])

@@ -133,7 +133,7 @@ def test_poisson_stream_driver_reports_latencies():
     plans, pool = S.build_pool(priors, slots=4)
     stream = S.draw_stream(200, len(priors), rate=20000.0, seed=3)
     server = S.Server(hbm_budget_bytes=1 << 30, max_batch=8, n_streams=4, use_graphs=True)
-    lat, bs, wall = S.run_stream(server, plans, pool, stream)
+    lat, bs, wall = S.run_stream(server, S.register_all(server, plans), pool, stream)
     assert np.all(lat > 0) and np.all(bs >= 1) and wall > 0
     assert server.stats()["completed"] == 200
     server.close()
