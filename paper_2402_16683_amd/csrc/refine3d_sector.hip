@@ -18,9 +18,10 @@
 //
 // Adjoint (a gather, no atomics): each block's cotangent y is mapped to sectors
 // (Q), scaled per channel (C^T) and sent back through P^T one axis at a time. The
-// z stage accumulates in registers while marching along z; the y and x stages need
-// the neighbouring blocks' contributions, which are exchanged through LDS inside a
-// tile of block pairs whose outer ring (halo) is recomputed by each tile.
+// z stage accumulates in registers while marching along z; the x stage takes the
+// neighbouring pairs' contributions from the adjacent lanes (DPP), the y stage from
+// the neighbouring rows through LDS, inside a tile of block pairs whose outer ring
+// (halo) is recomputed by each tile.
 // Every coarse cotangent is summed by one thread in a fixed order.
 #include "icr_internal.h"
 
@@ -33,6 +34,9 @@ template <> struct Io<float> {
   static __device__ __forceinline__ float2 ld2(const float* p) { return *reinterpret_cast<const float2*>(p); }
   static __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
   static __device__ __forceinline__ void st1(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ void st2(float* p, float a, float b) {
+    *reinterpret_cast<float2*>(p) = make_float2(a, b);
+  }
 };
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
   return static_cast<uint32_t>(f32_to_bf16(a)) | (static_cast<uint32_t>(f32_to_bf16(b)) << 16);
@@ -51,6 +55,9 @@ template <> struct Io<bf16_t> {
     *reinterpret_cast<uint2*>(p) = make_uint2(pack_bf16(v.x, v.y), pack_bf16(v.z, v.w));
   }
   static __device__ __forceinline__ void st1(bf16_t* p, float v) { *p = f32_to_bf16(v); }
+  static __device__ __forceinline__ void st2(bf16_t* p, float a, float b) {
+    *reinterpret_cast<uint32_t*>(p) = pack_bf16(a, b);
+  }
 };
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup w runs on XCD w % 8),
@@ -90,6 +97,15 @@ template <>
 __device__ __forceinline__ void st4_stream<bf16_t>(bf16_t* p, float4 v) {
   const nt_u2 w = {pack_bf16(v.x, v.y), pack_bf16(v.z, v.w)};
   __builtin_nontemporal_store(w, reinterpret_cast<nt_u2*>(p));
+}
+
+// Cross-lane moves inside rows of 16 lanes (DPP row shifts); lanes whose source falls
+// outside their row read 0.
+__device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
 }
 
 // sector coefficients C (27, already divided by 8) and the lower sqrtD packed by rows
@@ -185,7 +201,9 @@ struct Fwd3Geom {
 // branch, so the next step's loads stay in flight while the current step computes.
 template <typename TS, bool kW>
 __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, Sector3 k) {
-  const int tile = xcd_tile(blockIdx.x, g.nwg);
+  // plane-major order (no XCD renumbering): the forward's only shared data is the
+  // small coarse level, and this order measured faster on the 388^3 level
+  const int tile = static_cast<int>(blockIdx.x);
   const int tid = (tile % g.xy_blocks) * 256 + threadIdx.x;
   if (tid >= g.rows * g.pairs) return;
   const int yi = tid / g.pairs;
@@ -294,11 +312,11 @@ struct Adj3Geom {
 // Tile: kTP block pairs (x) by kTR block rows (y), halo ring included.
 template <typename TS, bool kAdd, int kTP, int kTR>
 __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, RefineAdjArgs a, Sector3 k) {
-  constexpr int kOP = kTP - 2;     // owned pairs per tile
+  constexpr int kOP = kTP - 2;     // owned pairs per tile (first and last lane of a row are halo)
   constexpr int kOR = kTR - 2;     // owned rows per tile
   constexpr int kAdjThreads = kTP * kTR;
-  __shared__ float ldy[12][kAdjThreads];
-  __shared__ float ldx[2][kAdjThreads];
+  static_assert(kTP == 16, "x neighbours are exchanged inside 16-lane DPP rows");
+  __shared__ float ldy[2][8][kAdjThreads];   // double-buffered by coarse-plane parity
   const int t = threadIdx.x;
   const int i = t % kTP, j = t / kTP;
   const int tile = xcd_tile(blockIdx.x, g.nwg);
@@ -417,38 +435,44 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
     }
     if (zb >= z0 + 1) {  // coarse plane zb - 1 is complete in G (uniform branch)
       const int zc = zb - 1;
-      float Cy[2][3];
+      const int buf = zc & 1;
+      // x stage: the pair sums its coarse columns x = 2P+1, 2P+2 from its own blocks and
+      // the outer column of each neighbouring pair (the adjacent lanes of this 16-lane
+      // row, read with DPP row shifts); the first and last pairs also sum the edge
+      // columns x = 0 and x = nx-1.
+      float H[4][3];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+      for (int ty = 0; ty < 3; ++ty) {
+        const float e0 = G[0][ty * 3], m0 = G[0][ty * 3 + 1], o0 = G[0][ty * 3 + 2];
+        const float e1 = G[1][ty * 3], m1 = G[1][ty * 3 + 1], o1 = G[1][ty * 3 + 2];
+        const float l0 = e0 - o0, r0 = e0 + o0;   // to the columns left / right of block 0
+        const float l1 = e1 - o1, r1 = e1 + o1;   // and of block 1
+        const float from_left = dpp_from_left(r1);    // x = 2P+1 from block 2P (left pair)
+        const float from_right = dpp_from_right(l0);  // x = 2P+2 from block 2P+3 (right pair)
+        H[0][ty] = from_left + m0 + l1;              // x = 2P+1
+        H[1][ty] = r0 + m1 + from_right;             // x = 2P+2
+        H[2][ty] = P == 0 ? l0 : 0.0f;               // x = 0
+        H[3][ty] = P == g.pairs - 1 ? r1 : 0.0f;     // x = nx-1
+      }
+      // y stage through LDS; the buffer alternates with the plane, so one barrier per
+      // plane separates this plane's writes from its reads and from the next plane's writes
+      float Cy[4];
 #pragma unroll
-        for (int tx = 0; tx < 3; ++tx) {
-          Cy[p][tx] = G[p][3 + tx];
-          ldy[p * 6 + tx][t] = G[p][tx] + G[p][6 + tx];      // to row yb + 1
-          ldy[p * 6 + 3 + tx][t] = G[p][tx] - G[p][6 + tx];  // to row yb - 1
-        }
+      for (int c = 0; c < 4; ++c) {
+        Cy[c] = H[c][1];
+        ldy[buf][c][t] = H[c][0] + H[c][2];      // to row yb + 1
+        ldy[buf][4 + c][t] = H[c][0] - H[c][2];  // to row yb - 1
+      }
       __syncthreads();
-      float Hy[2][3];
+      if (owner) {  // owner rows have both neighbour rows inside the tile
+        float sv[4];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int tx = 0; tx < 3; ++tx) {
-          const float up = j > 0 ? ldy[p * 6 + tx][t - kTP] : 0.0f;
-          const float dn = j < kTR - 1 ? ldy[p * 6 + 3 + tx][t + kTP] : 0.0f;
-          Hy[p][tx] = Cy[p][tx] + up + dn;
-        }
-      const float lx0 = Hy[0][0] + Hy[0][2], rx0 = Hy[0][0] - Hy[0][2];
-      const float lx1 = Hy[1][0] + Hy[1][2], rx1 = Hy[1][0] - Hy[1][2];
-      ldx[0][t] = lx1;  // to the pair on the right (its first block's left neighbour)
-      ldx[1][t] = rx0;  // to the pair on the left
-      __syncthreads();
-      if (owner) {
-        const float left = i > 0 ? ldx[0][t - 1] : 0.0f;
-        const float right = i < kTP - 1 ? ldx[1][t + 1] : 0.0f;
+        for (int c = 0; c < 4; ++c) sv[c] = Cy[c] + ldy[buf][c][t - kTP] + ldy[buf][4 + c][t + kTP];
         TS* row = sb + (static_cast<int64_t>(zc) * g.ny + yb) * g.nx;
-        Io<TS>::st1(row + 2 * P + 1, left + Hy[0][1] + rx1);
-        Io<TS>::st1(row + 2 * P + 2, lx0 + Hy[1][1] + right);
-        if (P == 0) Io<TS>::st1(row, rx0);
-        if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, lx1);
+        Io<TS>::st1(row + 2 * P + 1, sv[0]);
+        Io<TS>::st1(row + 2 * P + 2, sv[1]);
+        if (P == 0) Io<TS>::st1(row, sv[2]);
+        if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, sv[3]);
       }
     }
   };
@@ -544,7 +568,7 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
 
 template <typename TS, int kTP, int kTR>
 hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
-  constexpr int kOP = kTP - 2, kOR = kTR - 2;
+  constexpr int kOP = kTP - 2, kOR = kTR - 2;  // as in the kernel
   const LevelMats& m = p->lev[level];
   Sector3 k;
   for (int t = 0; t < 27; ++t) k.c[t] = m.h_sector[t];
