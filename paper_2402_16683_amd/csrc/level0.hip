@@ -1,8 +1,9 @@
 // Level 0 of the ICR sweep: s_0 = L00 xi_0 with L00 the lower Cholesky factor of
 // the kernel over the coarsest grid, and its transpose xi_bar_0 = L00^T s_bar_0
 // (stored as the row-major upper factor U00 = L00^T so both directions stream
-// rows). One wavefront per output element and sample; lanes stride the row and
-// the partial sums are combined by a fixed butterfly, so results are reproducible.
+// rows). One wavefront per output element and sample; lanes stride the row with
+// several loads in flight, and the partial sums are combined in a fixed order (pairwise,
+// then a butterfly across lanes), so results are reproducible.
 #include "icr_internal.h"
 
 namespace icr {
@@ -29,13 +30,35 @@ __global__ void __launch_bounds__(256) level0_kernel(const typename Acc<TS>::typ
   const TA* m = mat + row * n;
   const int64_t j0 = kLower ? 0 : row;
   const int64_t j1 = kLower ? row + 1 : n;
-  TA acc = 0;
-  for (int64_t j = j0 + lane; j < j1; j += 64) acc += m[j] * load_acc(in + j);
-  acc = wave_sum(acc);
+  // kU independent partial sums so kU loads of the row are in flight at once; a lane
+  // past the end of the row reads an in-bounds element and adds zero, so no load sits
+  // in a divergent branch
+  constexpr int kU = 8;
+  TA part[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) part[u] = 0;
+  for (int64_t base = j0; base < j1; base += 64 * kU) {
+    TA mv[kU], xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t j = base + u * 64 + lane;
+      const int64_t jc = j < j1 ? j : j0;
+      mv[u] = m[jc];
+      xv[u] = load_acc(in + jc);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) part[u] += (base + u * 64 + lane < j1 ? mv[u] : TA(0)) * xv[u];
+  }
+#pragma unroll
+  for (int w = kU / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) part[u] += part[u + w];
+  const TA acc = wave_sum(part[0]);
   if (lane == 0) {
-    if (kLower && a.w) acc *= static_cast<const TA*>(a.w)[b * a.w_bs + row];
-    if (!kLower && a.add) acc += load_acc(static_cast<const TS*>(a.add) + b * a.add_bs + row);
-    store_acc(static_cast<TS*>(a.out) + b * a.out_bs + row, acc);
+    TA r = acc;
+    if (kLower && a.w) r *= static_cast<const TA*>(a.w)[b * a.w_bs + row];
+    if (!kLower && a.add) r += load_acc(static_cast<const TS*>(a.add) + b * a.add_bs + row);
+    store_acc(static_cast<TS*>(a.out) + b * a.out_bs + row, r);
   }
 }
 

@@ -99,13 +99,14 @@ __device__ __forceinline__ void st4_stream<bf16_t>(bf16_t* p, float4 v) {
   __builtin_nontemporal_store(w, reinterpret_cast<nt_u2*>(p));
 }
 
-// Cross-lane moves inside rows of 16 lanes (DPP row shifts); lanes whose source falls
-// outside their row read 0.
+// Cross-lane moves over the whole wavefront (DPP wave shifts); lane 0 (from_left) and
+// lane 63 (from_right) read 0. A tile row of lanes may be any divisor of 64: the lanes
+// at the ends of a row are halo lanes, so what crosses a row boundary is never used.
 __device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+1
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
 // sector coefficients C (27, already divided by 8) and the lower sqrtD packed by rows
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   constexpr int kOP = kTP - 2;     // owned pairs per tile (first and last lane of a row are halo)
   constexpr int kOR = kTR - 2;     // owned rows per tile
   constexpr int kAdjThreads = kTP * kTR;
-  static_assert(kTP == 16, "x neighbours are exchanged inside 16-lane DPP rows");
+  static_assert(64 % kTP == 0, "tile rows of lanes must not straddle wavefronts");
   __shared__ float ldy[2][8][kAdjThreads];   // double-buffered by coarse-plane parity
   const int t = threadIdx.x;
   const int i = t % kTP, j = t / kTP;
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
             const float4 av = pl.v[bz][by];
             v.x += av.x; v.y += av.y; v.z += av.z; v.w += av.w;
           }
-          st4_stream<TS>(xb + fine_off(zb, bz, by), v);
+          Io<TS>::st4(xb + fine_off(zb, bz, by), v);
         }
     }
     // sectors (Q), channels (C^T) and the z stage of P^T
@@ -437,9 +438,8 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
       const int zc = zb - 1;
       const int buf = zc & 1;
       // x stage: the pair sums its coarse columns x = 2P+1, 2P+2 from its own blocks and
-      // the outer column of each neighbouring pair (the adjacent lanes of this 16-lane
-      // row, read with DPP row shifts); the first and last pairs also sum the edge
-      // columns x = 0 and x = nx-1.
+      // the outer column of each neighbouring pair (the adjacent lanes, read with DPP
+      // wave shifts); the first and last pairs also sum the edge columns x = 0 and nx-1.
       float H[4][3];
 #pragma unroll
       for (int ty = 0; ty < 3; ++ty) {
@@ -478,7 +478,8 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   };
 
   // Block planes z0-1 .. z1 (coarse plane zb - 1 is finished while plane zb is read),
-  // three planes in flight: a ring of three buffers, unrolled so no buffer is copied.
+  // three planes in flight: a ring of three buffers, unrolled so no buffer is copied
+  // (measured faster than deeper rings or an indexed ring array).
   Plane pa, pb, pc;
   load_plane_y(z0 - 1, pa);
   load_plane_y(z0, pb);

@@ -2,12 +2,17 @@
 
     python profile_summary.py trace <dir>               # --kernel-trace --stats run
     python profile_summary.py counters <dir> <counter>  # --pmc run (FETCH_SIZE / WRITE_SIZE)
+    python profile_summary.py traffic <fetch_dir> <write_dir> <workload> <precision>
 
 `trace` groups dispatches by kernel and grid (so the levels of one kernel are told
 apart) and reports count and average / min / max duration in microseconds.
 `counters` reports the counter per dispatch group in KiB, and the ratio of that
 counter to the known bytes of the copy probe (a 256 MiB device-to-device tensor copy
 that `bench.py --copy-probe` runs), which calibrates bytes per counter unit.
+`traffic` combines a FETCH_SIZE run and a WRITE_SIZE run of `bench.py --copy-probe`
+into HBM bytes per launch of the last-level forward and adjoint sweep kernels (the
+largest dispatch group of each), prints the summary and records it in
+profiles/traffic.json under the current kernel-source digest, where bench.py reads it.
 """
 
 from __future__ import annotations
@@ -64,6 +69,60 @@ def trace(d: str):
         print(f"{name[:70]:70s} {grid:>18s} {len(v):6d} {sum(v) / len(v):10.2f} {min(v):10.2f} {max(v):10.2f}")
 
 
+def _counter_groups(d: str, counter: str):
+    path = _find(d, "counter_collection.csv")
+    groups = defaultdict(list)
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            groups[(short_name(row["Kernel_Name"]), row.get("Grid_Size", "?"))].append(float(row["Counter_Value"]))
+    return path, {k: sum(v) / len(v) for k, v in groups.items()}, {k: len(v) for k, v in groups.items()}
+
+
+def traffic(fetch_dir: str, write_dir: str, workload: str, precision: str):
+    import json
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from bench import PROFILES, kernel_source_digest
+    from workloads import WORKLOADS
+    wl = WORKLOADS[workload]
+    n = [int(v) for v in wl["shape0"]]
+    shapes = [n]
+    for _ in range(wl["depth"]):
+        n = [2 * (v - 2) for v in n]
+        shapes.append(n)
+    el = {"f32": 4, "bf16": 2}[precision]
+    prod = lambda v: int(__import__("math").prod(v))
+    alg = wl.get("batch", 1) * (2 * prod(shapes[-1]) + prod(shapes[-2])) * el
+    _, fetch, _ = _counter_groups(fetch_dir, "FETCH_SIZE")
+    _, write, calls = _counter_groups(write_dir, "WRITE_SIZE")
+    f_probe = max(v for (nm, g), v in fetch.items() if "copy" in nm.lower())
+    w_probe = max(v for (nm, g), v in write.items() if "copy" in nm.lower())
+    f_scale = COPY_PROBE_BYTES / f_probe          # bytes read per reported unit
+    w_scale = COPY_PROBE_BYTES / w_probe          # bytes written per reported unit
+    digest = kernel_source_digest()
+    path = os.path.join(PROFILES, "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    print(f"# kernel sources digest: {digest}")
+    print(f"# Calibration: the 256 MiB copy probe reads {f_probe:.0f} (FETCH_SIZE) for {COPY_PROBE_BYTES} bytes "
+          f"read (factor {f_scale / 1024:.3f}) and {w_probe:.0f} (WRITE_SIZE) for {COPY_PROBE_BYTES} bytes written "
+          f"(factor {w_scale / 1024:.3f}); the kernels' counters are scaled by these factors.")
+    for tag, kname in (("refine_adj_last", "refine3_adj_sector"), ("refine_fwd_last", "refine3_fwd_sector")):
+        cands = [(v, k) for k, v in fetch.items() if k[0].startswith(kname) and k in write]
+        if not cands:
+            continue
+        _, key = max(cands)
+        rd, wr = fetch[key] * f_scale, write[key] * w_scale
+        print(f"{tag:16s} {key[0]} grid {key[1]:>8s} ({calls[key]} launches): FETCH {fetch[key]:9.0f} KiB -> "
+              f"{rd / 1e6:6.1f} MB read; WRITE {write[key]:9.0f} KiB -> {wr / 1e6:6.1f} MB written; total "
+              f"{(rd + wr) / 1e6:6.1f} MB vs algorithmic {alg / 1e6:.1f} MB ({(rd + wr) / alg:.2f}x)")
+        rec[f"{tag}:{workload}:{precision}"] = {"source_digest": digest, "hbm_bytes_per_launch": rd + wr,
+                                               "read_bytes": rd, "write_bytes": wr, "alg_bytes": alg}
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+
+
 def counters(d: str, counter: str):
     path = _find(d, "counter_collection.csv")
     groups = defaultdict(list)
@@ -89,5 +148,7 @@ if __name__ == "__main__":
         trace(sys.argv[2])
     elif len(sys.argv) >= 4 and sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:6])
     else:
         raise SystemExit(__doc__)
