@@ -6,6 +6,7 @@
 #include <new>
 #include <string>
 
+#include "host_checks.h"
 #include "icr_internal.h"
 
 namespace icr {
@@ -79,12 +80,6 @@ icr_status check_config(const icr_config* c) {
 }
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
-
-bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
-  const char* pa = static_cast<const char*>(a);
-  const char* pb = static_cast<const char*>(b);
-  return na && nb && pa < pb + nb && pb < pa + na;
-}
 
 bool aligned(const void* p, int el) { return (reinterpret_cast<uintptr_t>(p) % el) == 0; }
 
@@ -421,7 +416,7 @@ icr_status icr_forward(const icr_plan* p, int64_t batch, const void* xi, void* s
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
   const size_t nx = size_t(batch) * p->n_xi * el, ns = size_t(batch) * p->n_out * el;
   const size_t nw = p->depth > 0 ? size_t(batch) * (p->n_xi - p->n_out) * el : 0;
-  if (overlaps(xi, nx, s, ns) || overlaps(xi, nx, workspace, nw) || overlaps(s, ns, workspace, nw))
+  if (icr::overlaps(xi, nx, s, ns) || icr::overlaps(xi, nx, workspace, nw) || icr::overlaps(s, ns, workspace, nw))
     return fail(ICR_ERR_INVALID_ARG, "xi, s and workspace overlap");
   return run_forward(p, batch, xi, s, p->n_out, workspace, p->n_xi - p->n_out, nullptr, 0,
                      static_cast<hipStream_t>(hip_stream));
@@ -438,8 +433,8 @@ icr_status icr_adjoint(const icr_plan* p, int64_t batch, const void* s_bar, void
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
   const size_t nx = size_t(batch) * p->n_xi * el, ns = size_t(batch) * p->n_out * el;
   const size_t nw = p->depth > 0 ? size_t(batch) * (p->n_xi - p->n_out) * el : 0;
-  if (overlaps(xi_bar, nx, s_bar, ns) || overlaps(xi_bar, nx, workspace, nw) ||
-      overlaps(s_bar, ns, workspace, nw))
+  if (icr::overlaps(xi_bar, nx, s_bar, ns) || icr::overlaps(xi_bar, nx, workspace, nw) ||
+      icr::overlaps(s_bar, ns, workspace, nw))
     return fail(ICR_ERR_INVALID_ARG, "s_bar, xi_bar and workspace overlap");
   return run_adjoint(p, batch, s_bar, p->n_out, xi_bar, workspace, p->n_xi - p->n_out, nullptr,
                      static_cast<hipStream_t>(hip_stream));
@@ -458,7 +453,7 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   if (!aligned(v, el) || !aligned(out, el) || !aligned(workspace, el) || !aligned(w, ab))
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
   const size_t nx = size_t(batch) * p->n_xi * el;
-  if (overlaps(v, nx, out, nx) || overlaps(v, nx, workspace, nx) || overlaps(out, nx, workspace, nx))
+  if (icr::overlaps(v, nx, out, nx) || icr::overlaps(v, nx, workspace, nx) || icr::overlaps(out, nx, workspace, nx))
     return fail(ICR_ERR_INVALID_ARG, "v, out and workspace overlap");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int64_t ws_bs = p->n_xi;
@@ -496,7 +491,7 @@ icr_status icr_cg_metric(const icr_plan* p, int64_t batch, const void* w, int64_
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned (workspace needs 256 bytes)");
   const size_t nx = size_t(batch) * p->n_xi * el;
   const size_t nw = size_t(icr::cg_workspace_bytes(p, batch));
-  if (overlaps(b, nx, x, nx) || overlaps(b, nx, workspace, nw) || overlaps(x, nx, workspace, nw))
+  if (icr::overlaps(b, nx, x, nx) || icr::overlaps(b, nx, workspace, nw) || icr::overlaps(x, nx, workspace, nw))
     return fail(ICR_ERR_INVALID_ARG, "b, x and workspace overlap");
   ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, b, x, iterations, residual_norms, workspace,
                              static_cast<hipStream_t>(hip_stream), metric_for_cg));
@@ -519,9 +514,9 @@ icr_status icr_forward_level(const icr_plan* p, int32_t level, int64_t batch, co
     return fail(ICR_ERR_INVALID_ARG, "stride smaller than the level size");
   if (!aligned(xi_fine, el) || !aligned(s_fine, el) || (s_coarse && !aligned(s_coarse, el)))
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
-  const size_t bx = size_t((batch - 1) * xi_stride + nf) * el, bf = size_t((batch - 1) * fine_stride + nf) * el;
-  const size_t bc = level >= 0 ? size_t((batch - 1) * coarse_stride + nc) * el : 0;
-  if (overlaps(s_fine, bf, xi_fine, bx) || overlaps(s_fine, bf, s_coarse, bc))
+  if (icr::overlaps_batched(s_fine, fine_stride * el, nf * el, xi_fine, xi_stride * el, nf * el, batch) ||
+      (level >= 0 &&
+       icr::overlaps_batched(s_fine, fine_stride * el, nf * el, s_coarse, coarse_stride * el, nc * el, batch)))
     return fail(ICR_ERR_INVALID_ARG, "s_fine overlaps an input");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (level < 0) {
@@ -550,10 +545,10 @@ icr_status icr_adjoint_level(const icr_plan* p, int32_t level, int64_t batch, co
     return fail(ICR_ERR_INVALID_ARG, "stride smaller than the level size");
   if (!aligned(y_fine, el) || !aligned(xi_bar_fine, el) || (s_bar_coarse && !aligned(s_bar_coarse, el)))
     return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
-  const size_t by = size_t((batch - 1) * y_stride + nf) * el, bx = size_t((batch - 1) * xi_bar_stride + nf) * el;
-  const size_t bc = level >= 0 ? size_t((batch - 1) * coarse_stride + nc) * el : 0;
-  if (overlaps(xi_bar_fine, bx, y_fine, by) || overlaps(s_bar_coarse, bc, y_fine, by) ||
-      overlaps(s_bar_coarse, bc, xi_bar_fine, bx))
+  const int64_t sy = y_stride * el, sx = xi_bar_stride * el, sc = coarse_stride * el;
+  if (icr::overlaps_batched(xi_bar_fine, sx, nf * el, y_fine, sy, nf * el, batch) ||
+      (level >= 0 && (icr::overlaps_batched(s_bar_coarse, sc, nc * el, y_fine, sy, nf * el, batch) ||
+                      icr::overlaps_batched(s_bar_coarse, sc, nc * el, xi_bar_fine, sx, nf * el, batch))))
     return fail(ICR_ERR_INVALID_ARG, "buffers overlap");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (level < 0) {

@@ -102,3 +102,44 @@ def test_large_batch_is_split_across_launches():
     torch.cuda.synchronize()
     rms, _ = C.rel_errors(C.to_numpy(s), model.forward(C.stored_values(xi, "f32")))
     assert rms <= 1e-5
+
+
+def test_level_calls_take_interleaved_slices_of_one_workspace():
+    """Per-level views of one [batch][W] workspace interleave without sharing a byte; the
+    level calls accept them and compute what separate buffers give. A view that shares
+    one element with an input is rejected before any launch."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = C.case(3, (6, 6, 6), 2, (0.1, 0.1, 0.1), "matern52", 0.3, name="lvl_3d")
+    plan = C.gpu_plan(c)
+    info, offs = plan.info, plan.info["level_offsets"]
+    nb = 3
+    xi = C.to_device(W.standard_normal(info["n_xi"], seed=21, batch=nb), plan)
+    ws = torch.zeros((nb, info["n_xi"]), dtype=torch.float32, device="cuda")
+    B.icr_forward_level(plan, -1, None, xi[:, :offs[1]], ws[:, :offs[1]])
+    B.icr_forward_level(plan, 0, ws[:, :offs[1]], xi[:, offs[1]:offs[2]], ws[:, offs[1]:offs[2]])
+    sep_in = ws[:, :offs[1]].clone()
+    sep_out = torch.zeros((nb, offs[2] - offs[1]), dtype=torch.float32, device="cuda")
+    B.icr_forward_level(plan, 0, sep_in, xi[:, offs[1]:offs[2]], sep_out)
+    torch.cuda.synchronize()
+    assert torch.equal(ws[:, offs[1]:offs[2]], sep_out)
+    # adjoint level with the coarse cotangent and the fine cotangent in one workspace
+    ya = torch.randn((nb, info["n_xi"]), dtype=torch.float32, device="cuda")
+    xb = torch.zeros((nb, offs[2] - offs[1]), dtype=torch.float32, device="cuda")
+    y_sep = ya[:, offs[1]:offs[2]].clone()
+    B.icr_adjoint_level(plan, 0, ya[:, offs[1]:offs[2]], xb, ya[:, :offs[1]])
+    xb_sep = torch.zeros_like(xb)
+    sbar_sep = torch.zeros((nb, offs[1]), dtype=torch.float32, device="cuda")
+    B.icr_adjoint_level(plan, 0, y_sep, xb_sep, sbar_sep)
+    torch.cuda.synchronize()
+    assert torch.equal(xb, xb_sep) and torch.equal(ya[:, :offs[1]], sbar_sep)
+    lib = B.load_library()
+    before = ws.clone()
+    n1 = offs[2] - offs[1]
+    st = ctypes.c_int64
+    rc = lib.icr_forward_level(plan.handle, 0, nb, ctypes.c_void_p(ws.data_ptr()), st(info["n_xi"]),
+                               ctypes.c_void_p(xi[:, offs[1]:].data_ptr()), st(info["n_xi"]),
+                               ctypes.c_void_p(ws.data_ptr() + 4 * (offs[1] - 1)), st(info["n_xi"]), None)
+    assert rc == 1 and "overlap" in B.icr_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(ws, before) and n1 > 0
