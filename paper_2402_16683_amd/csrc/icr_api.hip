@@ -195,6 +195,7 @@ hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& 
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (try_refine3_adj_sector(p, level, a, st, &e)) return e;
+  if (try_refine2_adj(p, level, a, st, &e)) return e;
   return launch_refine_adj_generic(p, level, a, st);
 }
 }  // namespace icr

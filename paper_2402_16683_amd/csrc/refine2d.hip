@@ -1,0 +1,225 @@
+// 2-D refinement level adjoint with the dense 4 x 9 R and lower 4 x 4 sqrtD of a
+// stationary level, FP32 arithmetic with FP32 or bfloat16 storage.
+//
+// The transpose of the forward block map s_{l+1}[2(c-1)+b] = sum_w R[b,w] s_l[c+w] +
+// sum_{b'} sqrtD[b,b'] xi_{l+1}[2(c-1)+b'] is, per coarse pixel p (a gather, no atomics)
+//   s_bar_l[p]            = sum_{w, c = p - w interior} sum_b R[b,w] y[2(c-1)+b],
+//   xi_bar_{l+1}[2(p-1)+b'] = sum_{b >= b'} sqrtD[b,b'] y[2(p-1)+b]       (p interior).
+// Each block c forms its nine window contributions u[w] = sum_b R[b,w] y_c[b] once.
+// A lane owns two neighbouring blocks along x (so the four fine values of a pair's
+// fine row are one 16-byte vector) and marches along y: the wy = -1, 0, +1 parts are
+// accumulated in registers row by row, and the wx = -1, +1 parts of the neighbouring
+// pairs come from the adjacent lanes through DPP wave shifts. A wavefront covers 62
+// pairs; its first and last lanes recompute the neighbouring strips' edge pairs.
+// There is no LDS and no barrier; each coarse cotangent is summed by one lane in a
+// fixed order, so results are bitwise reproducible.
+#include "icr_internal.h"
+#include "sweep_io.h"
+
+namespace icr {
+namespace {
+
+using namespace sweep;
+
+struct Mat2 {
+  float r[36];  // R[b][w], b = (by, bx), w = (wy, wx), lexicographic with the last axis fastest
+  float s[10];  // lower sqrtD by rows: s[c (c + 1) / 2 + c']
+};
+
+struct Adj2Geom {
+  int ny, nx;   // coarse shape
+  int pairs;    // (nx - 2) / 2 block pairs per row
+  int strips;   // wavefront strips along x
+  int ychunk;   // coarse rows per wavefront
+  int nfx;      // fine row length
+  int waves;    // wavefronts per sample
+};
+
+constexpr int kLanes = 64;
+constexpr int kOwnedPairs = kLanes - 2;  // the first and last lanes are halo
+constexpr int kWavesPerGroup = 4;
+
+__host__ __device__ __forceinline__ int sd2(int c, int cp) { return c * (c + 1) / 2 + cp; }
+
+template <typename TS, bool kAdd>
+__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom g, RefineAdjArgs a, Mat2 m) {
+  const int lane = threadIdx.x % kLanes;
+  const int wave = blockIdx.x * kWavesPerGroup + threadIdx.x / kLanes;
+  if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
+  const int strip = wave % g.strips, chunk = wave / g.strips;
+  const int P = strip * kOwnedPairs + lane - 1;  // blocks x = 2P+1, 2P+2
+  const bool pair_ok = P >= 0 && P < g.pairs;
+  const bool owner = lane >= 1 && lane <= kOwnedPairs && pair_ok;
+  const int y0 = chunk * g.ychunk;
+  const int y1 = min(y0 + g.ychunk, g.ny);
+  const int64_t b = blockIdx.y;
+  const TS* y = static_cast<const TS*>(a.y) + b * a.y_bs;
+  TS* xb = static_cast<TS*>(a.xi_bar) + b * a.xi_bar_bs;
+  TS* sb = static_cast<TS*>(a.s_bar) + b * a.s_bar_bs;
+  const TS* add = kAdd ? static_cast<const TS*>(a.add) + b * a.add_bs : nullptr;
+  // loads use clamped (in-bounds) block coordinates; blocks outside the interior are
+  // zeroed after the load, so no load sits under a branch
+  const int Pc = min(max(P, 0), g.pairs - 1);
+  auto fine_off = [&](int yb, int by) { return static_cast<int64_t>(2 * (yb - 1) + by) * g.nfx + 4 * Pc; };
+
+  struct Row {
+    float4 r[2];  // cotangent of the pair's fine rows 2(yb-1) and 2(yb-1)+1
+    float4 v[2];  // metric: values added to xi_bar (kAdd)
+  };
+  auto load_row = [&](int yb, Row& rw) {
+    const int yc = min(max(yb, 1), g.ny - 2);
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      rw.r[by] = Io<TS>::ld4(y + fine_off(yc, by));
+      if (kAdd) rw.v[by] = Io<TS>::ld4(add + fine_off(yc, by));
+    }
+  };
+
+  float A0[2][3], A1[2][3];  // partial coarse cotangents of rows yb-1 and yb, per block and wx
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) { A0[p][x] = 0.0f; A1[p][x] = 0.0f; }
+
+  auto process = [&](int yb, const Row& rw) {
+    const bool ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
+    float yv[2][4];  // [block of the pair][by * 2 + bx]
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const float4 r = rw.r[by];
+      yv[0][by * 2] = ok ? r.x : 0.0f;
+      yv[0][by * 2 + 1] = ok ? r.y : 0.0f;
+      yv[1][by * 2] = ok ? r.z : 0.0f;
+      yv[1][by * 2 + 1] = ok ? r.w : 0.0f;
+    }
+    if (ok && owner && yb >= y0 && yb < y1) {
+      float xo[2][4];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int cp = 0; cp < 4; ++cp) {
+          float v = 0.0f;
+#pragma unroll
+          for (int c = cp; c < 4; ++c) v = fmaf(m.s[sd2(c, cp)], yv[p][c], v);
+          xo[p][cp] = v;
+        }
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        float4 v = make_float4(xo[0][by * 2], xo[0][by * 2 + 1], xo[1][by * 2], xo[1][by * 2 + 1]);
+        if (kAdd) {
+          const float4 av = rw.v[by];
+          v.x += av.x; v.y += av.y; v.z += av.z; v.w += av.w;
+        }
+        Io<TS>::st4(xb + fine_off(yb, by), v);
+      }
+    }
+    // window contributions, then the y march: row yb-1 is complete after this block row
+    float G[2][3];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float u[9];
+#pragma unroll
+      for (int w = 0; w < 9; ++w) {
+        float v = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v = fmaf(m.r[c * 9 + w], yv[p][c], v);
+        u[w] = v;
+      }
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        G[p][x] = A0[p][x] + u[x];       // wy = -1: coarse row yb - 1
+        A0[p][x] = A1[p][x] + u[3 + x];  // wy =  0: coarse row yb
+        A1[p][x] = u[6 + x];             // wy = +1: coarse row yb + 1
+      }
+    }
+    if (yb >= y0 + 1) {  // uniform over the wavefront
+      // column 2P+1 takes block 2P+1 at wx = 0, block 2P+2 at wx = -1 and block 2P (the
+      // left lane's second block) at wx = +1; column 2P+2 symmetrically
+      const float from_left = dpp_from_left(G[1][2]);
+      const float from_right = dpp_from_right(G[0][0]);
+      if (owner) {
+        TS* row = sb + static_cast<int64_t>(yb - 1) * g.nx;
+        Io<TS>::st1(row + 2 * P + 1, from_left + G[0][1] + G[1][0]);
+        Io<TS>::st1(row + 2 * P + 2, G[0][2] + G[1][1] + from_right);
+        if (P == 0) Io<TS>::st1(row, G[0][0]);
+        if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, G[1][2]);
+      }
+    }
+  };
+
+  // block rows y0-1 .. y1, two rows in flight: a ring of three buffers, unrolled so no
+  // buffer is copied
+  Row ra, rb, rc;
+  load_row(y0 - 1, ra);
+  load_row(y0, rb);
+  for (int yb = y0 - 1; yb <= y1; yb += 3) {
+    load_row(yb + 2, rc);
+    process(yb, ra);
+    if (yb + 1 > y1) break;
+    load_row(yb + 3, ra);
+    process(yb + 1, rb);
+    if (yb + 2 > y1) break;
+    load_row(yb + 4, rb);
+    process(yb + 2, rc);
+  }
+}
+
+bool aligned2(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
+
+template <typename TS>
+hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  const LevelMats& lm = p->lev[level];
+  Mat2 m;
+  for (int t = 0; t < 36; ++t) m.r[t] = lm.h_r[t];
+  for (int c = 0; c < 4; ++c)
+    for (int cp = 0; cp <= c; ++cp) m.s[sd2(c, cp)] = lm.h_s[c * 4 + cp];
+  Adj2Geom g;
+  g.ny = p->shapes[level][1];
+  g.nx = p->shapes[level][2];
+  g.pairs = (g.nx - 2) / 2;
+  g.strips = (g.pairs + kOwnedPairs - 1) / kOwnedPairs;
+  g.nfx = p->shapes[level + 1][2];
+  // enough wavefronts to keep every SIMD busy (about 8 per SIMD over 1024 SIMDs), in
+  // chunks of at least 8 rows so the recomputed halo rows stay a small share
+  const int64_t batch = a.batch < 65535 ? a.batch : 65535;
+  const int64_t target = 8192;
+  int64_t chunks = target / (int64_t(g.strips) * batch);
+  chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (g.ny + 7) / 8));
+  g.ychunk = static_cast<int>((g.ny + chunks - 1) / chunks);
+  const int nchunks = (g.ny + g.ychunk - 1) / g.ychunk;
+  g.waves = g.strips * nchunks;
+  const unsigned groups = static_cast<unsigned>((g.waves + kWavesPerGroup - 1) / kWavesPerGroup);
+  for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
+    RefineAdjArgs c = a;
+    c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
+    c.y = static_cast<const TS*>(a.y) + b0 * a.y_bs;
+    c.xi_bar = static_cast<TS*>(a.xi_bar) + b0 * a.xi_bar_bs;
+    c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
+    if (a.add) c.add = static_cast<const TS*>(a.add) + b0 * a.add_bs;
+    const dim3 grid(groups, static_cast<unsigned>(c.batch));
+    if (a.add) refine2_adj<TS, true><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    else refine2_adj<TS, false><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// Stationary 2-D levels in FP32 arithmetic with an even coarse row length, vector-aligned
+// fine rows and batch strides; everything else takes the generic kernels.
+bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err) {
+  if (p->ndim != 2 || p->charted || p->precision == ICR_F64) return false;
+  const int nx = p->shapes[level][2];
+  if (nx % 2 != 0 || nx < 4) return false;
+  const int64_t nf = int64_t(p->shapes[level + 1][1]) * p->shapes[level + 1][2];
+  if (nf >= (int64_t(1) << 31)) return false;
+  const int vec = 4 * p->elem_bytes;
+  if (!aligned2(a.y, vec) || !aligned2(a.xi_bar, vec) || (a.add && !aligned2(a.add, vec))) return false;
+  if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;
+  *err = p->precision == ICR_F32 ? adj2_launch<float>(p, level, a, st) : adj2_launch<bf16_t>(p, level, a, st);
+  return true;
+}
+
+}  // namespace icr

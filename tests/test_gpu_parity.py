@@ -32,6 +32,10 @@ CASES = [
     C.from_workload("icr3d_m52_10to388", depth=2, precision="f64", name="3d_m52_10to28_f64"),
     C.case(3, (5, 7, 6), 2, (0.1, 0.12, 0.09), "matern32", 0.3, batch=2, name="3d_ragged_f32"),
     C.case(2, (9, 5), 3, (0.05, 0.07), "matern12", 0.2, precision="f64", name="2d_ragged_m12_f64"),
+    # odd rows, even row length at every level: the 2-D fast adjoint on all levels
+    C.case(2, (11, 8), 4, (0.03, 0.035), "matern52", 0.15, batch=3, name="2d_ragged_m52_f32"),
+    # odd row length at level 0 (generic kernel), even above (fast adjoint)
+    C.case(2, (8, 9), 4, (0.04, 0.03), "matern32", 0.2, batch=2, precision="bf16", name="2d_ragged_m32_bf16"),
     C.case(1, (7,), 4, (0.1,), "sqexp", 0.4, batch=4, name="1d_se_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=3, name="2d_chart_24to164_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=2, precision="f64", name="2d_chart_24to84_f64"),
