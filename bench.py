@@ -47,9 +47,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--levels", action="store_true", help="also time every level's kernels")
-    ap.add_argument("--serve-requests", type=int, default=2000,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests in the served-mode stream (0: skip the served measurement)")
     ap.add_argument("--serve-priors", type=int, default=24)
+    ap.add_argument("--cg-iters", type=int, default=None,
+                    help="CG iterations on the metric (default: 200 for a charted workload, else none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -107,8 +109,10 @@ def cpu_baseline(wl: dict, quiet: bool):
 
 def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     """Mixed 1-D/2-D/3-D forward/adjoint/metric requests on a pool of priors: the
-    one-launch-per-request capacity, then a Poisson stream at 0.8x that rate through the
-    served form (continuous batching, hipGraphs, 4 streams) and through the plain form."""
+    one-launch-per-request capacity first, then Poisson streams at 0.5, 0.8 and 1.2x that
+    rate through the served form (continuous batching, hipGraphs, 4 streams, 8 GB
+    arena) and through the plain form; the served form once more under a 256 MB arena,
+    and back to back for its saturated rate."""
     import torch
 
     from paper_2402_16683_amd import serve as S
@@ -124,33 +128,89 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     S.run_stream(plain, pid, pool, S.draw_stream(min(200, n_requests), n_priors, 0.0, seed=7), pace=False)
     _, _, wall = S.run_stream(plain, pid, pool, base, pace=False)
     capacity = n_requests / wall
-    rate = 0.8 * capacity
-    stream = S.draw_stream(n_requests, n_priors, rate=rate, seed=6)
     out = {"requests": n_requests, "priors": n_priors, "plain_capacity_req_per_s": capacity,
-           "arrival_rate_req_per_s": rate, "hbm_budget_bytes": budget, "build_s": build_s}
-    px = S.fine_pixels(plans, stream)
-    servers = {"served": S.Server(budget, max_batch=16, n_streams=4, use_graphs=True), "plain": plain}
-    for name, srv in servers.items():
-        ids = pid if srv is plain else S.register_all(srv, plans)
-        if srv is not plain:   # capture this server's graphs before timing
-            S.run_stream(srv, ids, pool, S.draw_stream(min(500, n_requests), n_priors, 0.0, seed=8), pace=False)
+           "hbm_budget_bytes": budget, "build_s": build_s}
+    servers = {"served": S.Server(budget, max_batch=16, n_streams=4, use_graphs=True), "plain": plain,
+               "served_256MB": S.Server(256 << 20, max_batch=16, n_streams=4, use_graphs=True)}
+    ids = {"plain": pid}
+    for name in ("served", "served_256MB"):   # capture each server's graphs before timing
+        ids[name] = S.register_all(servers[name], plans)
+        S.run_stream(servers[name], ids[name], pool, S.draw_stream(min(500, n_requests), n_priors, 0.0, seed=8),
+                     pace=False)
+
+    def one(name, stream):
+        srv = servers[name]
         before = srv.stats()
-        lat, bs, wall = S.run_stream(srv, ids, pool, stream)
+        lat, bs, wall = S.run_stream(srv, ids[name], pool, stream)
         st = srv.stats()
-        out[name] = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                     "fine_px_per_s": px / wall, "requests_per_s": n_requests / wall,
-                     "mean_batch": float(bs.mean()), "launches": st["batches"] - before["batches"],
-                     "graph_captures": st["graph_captures"]}
-        log(f"served: {name} p50 {out[name]['p50_ms']:.3f} ms p99 {out[name]['p99_ms']:.3f} ms "
-            f"{out[name]['fine_px_per_s']:.3g} px/s", quiet)
+        ok = ~np.isnan(lat)
+        r = {"p50_ms": float(np.percentile(lat[ok], 50) * 1e3), "p99_ms": float(np.percentile(lat[ok], 99) * 1e3),
+             "fine_px_per_s": S.fine_pixels(plans, stream, ok) / wall, "requests_per_s": int(ok.sum()) / wall,
+             "mean_batch": float(bs[ok].mean()), "launches": st["batches"] - before["batches"],
+             "admissions_deferred": st["admissions_deferred"] - before["admissions_deferred"],
+             "refused": int((~ok).sum())}
+        log(f"served: {name} at {stream_rate:.0f} req/s: p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms "
+            f"{r['fine_px_per_s']:.3g} px/s, mean batch {r['mean_batch']:.2f}", quiet)
+        return r
+
+    out["rates"] = []
+    for factor in (0.5, 0.8, 1.2):
+        stream_rate = factor * capacity
+        stream = S.draw_stream(n_requests, n_priors, rate=stream_rate, seed=6)
+        row = {"factor": factor, "arrival_rate_req_per_s": stream_rate,
+               "served": one("served", stream), "plain": one("plain", stream)}
+        if factor == 0.8:
+            row["served_256MB"] = one("served_256MB", stream)
+            out.update({"arrival_rate_req_per_s": stream_rate, "served": row["served"], "plain": row["plain"],
+                        "served_256MB": row["served_256MB"]})
+        out["rates"].append(row)
     # saturation: the stream back to back
     sat = servers["served"]
-    _, bs, wall = S.run_stream(sat, S.register_all(sat, plans), pool, base, pace=False)
+    _, bs, wall = S.run_stream(sat, ids["served"], pool, base, pace=False)
     out["served_saturated_req_per_s"] = n_requests / wall
+    out["graph_captures"] = sat.stats()["graph_captures"]
     for srv in servers.values():
         srv.close()
     del plans, pool
     torch.cuda.empty_cache()
+    return out
+
+
+def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
+    """MGVI-style metric solve on the workload: d = mask * L xi* + 0.1 noise with a
+    Bernoulli(0.7) mask, w = mask / 0.1^2, b = L^T (w * d); `iters` CG steps of
+    (L^T W L + 1) x = b on the device (each step one metric product), timed over
+    several solves."""
+    import torch
+    info = plan.info
+    n_xi, n_out = info["n_xi"], info["n_out"]
+    xi_true = torch.from_numpy(W.standard_normal_f32(n_xi, seed=2)).cuda().to(plan.dtype)
+    noise = torch.from_numpy(W.standard_normal_f32(n_out, seed=3)).cuda().to(plan.acc_dtype)
+    mask = torch.from_numpy(W.bernoulli_mask(n_out, 0.7, seed=4)).cuda().to(plan.acc_dtype)
+    w = mask / 0.01
+    s = B.icr_forward(plan, xi_true[None])[0].to(plan.acc_dtype)
+    d = mask * s + 0.1 * noise
+    b = B.icr_adjoint(plan, (w * d).to(plan.dtype)[None])[0]
+    ws = torch.empty(B.icr_cg_workspace_bytes(plan, 1), dtype=torch.uint8, device="cuda")
+    x = torch.empty_like(b)
+    x, norms = B.icr_cg_metric(plan, w, b, iters, x=x, residual_norms=True, workspace=ws)
+    torch.cuda.synchronize()
+    n_solves = 5
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_solves)]
+    for e0, e1 in evs:
+        e0.record()
+        B.icr_cg_metric(plan, w, b, iters, x=x, workspace=ws)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = statistics.median(e0.elapsed_time(e1) for e0, e1 in evs)
+    nr = norms[0].double().cpu().numpy()
+    out = {"iterations": iters, "ms_per_solve": ms, "us_per_metric_product": ms * 1e3 / iters,
+           "metric_products_per_s": iters / (ms * 1e-3),
+           "fine_px_per_s": 2 * iters * n_out / (ms * 1e-3),
+           "residual_reduction": float(nr[-1] / nr[0]),
+           "data": "truth xi* seed 2, noise sigma 0.1 seed 3, 70% observed (Bernoulli seed 4)"}
+    log(f"cg: {iters} iterations in {ms:.2f} ms ({out['us_per_metric_product']:.1f} us per metric product), "
+        f"|r|/|r0| = {out['residual_reduction']:.2e}", quiet)
     return out
 
 
@@ -316,6 +376,9 @@ def main():
     }
     if levels is not None:
         out["levels"] = levels
+    cg_iters = args.cg_iters if args.cg_iters is not None else (200 if wl["chart"] != "regular" else 0)
+    if cg_iters > 0 and not args.copy_probe and prec != "bf16":
+        out["cg"] = cg_solve(B, plan, wl, cg_iters, args.quiet)
     if args.serve_requests > 0 and not args.copy_probe:
         out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
     if not args.no_cpu_baseline:

@@ -9,7 +9,8 @@
 //   3. admits a batch only if its buffers fit in the fixed HBM arena (first fit), and
 //      launches it on a stream with no batch in flight: gather the requests' inputs into a
 //      contiguous batch, run the batched sweep (replaying a hipGraph captured once per
-//      (plan, op, batch size) when graphs are enabled), scatter the outputs, record an event.
+//      (plan, op, batch size) when graphs are enabled and the batch needs at most 1/32 of
+//      the arena; larger batches launch eagerly), scatter the outputs, record an event.
 // Requests that arrive while others run join the queue and are admitted as streams and
 // memory free up, so batches of different priors overlap on the device. With
 // max_batch = 1, one stream and no graphs the same server is the one-launch-per-request
@@ -254,37 +255,42 @@ hipError_t copy_rows(const std::vector<const void*>& ptrs, void* contiguous, int
   return hipGetLastError();
 }
 
+// Carve a batch's buffers; if the arena is full, evict idle captured graphs (least
+// recently used first) until the buffers fit. Fails only while the memory is held by
+// batches in flight, which retire and free it.
+bool carve_evicting(icr_server* s, const PlanEntry& pe, int op, int k, Buffers* b) {
+  if (carve(s, pe, op, k, b)) return true;
+  std::vector<std::pair<double, std::tuple<int, int, int>>> idle;
+  for (auto& kv : s->graphs)
+    for (Graph* h : kv.second)
+      if (!h->busy) idle.push_back({h->last_used, kv.first});
+  std::sort(idle.begin(), idle.end());
+  for (auto& cand : idle) {
+    auto& l2 = s->graphs[cand.second];
+    for (size_t i = 0; i < l2.size(); ++i) {
+      if (!l2[i]->busy && l2[i]->last_used == cand.first) {
+        (void)hipGraphExecDestroy(l2[i]->exec);
+        s->arena.release(l2[i]->buf.in);
+        delete l2[i];
+        l2.erase(l2.begin() + i);
+        break;
+      }
+    }
+    if (carve(s, pe, op, k, b)) return true;
+  }
+  return false;
+}
+
 Graph* find_graph(icr_server* s, const PlanEntry& pe, int plan_id, int op, int k, hipStream_t st, bool* oom) {
   auto& list = s->graphs[std::make_tuple(plan_id, op, k)];
   for (Graph* g : list)
     if (!g->busy) return g;
   // capture a new instance with its own buffers
   Graph* g = new Graph;
-  if (!carve(s, pe, op, k, &g->buf)) {
-    // evict idle graphs of other keys, least recently used first
-    std::vector<std::pair<double, std::tuple<int, int, int>>> idle;
-    for (auto& kv : s->graphs)
-      for (Graph* h : kv.second)
-        if (!h->busy) idle.push_back({h->last_used, kv.first});
-    std::sort(idle.begin(), idle.end());
-    for (auto& cand : idle) {
-      auto& l2 = s->graphs[cand.second];
-      for (size_t i = 0; i < l2.size(); ++i) {
-        if (!l2[i]->busy && l2[i]->last_used == cand.first) {
-          (void)hipGraphExecDestroy(l2[i]->exec);
-          s->arena.release(l2[i]->buf.in);
-          delete l2[i];
-          l2.erase(l2.begin() + i);
-          break;
-        }
-      }
-      if (carve(s, pe, op, k, &g->buf)) break;
-    }
-    if (!g->buf.in) {
-      delete g;
-      *oom = true;
-      return nullptr;
-    }
+  if (!carve_evicting(s, pe, op, k, &g->buf)) {
+    delete g;
+    *oom = true;
+    return nullptr;
   }
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -319,7 +325,11 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
   b->op = op;
   b->stream = si;
   Buffers buf;
-  if (s->cfg.use_graphs) {
+  // graphs pay off for small, launch-bound batches; a batch larger than 1/32 of the
+  // arena runs eagerly so captured graphs never crowd the arena (evicting and
+  // recapturing them would cost more host time than the launches they save)
+  const bool use_graph = s->cfg.use_graphs && batch_bytes(pe, op, k) * 32 <= s->arena.capacity();
+  if (use_graph) {
     bool oom = false;
     b->graph = find_graph(s, pe, r0.plan_id, op, k, st, &oom);
     if (!b->graph) {
@@ -329,7 +339,7 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
     }
     buf = b->graph->buf;
   } else {
-    if (!carve(s, pe, op, k, &b->buf)) {
+    if (!carve_evicting(s, pe, op, k, &b->buf)) {
       delete b;
       return false;
     }

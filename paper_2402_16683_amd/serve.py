@@ -188,9 +188,11 @@ def register_all(server: Server, plans) -> list:
     return [server.register(p) for p in plans]
 
 
-def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True):
+def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True, slot_timeout_s: float = 60.0):
     """Submit the stream at its arrival times; returns per-request latency (s), batch size
-    and the wall time of the run. `plan_ids` are the pool's ids in this server."""
+    and the wall time of the run. `plan_ids` are the pool's ids in this server. A request
+    that can never fit the server's memory budget is refused at submission: its latency
+    is NaN and its batch size 0."""
     ids_for = list(plan_ids)
     names = ("forward", "adjoint", "metric")
     n = len(stream.op)
@@ -206,32 +208,45 @@ def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True
         j = counters[k] % len(sl.xi)
         counters[k] += 1
         if sl.last[j] is not None:       # the slot's previous request must be finished
+            deadline = time.perf_counter() + slot_timeout_s
             while not server.query(sl.last[j])[0]:
+                if time.perf_counter() > deadline:
+                    raise RuntimeError(f"request {sl.last[j]} did not finish within {slot_timeout_s} s")
                 time.sleep(20e-6)
         if pace:
             target = t0 + stream.arrivals[i]
             while time.perf_counter() < target:
                 pass
         op = names[int(stream.op[i])]
-        if op == "forward":
-            rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_s[j])
-        elif op == "adjoint":
-            rid = server.submit(ids_for[k], op, sl.ybar[j], sl.out_x[j])
-        else:
-            rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_x[j], sl.w[j])
+        try:
+            if op == "forward":
+                rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_s[j])
+            elif op == "adjoint":
+                rid = server.submit(ids_for[k], op, sl.ybar[j], sl.out_x[j])
+            else:
+                rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_x[j], sl.w[j])
+        except B.ICRError as e:
+            if e.status != 4:           # only "does not fit the server's budget" is a refusal
+                raise
+            rid = -1
         lag[i] = max(0.0, time.perf_counter() - (t0 + stream.arrivals[i])) if pace else 0.0
-        sl.last[j] = rid
+        sl.last[j] = rid if rid >= 0 else sl.last[j]
         rids[i] = rid
-    server.drain(600.0)
+    server.drain(slot_timeout_s)
     wall = time.perf_counter() - t0
     lat = np.zeros(n)
     bs = np.zeros(n, dtype=np.int64)
     for i, rid in enumerate(rids):
+        if rid < 0:                     # refused at submission
+            lat[i], bs[i] = np.nan, 0
+            continue
         done, ts, _, td, b = server.query(int(rid))
         lat[i] = (td - ts) + lag[i]
         bs[i] = b
     return lat, bs, wall
 
 
-def fine_pixels(plans, stream: Stream) -> int:
-    return int(sum(plans[int(k)].info["n_out"] for k in stream.prior))
+def fine_pixels(plans, stream: Stream, served=None) -> int:
+    """Fine pixels of the stream's requests (only those with served[i] True, if given)."""
+    keep = np.ones(len(stream.prior), dtype=bool) if served is None else np.asarray(served)
+    return int(sum(plans[int(k)].info["n_out"] for k, ok in zip(stream.prior, keep) if ok))

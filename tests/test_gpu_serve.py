@@ -137,3 +137,41 @@ def test_poisson_stream_driver_reports_latencies():
     assert np.all(lat > 0) and np.all(bs >= 1) and wall > 0
     assert server.stats()["completed"] == 200
     server.close()
+
+
+def _batch_bytes(info, op, k=1, acc=4):
+    up = lambda v: (v + 255) // 256 * 256
+    el = info["elem_bytes"]
+    n_in = info["n_out"] if op == "adjoint" else info["n_xi"]
+    n_out = info["n_out"] if op == "forward" else info["n_xi"]
+    ws = info["n_xi"] if op == "metric" else max(info["n_xi"] - info["n_out"], 1)
+    b = up(k * n_in * el) + up(k * n_out * el) + up(k * ws * el)
+    return b + (up(k * info["n_out"] * acc) if op == "metric" else 0)
+
+
+def test_idle_graphs_are_evicted_for_a_large_request():
+    """A batch too large for a graph runs eagerly from the arena; when idle captured
+    graphs hold the memory it needs, they are evicted (the request is not starved)."""
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    small, big = plans[0], plans[2]
+    need = _batch_bytes(big.info, "metric")
+    assert _batch_bytes(small.info, "forward") * 32 <= need + 256   # the small one is graphed
+    server = Server(hbm_budget_bytes=need + 256, max_batch=1, n_streams=1, use_graphs=True)
+    sid, bid = server.register(small), server.register(big)
+    xs = torch.randn(small.info["n_xi"], device="cuda")
+    out_s = torch.empty(small.info["n_out"], device="cuda")
+    server.submit(sid, "forward", xs, out_s)
+    server.drain(30.0)
+    assert server.stats()["graph_captures"] == 1        # its graph stays in the arena
+    v = torch.randn(big.info["n_xi"], device="cuda")
+    w = (torch.rand(big.info["n_out"], device="cuda") < 0.7).float() * 100.0
+    out_b = torch.full((big.info["n_xi"],), float("nan"), device="cuda")
+    rid = server.submit(bid, "metric", v, out_b, w)
+    server.drain(30.0)                                   # raises on a time-out
+    assert server.query(rid)[0]
+    from paper_2402_16683_amd import icr as B
+    assert torch.equal(out_b, B.icr_metric_apply(big, w, v[None])[0])
+    assert torch.equal(out_s, B.icr_forward(small, xs[None])[0])
+    server.close()
