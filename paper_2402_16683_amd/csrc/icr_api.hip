@@ -190,6 +190,7 @@ namespace icr {
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (try_refine3_fwd_sector(p, level, a, st, &e)) return e;
+  if (try_refine2_fwd(p, level, a, st, &e)) return e;
   return launch_refine_fwd_generic(p, level, a, st);
 }
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {

@@ -150,6 +150,7 @@ bool try_refine3_fwd_sector(const icr_plan* p, int level, const RefineFwdArgs& a
                             hipError_t* err);
 bool try_refine3_adj_sector(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st,
                             hipError_t* err);
+bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st, hipError_t* err);
 bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);

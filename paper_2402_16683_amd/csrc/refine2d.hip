@@ -1,5 +1,10 @@
-// 2-D refinement level adjoint with the dense 4 x 9 R and lower 4 x 4 sqrtD of a
-// stationary level, FP32 arithmetic with FP32 or bfloat16 storage.
+// 2-D refinement level, forward and adjoint, with the dense 4 x 9 R and lower 4 x 4
+// sqrtD of a stationary level, FP32 arithmetic with FP32 or bfloat16 storage.
+//
+// Forward: a lane owns two neighbouring interior coarse pixels along x (x = 2P+1, 2P+2)
+// and marches along y; the four coarse columns 2P .. 2P+3 of the rows y-1, y, y+1 slide
+// in registers, so each coarse row is read once per lane, and the pair's four fine
+// values per fine row are one 16-byte excitation load and one 16-byte store.
 //
 // The transpose of the forward block map s_{l+1}[2(c-1)+b] = sum_w R[b,w] s_l[c+w] +
 // sum_{b'} sqrtD[b,b'] xi_{l+1}[2(c-1)+b'] is, per coarse pixel p (a gather, no atomics)
@@ -43,6 +48,9 @@ __host__ __device__ __forceinline__ int sd2(int c, int cp) { return c * (c + 1) 
 
 template <typename TS, bool kAdd>
 __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom g, RefineAdjArgs a, Mat2 m) {
+  fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.y, a.y_bs, a.xi_bar, a.xi_bar_bs, a.s_bar,
+             a.s_bar_bs);
+  if (kAdd) fetch_args(a.add, a.add_bs);
   const int lane = threadIdx.x % kLanes;
   const int wave = blockIdx.x * kWavesPerGroup + threadIdx.x / kLanes;
   if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
@@ -152,40 +160,197 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
   Row ra, rb, rc;
   load_row(y0 - 1, ra);
   load_row(y0, rb);
+  // the scheduling barriers keep each prefetch ahead of the next row's first wait (with
+  // the prefetch sunk below it, the loop entry and the back edge merge into a wait for
+  // every outstanding access, loads and stores sharing one counter)
   for (int yb = y0 - 1; yb <= y1; yb += 3) {
     load_row(yb + 2, rc);
+    __builtin_amdgcn_sched_barrier(0);
     process(yb, ra);
     if (yb + 1 > y1) break;
     load_row(yb + 3, ra);
+    __builtin_amdgcn_sched_barrier(0);
     process(yb + 1, rb);
     if (yb + 2 > y1) break;
     load_row(yb + 4, rb);
+    __builtin_amdgcn_sched_barrier(0);
     process(yb + 2, rc);
+  }
+}
+
+struct Fwd2Geom {
+  int ny, nx;   // coarse shape
+  int pairs;    // (nx - 2) / 2 pixel pairs per interior row
+  int strips;   // wavefront strips along x (64 pairs each)
+  int ychunk;   // interior coarse rows per wavefront
+  int nfx;      // fine row length
+  int waves;    // wavefronts per sample
+};
+
+template <typename TS, bool kW>
+__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom g, RefineFwdArgs a, Mat2 m) {
+  fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.s_in, a.s_in_bs, a.xi, a.xi_bs, a.s_out,
+             a.s_out_bs);
+  if (kW) fetch_args(a.w, a.w_bs);
+  const int lane = threadIdx.x % kLanes;
+  const int wave = blockIdx.x * kWavesPerGroup + threadIdx.x / kLanes;
+  if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
+  const int strip = wave % g.strips, chunk = wave / g.strips;
+  const int P = strip * kLanes + lane;
+  const bool valid = P < g.pairs;
+  const int Pc = valid ? P : g.pairs - 1;  // lanes past the row end load the last pair, store nothing
+  const int y0 = 1 + chunk * g.ychunk;     // interior coarse rows y0 .. y1-1
+  const int y1 = min(y0 + g.ychunk, g.ny - 1);
+  const int64_t b = blockIdx.y;
+  const TS* sc = static_cast<const TS*>(a.s_in) + b * a.s_in_bs;
+  const TS* xi = static_cast<const TS*>(a.xi) + b * a.xi_bs;
+  TS* so = static_cast<TS*>(a.s_out) + b * a.s_out_bs;
+  const float* w = kW ? static_cast<const float*>(a.w) + b * a.w_bs : nullptr;
+  auto fine_off = [&](int y, int by) { return static_cast<int64_t>(2 * (y - 1) + by) * g.nfx + 4 * Pc; };
+  auto coarse_row = [&](int y, float (&r)[4]) {
+    const TS* row = sc + static_cast<int64_t>(y) * g.nx + 2 * Pc;
+    const float2 u = Io<TS>::ld2(row), v = Io<TS>::ld2(row + 2);
+    r[0] = u.x; r[1] = u.y; r[2] = v.x; r[3] = v.y;
+  };
+
+  struct Step {
+    float c[4];    // coarse row y + 1, columns 2P .. 2P+3
+    float4 x[2];   // excitations of the pair's fine rows 2(y-1), 2(y-1)+1
+    float4 wr[2];  // metric weights (kW)
+  };
+  auto load_step = [&](int y, Step& st) {
+    const int yc = min(y, y1 - 1);  // past the chunk: reload its last row (in bounds, unused)
+    coarse_row(yc + 1, st.c);
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      st.x[by] = Io<TS>::ld4(xi + fine_off(yc, by));
+      if (kW) st.wr[by] = *reinterpret_cast<const float4*>(w + fine_off(yc, by));
+    }
+  };
+  float rm[4], r0[4];  // coarse rows y-1 and y
+  auto compute_step = [&](int y, const Step& st) {
+    float o[2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float win[9];  // window of block 2P+1+p: columns 2P+p .. 2P+p+2 of rows y-1, y, y+1
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        win[x] = rm[p + x];
+        win[3 + x] = r0[p + x];
+        win[6 + x] = st.c[p + x];
+      }
+      float xv[4];
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        xv[by * 2] = p == 0 ? st.x[by].x : st.x[by].z;
+        xv[by * 2 + 1] = p == 0 ? st.x[by].y : st.x[by].w;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float v = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v = fmaf(m.r[c * 9 + k], win[k], v);
+#pragma unroll
+        for (int cp = 0; cp <= c; ++cp) v = fmaf(m.s[sd2(c, cp)], xv[cp], v);
+        o[p][c] = v;
+      }
+    }
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      float4 v = make_float4(o[0][by * 2], o[0][by * 2 + 1], o[1][by * 2], o[1][by * 2 + 1]);
+      if (kW) {
+        const float4 ww = st.wr[by];
+        v.x *= ww.x; v.y *= ww.y; v.z *= ww.z; v.w *= ww.w;
+      }
+      if (valid) st4_stream<TS>(so + fine_off(y, by), v);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { rm[k] = r0[k]; r0[k] = st.c[k]; }
+  };
+
+  coarse_row(y0 - 1, rm);
+  coarse_row(y0, r0);
+  // two rows in flight: a ring of three buffers, unrolled so no buffer is copied; the
+  // scheduling barriers keep each prefetch ahead of the next row's first wait
+  Step sa, sb, sc2;
+  load_step(y0, sa);
+  load_step(y0 + 1, sb);
+  for (int y = y0; y < y1; y += 3) {
+    load_step(y + 2, sc2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_step(y, sa);
+    if (y + 1 >= y1) break;
+    load_step(y + 3, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_step(y + 1, sb);
+    if (y + 2 >= y1) break;
+    load_step(y + 4, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_step(y + 2, sc2);
   }
 }
 
 bool aligned2(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
 
-template <typename TS>
-hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+Mat2 mat2_of(const icr_plan* p, int level) {
   const LevelMats& lm = p->lev[level];
   Mat2 m;
   for (int t = 0; t < 36; ++t) m.r[t] = lm.h_r[t];
   for (int c = 0; c < 4; ++c)
     for (int cp = 0; cp <= c; ++cp) m.s[sd2(c, cp)] = lm.h_s[c * 4 + cp];
+  return m;
+}
+
+// rows per wavefront for a sweep of `rows` rows in `strips` strips: enough wavefronts
+// to keep every SIMD busy (about 8 per SIMD over 1024 SIMDs); a small level gets one
+// row per wavefront (a march is a chain of dependent steps), a large one long marches
+int pick_ychunk(int rows, int strips, int64_t batch) {
+  int64_t chunks = 8192 / (int64_t(strips) * batch);
+  chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, rows));
+  return static_cast<int>((rows + chunks - 1) / chunks);
+}
+
+template <typename TS>
+hipError_t fwd2_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
+  const Mat2 m = mat2_of(p, level);
+  Fwd2Geom g;
+  g.ny = p->shapes[level][1];
+  g.nx = p->shapes[level][2];
+  g.pairs = (g.nx - 2) / 2;
+  g.strips = (g.pairs + kLanes - 1) / kLanes;
+  g.nfx = p->shapes[level + 1][2];
+  const int64_t batch = a.batch < 65535 ? a.batch : 65535;
+  g.ychunk = pick_ychunk(g.ny - 2, g.strips, batch);
+  const int nchunks = (g.ny - 2 + g.ychunk - 1) / g.ychunk;
+  g.waves = g.strips * nchunks;
+  const unsigned groups = static_cast<unsigned>((g.waves + kWavesPerGroup - 1) / kWavesPerGroup);
+  for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
+    RefineFwdArgs c = a;
+    c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
+    c.s_in = static_cast<const TS*>(a.s_in) + b0 * a.s_in_bs;
+    c.xi = static_cast<const TS*>(a.xi) + b0 * a.xi_bs;
+    c.s_out = static_cast<TS*>(a.s_out) + b0 * a.s_out_bs;
+    if (a.w) c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
+    const dim3 grid(groups, static_cast<unsigned>(c.batch));
+    if (a.w) refine2_fwd<TS, true><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    else refine2_fwd<TS, false><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TS>
+hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  const Mat2 m = mat2_of(p, level);
   Adj2Geom g;
   g.ny = p->shapes[level][1];
   g.nx = p->shapes[level][2];
   g.pairs = (g.nx - 2) / 2;
   g.strips = (g.pairs + kOwnedPairs - 1) / kOwnedPairs;
   g.nfx = p->shapes[level + 1][2];
-  // enough wavefronts to keep every SIMD busy (about 8 per SIMD over 1024 SIMDs), in
-  // chunks of at least 8 rows so the recomputed halo rows stay a small share
   const int64_t batch = a.batch < 65535 ? a.batch : 65535;
-  const int64_t target = 8192;
-  int64_t chunks = target / (int64_t(g.strips) * batch);
-  chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (g.ny + 7) / 8));
-  g.ychunk = static_cast<int>((g.ny + chunks - 1) / chunks);
+  g.ychunk = pick_ychunk(g.ny, g.strips, batch);
   const int nchunks = (g.ny + g.ychunk - 1) / g.ychunk;
   g.waves = g.strips * nchunks;
   const unsigned groups = static_cast<unsigned>((g.waves + kWavesPerGroup - 1) / kWavesPerGroup);
@@ -205,16 +370,30 @@ hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hip
   return hipSuccess;
 }
 
-}  // namespace
-
 // Stationary 2-D levels in FP32 arithmetic with an even coarse row length, vector-aligned
 // fine rows and batch strides; everything else takes the generic kernels.
-bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err) {
+bool eligible2(const icr_plan* p, int level) {
   if (p->ndim != 2 || p->charted || p->precision == ICR_F64) return false;
   const int nx = p->shapes[level][2];
   if (nx % 2 != 0 || nx < 4) return false;
   const int64_t nf = int64_t(p->shapes[level + 1][1]) * p->shapes[level + 1][2];
-  if (nf >= (int64_t(1) << 31)) return false;
+  return nf < (int64_t(1) << 31);
+}
+
+}  // namespace
+
+bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st, hipError_t* err) {
+  if (!eligible2(p, level)) return false;
+  const int el = p->elem_bytes;
+  if (!aligned2(a.xi, 4 * el) || !aligned2(a.s_out, 4 * el) || !aligned2(a.s_in, 2 * el)) return false;
+  if (a.xi_bs % 4 || a.s_out_bs % 4 || a.s_in_bs % 2) return false;
+  if (a.w && (!aligned2(a.w, 16) || a.w_bs % 4)) return false;
+  *err = p->precision == ICR_F32 ? fwd2_launch<float>(p, level, a, st) : fwd2_launch<bf16_t>(p, level, a, st);
+  return true;
+}
+
+bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err) {
+  if (!eligible2(p, level)) return false;
   const int vec = 4 * p->elem_bytes;
   if (!aligned2(a.y, vec) || !aligned2(a.xi_bar, vec) || (a.add && !aligned2(a.add, vec))) return false;
   if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;

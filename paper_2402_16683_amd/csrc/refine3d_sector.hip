@@ -126,9 +126,16 @@ template <typename TS, bool kW>
 __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, Sector3 k) {
   // plane-major order (no XCD renumbering): the forward's only shared data is the
   // small coarse level, and this order measured faster on the 388^3 level
+  fetch_args(g.nz, g.ny, g.nx, g.pairs, g.rows, g.zchunk, g.nfy, g.nfx, g.xy_blocks, a.s_in, a.s_in_bs, a.xi,
+             a.xi_bs, a.s_out, a.s_out_bs);
+  if (kW) fetch_args(a.w, a.w_bs);
   const int tile = static_cast<int>(blockIdx.x);
-  const int tid = (tile % g.xy_blocks) * 256 + threadIdx.x;
-  if (tid >= g.rows * g.pairs) return;
+  // no early exit: threads past the last pair work on the last pair and store nothing,
+  // so every kernel argument can be fetched in one round at the start (an exit branch
+  // made the pointer loads wait for the geometry loads)
+  const int tid_raw = (tile % g.xy_blocks) * 256 + threadIdx.x;
+  const bool valid = tid_raw < g.rows * g.pairs;
+  const int tid = valid ? tid_raw : g.rows * g.pairs - 1;
   const int yi = tid / g.pairs;
   const int q = tid - yi * g.pairs;
   const int y = yi + 1;
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
           const float4 ww = st.wr[bz][by];
           v.x *= ww.x; v.y *= ww.y; v.z *= ww.z; v.w *= ww.w;
         }
-        st4_stream<TS>(so + fine_off(z, bz, by), v);
+        if (valid) st4_stream<TS>(so + fine_off(z, bz, by), v);
       }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -207,14 +214,21 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
   Step sa, sb2, sc2;
   load_step(zb, sa);
   load_step(zb + 1, sb2);
+  // The scheduling barriers keep each prefetch ahead of the next step's first wait: the
+  // loop header is also entered from the prologue, and with the prefetch sunk below the
+  // wait the two paths merge into a wait for every outstanding access (loads and stores
+  // share one counter), which drains the pipeline once per unrolled body.
   for (int z = zb; z < ze; z += 3) {
     load_step(z + 2, sc2);
+    __builtin_amdgcn_sched_barrier(0);
     compute_step(z, sa);
     if (z + 1 >= ze) break;
     load_step(z + 3, sa);
+    __builtin_amdgcn_sched_barrier(0);
     compute_step(z + 1, sb2);
     if (z + 2 >= ze) break;
     load_step(z + 4, sb2);
+    __builtin_amdgcn_sched_barrier(0);
     compute_step(z + 2, sc2);
   }
 }
@@ -240,6 +254,9 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   constexpr int kAdjThreads = kTP * kTR;
   static_assert(64 % kTP == 0, "tile rows of lanes must not straddle wavefronts");
   __shared__ float ldy[2][8][kAdjThreads];   // double-buffered by coarse-plane parity
+  fetch_args(g.nz, g.ny, g.nx, g.pairs, g.xtiles, g.zchunk, g.nfy, g.nfx, g.xy_tiles, g.nwg, a.y, a.y_bs, a.xi_bar,
+             a.xi_bar_bs, a.s_bar, a.s_bar_bs);
+  if (kAdd) fetch_args(a.add, a.add_bs);
   const int t = threadIdx.x;
   const int i = t % kTP, j = t / kTP;
   const int tile = xcd_tile(blockIdx.x, g.nwg);
@@ -405,14 +422,17 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   Plane pa, pb, pc;
   load_plane_y(z0 - 1, pa);
   load_plane_y(z0, pb);
-  for (int zb = z0 - 1; zb <= z1; zb += 3) {
+  for (int zb = z0 - 1; zb <= z1; zb += 3) {  // scheduling barriers: as in the forward
     load_plane_y(zb + 2, pc);
+    __builtin_amdgcn_sched_barrier(0);
     process(zb, pa);
     if (zb + 1 > z1) break;
     load_plane_y(zb + 3, pa);
+    __builtin_amdgcn_sched_barrier(0);
     process(zb + 1, pb);
     if (zb + 2 > z1) break;
     load_plane_y(zb + 4, pb);
+    __builtin_amdgcn_sched_barrier(0);
     process(zb + 2, pc);
   }
 }

@@ -29,13 +29,23 @@ __device__ __forceinline__ int64_t lin(const int* idx, const int* shape) {
 
 template <int D, typename TS, bool kCharted>
 __global__ void __launch_bounds__(256) refine_fwd_generic(Geom g, RefineFwdArgs a,
-                                                          const typename Acc<TS>::type* __restrict__ R,
-                                                          const typename Acc<TS>::type* __restrict__ S) {
+                                                          const typename Acc<TS>::type* R,
+                                                          const typename Acc<TS>::type* S) {
   using TA = typename Acc<TS>::type;
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
+  // a stationary level's R and sqrtD are staged in LDS with one cooperative load (read
+  // element by element from memory they would be a long chain of dependent loads)
+  __shared__ TA lds_r[kCharted ? 1 : NC * NW], lds_s[kCharted ? 1 : NC * NC];
+  if (!kCharted) {
+    for (int e = threadIdx.x; e < NC * NW; e += blockDim.x) lds_r[e] = R[e];
+    for (int e = threadIdx.x; e < NC * NC; e += blockDim.x) lds_s[e] = S[e];
+    __syncthreads();
+    R = lds_r;
+    S = lds_s;
+  }
   if (t >= g.nsets) return;  // nsets = prod(mi) for both stationary and charted here
   int c[D];
   {
@@ -75,13 +85,21 @@ __global__ void __launch_bounds__(256) refine_fwd_generic(Geom g, RefineFwdArgs 
 
 template <int D, typename TS, bool kCharted>
 __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoarse, RefineAdjArgs a,
-                                                          const typename Acc<TS>::type* __restrict__ R,
-                                                          const typename Acc<TS>::type* __restrict__ S) {
+                                                          const typename Acc<TS>::type* R,
+                                                          const typename Acc<TS>::type* S) {
   using TA = typename Acc<TS>::type;
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
+  __shared__ TA lds_r[kCharted ? 1 : NC * NW], lds_s[kCharted ? 1 : NC * NC];  // as in the forward
+  if (!kCharted) {
+    for (int e = threadIdx.x; e < NC * NW; e += blockDim.x) lds_r[e] = R[e];
+    for (int e = threadIdx.x; e < NC * NC; e += blockDim.x) lds_s[e] = S[e];
+    __syncthreads();
+    R = lds_r;
+    S = lds_s;
+  }
   if (t >= ncoarse) return;
   int p[D];
   {

@@ -90,6 +90,19 @@ __device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
+// Kernel arguments are fetched from memory by scalar loads that the compiler places
+// after the kernel's first branches, so a kernel could wait for two or three dependent
+// fetch rounds before its first vector load. Naming the arguments here, at the top of
+// a kernel, makes them resident in scalar registers at once: one fetch round.
+template <typename T>
+__device__ __forceinline__ void pin_scalar(const T& v) {
+  asm volatile("" ::"s"(v));
+}
+template <typename... T>
+__device__ __forceinline__ void fetch_args(const T&... v) {
+  (pin_scalar(v), ...);
+}
+
 }  // namespace sweep
 }  // namespace icr
 
