@@ -14,7 +14,7 @@ namespace icr {
 namespace {
 
 constexpr int kDotThreads = 256;
-constexpr int kDotBlocks = 256;  // partial sums per sample
+constexpr int kDotBlocks = 1024;  // partial sums per sample
 
 struct CgScalars {
   double rr;     // r.r of the current residual
@@ -23,7 +23,6 @@ struct CgScalars {
   double pq;
 };
 
-template <typename T>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -35,8 +34,40 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
-// partial[b][blk] = sum over this block's strided share of a[b] * c[b]
-template <typename T>
+// V consecutive elements as one access: 16 bytes when the vectors are aligned (V * sizeof(T)
+// == 16), else V = 1. Thread g of a sample handles groups g, g + G, g + 2G, ... of V
+// elements (G = blocks x threads), so the partition, and with it every partial sum, is
+// fixed by n alone.
+template <typename T, int V>
+struct Chunk {
+  T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Chunk<T, V> ldv(const T* p) {
+  Chunk<T, V> c;
+  if constexpr (V * sizeof(T) == 16) {
+    const uint4 u = *reinterpret_cast<const uint4*>(p);
+    __builtin_memcpy(c.v, &u, 16);
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) c.v[k] = p[k];
+  }
+  return c;
+}
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const Chunk<T, V>& c) {
+  if constexpr (V * sizeof(T) == 16) {
+    uint4 u;
+    __builtin_memcpy(&u, c.v, 16);
+    *reinterpret_cast<uint4*>(p) = u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) p[k] = c.v[k];
+  }
+}
+
+// partial[b][blk] = sum over this block's share of a[b] * c[b]
+template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__ a, const T* __restrict__ c,
                                                            int64_t n, double* __restrict__ partial) {
   __shared__ double sh[kDotThreads];
@@ -44,9 +75,12 @@ __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__
   const T* pa = a + b * n;
   const T* pc = c + b * n;
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; i < n; i += int64_t(kDotBlocks) * kDotThreads)
-    acc += static_cast<double>(pa[i]) * static_cast<double>(pc[i]);
-  const double s = block_sum<T>(acc, sh);
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+    const Chunk<T, V> u = ldv<T, V>(pa + g * V), w = ldv<T, V>(pc + g * V);
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc += static_cast<double>(u.v[k]) * static_cast<double>(w.v[k]);
+  }
+  const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
@@ -59,7 +93,7 @@ __global__ void __launch_bounds__(kDotThreads) dot_finish(const double* __restri
   const int64_t b = blockIdx.x;
   double v = 0.0;
   for (int k = threadIdx.x; k < kDotBlocks; k += kDotThreads) v += partial[b * kDotBlocks + k];
-  const double s = block_sum<double>(v, sh);
+  const double s = block_sum(v, sh);
   if (threadIdx.x != 0) return;
   CgScalars& c = sc[b];
   if (which == 0) {
@@ -76,59 +110,106 @@ __global__ void __launch_bounds__(kDotThreads) dot_finish(const double* __restri
 }
 
 // x += alpha p; r -= alpha q; partial sums of r.r
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                          const T* __restrict__ q, int64_t n, const CgScalars* sc,
                                                          double* __restrict__ partial) {
   __shared__ double sh[kDotThreads];
   const int64_t b = blockIdx.y;
-  const double alpha = sc[b].alpha;
-  const T a = static_cast<T>(alpha);
+  const T a = static_cast<T>(sc[b].alpha);
   T* px = x + b * n;
   T* pr = r + b * n;
   const T* pp = p + b * n;
   const T* pq = q + b * n;
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; i < n; i += int64_t(kDotBlocks) * kDotThreads) {
-    px[i] += a * pp[i];
-    const T rn = pr[i] - a * pq[i];
-    pr[i] = rn;
-    acc += static_cast<double>(rn) * static_cast<double>(rn);
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+    Chunk<T, V> xv = ldv<T, V>(px + g * V), rv = ldv<T, V>(pr + g * V);
+    const Chunk<T, V> pv = ldv<T, V>(pp + g * V), qv = ldv<T, V>(pq + g * V);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      xv.v[k] += a * pv.v[k];
+      rv.v[k] = rv.v[k] - a * qv.v[k];
+      acc += static_cast<double>(rv.v[k]) * static_cast<double>(rv.v[k]);
+    }
+    stv<T, V>(px + g * V, xv);
+    stv<T, V>(pr + g * V, rv);
   }
-  const double s = block_sum<T>(acc, sh);
+  const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
 // p = r + beta p
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const T* __restrict__ r, int64_t n,
                                                         const CgScalars* sc) {
   const int64_t b = blockIdx.y;
   const T beta = static_cast<T>(sc[b].beta);
   T* pp = p + b * n;
   const T* pr = r + b * n;
-  for (int64_t i = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; i < n; i += int64_t(kDotBlocks) * kDotThreads)
-    pp[i] = pr[i] + beta * pp[i];
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+    Chunk<T, V> pv = ldv<T, V>(pp + g * V);
+    const Chunk<T, V> rv = ldv<T, V>(pr + g * V);
+#pragma unroll
+    for (int k = 0; k < V; ++k) pv.v[k] = rv.v[k] + beta * pv.v[k];
+    stv<T, V>(pp + g * V, pv);
+  }
 }
 
 // x = 0, r = p = b, partial sums of b.b
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) cg_init(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                        const T* __restrict__ bvec, int64_t n,
                                                        double* __restrict__ partial) {
   __shared__ double sh[kDotThreads];
   const int64_t b = blockIdx.y;
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; i < n; i += int64_t(kDotBlocks) * kDotThreads) {
-    const T v = bvec[b * n + i];
-    x[b * n + i] = T(0);
-    r[b * n + i] = v;
-    p[b * n + i] = v;
-    acc += static_cast<double>(v) * static_cast<double>(v);
+  Chunk<T, V> zero;
+#pragma unroll
+  for (int k = 0; k < V; ++k) zero.v[k] = T(0);
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+    const Chunk<T, V> v = ldv<T, V>(bvec + b * n + g * V);
+    stv<T, V>(x + b * n + g * V, zero);
+    stv<T, V>(r + b * n + g * V, v);
+    stv<T, V>(p + b * n + g * V, v);
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc += static_cast<double>(v.v[k]) * static_cast<double>(v.v[k]);
   }
-  const double s = block_sum<T>(acc, sh);
+  const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
+
+template <typename T, int V>
+hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec, void* x,
+                  int32_t iterations, double* norms, void* mws, T* r, T* pv, T* q, double* partial,
+                  CgScalars* sc, hipStream_t st,
+                  hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*, void*,
+                                       hipStream_t)) {
+  const int64_t n = p->n_xi;
+  const dim3 grid(kDotBlocks, static_cast<unsigned>(batch));
+  const int stride = iterations + 1;
+  T* xv = static_cast<T*>(x);
+  cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 2, norms, 0, stride);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int it = 0; it < iterations; ++it) {
+    if ((e = metric(p, batch, w, w_bs, pv, q, mws, st)) != hipSuccess) return e;
+    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 0, nullptr, it, stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 1, norms, it, stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
 
 }  // namespace
 
@@ -157,34 +238,20 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   void* q = base; base += up(batch * n * el);
   double* partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
   CgScalars* sc = reinterpret_cast<CgScalars*>(base);
-  const dim3 grid(kDotBlocks, static_cast<unsigned>(batch));
-  const int stride = iterations + 1;
-  const bool f64 = p->precision == ICR_F64;
-#define AS(T, ptr) static_cast<T*>(ptr)
-  if (f64) cg_init<double><<<grid, kDotThreads, 0, st>>>(AS(double, x), AS(double, r), AS(double, pv), static_cast<const double*>(bvec), n, partial);
-  else cg_init<float><<<grid, kDotThreads, 0, st>>>(AS(float, x), AS(float, r), AS(float, pv), static_cast<const float*>(bvec), n, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 2, norms, 0, stride);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int it = 0; it < iterations; ++it) {
-    if ((e = metric(p, batch, w, w_bs, pv, q, mws, st)) != hipSuccess) return e;
-    if (f64) dot_partial<double><<<grid, kDotThreads, 0, st>>>(AS(double, pv), AS(double, q), n, partial);
-    else dot_partial<float><<<grid, kDotThreads, 0, st>>>(AS(float, pv), AS(float, q), n, partial);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 0, nullptr, it, stride);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (f64) update_xr<double><<<grid, kDotThreads, 0, st>>>(AS(double, x), AS(double, r), AS(double, pv), AS(double, q), n, sc, partial);
-    else update_xr<float><<<grid, kDotThreads, 0, st>>>(AS(float, x), AS(float, r), AS(float, pv), AS(float, q), n, sc, partial);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 1, norms, it, stride);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (f64) update_p<double><<<grid, kDotThreads, 0, st>>>(AS(double, pv), AS(double, r), n, sc);
-    else update_p<float><<<grid, kDotThreads, 0, st>>>(AS(float, pv), AS(float, r), n, sc);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 16-byte accesses when every sample's vector starts 16-byte aligned (the workspace
+  // vectors are 256-byte aligned; x and b are the caller's)
+  const int v16 = 16 / el;
+  const bool vec = n % v16 == 0 && aligned16(x) && aligned16(bvec) && aligned16(workspace);
+  if (p->precision == ICR_F64) {
+    return vec ? run_cg<double, 2>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<double*>(r),
+                                   static_cast<double*>(pv), static_cast<double*>(q), partial, sc, st, metric)
+               : run_cg<double, 1>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<double*>(r),
+                                   static_cast<double*>(pv), static_cast<double*>(q), partial, sc, st, metric);
   }
-#undef AS
-  return hipSuccess;
+  return vec ? run_cg<float, 4>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<float*>(r),
+                                static_cast<float*>(pv), static_cast<float*>(q), partial, sc, st, metric)
+             : run_cg<float, 1>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<float*>(r),
+                                static_cast<float*>(pv), static_cast<float*>(q), partial, sc, st, metric);
 }
 
 }  // namespace icr

@@ -109,29 +109,38 @@ __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoars
   const TS* y = static_cast<const TS*>(a.y) + b * a.y_bs;
   const int64_t stride = kCharted ? g.nsets : 1;
 
-  // coarse cotangent: gather the blocks c = p - w that read p at window slot w
+  // coarse cotangent: gather the blocks c = p - w that read p at window slot w. A block
+  // outside the interior is read at a clamped (in-bounds) position and weighted by zero,
+  // so no load sits under a branch and all of them can be in flight at once.
   TA acc = 0;
+#pragma unroll
   for (int iw = 0; iw < NW; ++iw) {
     int c[D];
     bool inside = true;
     int rem = iw;
+#pragma unroll
     for (int ax = D - 1; ax >= 0; --ax) {
-      c[ax] = p[ax] - ((rem % 3) - 1);
+      const int cv = p[ax] - ((rem % 3) - 1);
       rem /= 3;
-      inside = inside && c[ax] >= 1 && c[ax] <= g.nc[ax] - 2;
+      inside = inside && cv >= 1 && cv <= g.nc[ax] - 2;
+      c[ax] = min(max(cv, 1), g.nc[ax] - 2);
     }
-    if (!inside) continue;
     int64_t set = 0;
     if (kCharted) {
       int ci[D];
+#pragma unroll
       for (int ax = 0; ax < D; ++ax) ci[ax] = c[ax] - 1;
       set = lin<D>(ci, g.mi);
     }
+    TA part = 0;
+#pragma unroll
     for (int ib = 0; ib < NC; ++ib) {
       int q[D];
+#pragma unroll
       for (int ax = 0; ax < D; ++ax) q[ax] = 2 * (c[ax] - 1) + ((ib >> (D - 1 - ax)) & 1);
-      acc += R[(ib * NW + iw) * stride + set] * load_acc(y + lin<D>(q, g.nf));
+      part += R[(ib * NW + iw) * stride + set] * load_acc(y + lin<D>(q, g.nf));
     }
+    acc += inside ? part : TA(0);
   }
   store_acc(static_cast<TS*>(a.s_bar) + b * a.s_bar_bs + t, acc);
 
