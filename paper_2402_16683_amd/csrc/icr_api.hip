@@ -97,7 +97,9 @@ icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t 
     ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
     return ICR_OK;
   }
-  for (int l = L - 1; l >= 0; --l) {
+  bool fuse0 = false;
+  const int K = icr::fused_levels(p, &fuse0);  // the smallest levels in one launch
+  for (int l = L - 1; l >= K; --l) {
     icr::RefineAdjArgs a;
     a.y = l == L - 1 ? y : at(ws, p->offsets[l + 1], el);
     a.y_bs = l == L - 1 ? y_bs : ws_bs;
@@ -110,8 +112,13 @@ icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t 
     a.batch = batch;
     ICR_HIP_TRY(icr::launch_refine_adj(p, l, a, st));
   }
-  icr::Level0Args a{ws, ws_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
-  ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
+  if (K > 0)
+    ICR_HIP_TRY(icr::launch_fused_adj(p, K, fuse0, batch, K == L ? y : at(ws, p->offsets[K], el),
+                                      K == L ? y_bs : ws_bs, xi_bar, ws, ws_bs, add, st));
+  if (!fuse0) {
+    icr::Level0Args a{ws, ws_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
+  }
   return ICR_OK;
 }
 
@@ -125,9 +132,16 @@ icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* o
     ICR_HIP_TRY(icr::launch_level0_fwd(p, a, st));
     return ICR_OK;
   }
-  icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch};
-  ICR_HIP_TRY(icr::launch_level0_fwd(p, a0, st));
-  for (int l = 0; l < L; ++l) {
+  bool fuse0 = false;
+  const int K = icr::fused_levels(p, &fuse0);  // the smallest levels in one launch
+  if (!fuse0) {
+    icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch};
+    ICR_HIP_TRY(icr::launch_level0_fwd(p, a0, st));
+  }
+  if (K > 0)
+    ICR_HIP_TRY(icr::launch_fused_fwd(p, K, fuse0, batch, xi, ws, ws_bs, K == L ? out : nullptr, out_bs,
+                                      K == L ? w : nullptr, w_bs, st));
+  for (int l = K; l < L; ++l) {
     icr::RefineFwdArgs a;
     a.s_in = at(ws, p->offsets[l], el);
     a.s_in_bs = ws_bs;

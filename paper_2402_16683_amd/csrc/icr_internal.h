@@ -63,12 +63,6 @@ struct LevelMats {
 // FP32 rounding of R itself.
 constexpr double kSectorTolerance = 1e-7;
 
-// conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1
-int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
-hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
-                     void* x, int32_t iterations, double* norms, void* workspace, hipStream_t st,
-                     hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*,
-                                          void*, hipStream_t));
 
 }  // namespace icr
 
@@ -154,6 +148,15 @@ bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipSt
 bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);
+
+// The first K refinement levels (and level 0 when its factor is small) of a sweep in one
+// launch (fused.hip). fused_levels returns K (0: no fusion) and whether level 0 is included.
+int fused_levels(const icr_plan* p, bool* level0);
+hipError_t launch_fused_fwd(const icr_plan* p, int K, bool level0, int64_t batch, const void* xi, void* ws,
+                            int64_t ws_bs, void* out, int64_t out_bs, const void* w, int64_t w_bs,
+                            hipStream_t st);
+hipError_t launch_fused_adj(const icr_plan* p, int K, bool level0, int64_t batch, const void* y, int64_t y_bs,
+                            void* xi_bar, void* ws, int64_t ws_bs, const void* add, hipStream_t st);
 
 // conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1
 int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
