@@ -3,7 +3,8 @@
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision f32|bf16]
 
 One step is icr_forward followed by icr_adjoint over one batch of the workload
-(every level, level 0 included) with inputs resident in HBM. Buffers rotate over
+(every level, level 0 included) with inputs resident in HBM, every kernel launched from
+the host (--graph replays a captured HIP graph instead). Buffers rotate over
 two sets (> 2 GB for the 3-D workload) so timed passes stream from HBM rather
 than the 256 MB Infinity Cache. Prints one JSON line:
 
@@ -52,6 +53,9 @@ def parse():
     ap.add_argument("--serve-priors", type=int, default=24)
     ap.add_argument("--cg-iters", type=int, default=None,
                     help="CG iterations on the metric (default: 200 for a charted workload, else none)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the step from a captured HIP graph (measured slower than launching "
+                         "every kernel from the host on this stack, so off by default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -265,11 +269,26 @@ def main():
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
+    run = step
+    if args.graph:
+        # the step's launch sequence captured once per buffer set and replayed: no host
+        # work per launch (the sweep calls allocate nothing and use the current stream)
+        graphs = []
+        for k in range(2):
+            gph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gph):
+                step(k)
+            graphs.append(gph)
+        torch.cuda.synchronize()
+        run = lambda k: graphs[k % 2].replay()
+        for k in range(2):
+            run(k)
+        torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
     ev[0].record()
     for k in range(args.steps):
-        step(k)
+        run(k)
         ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -362,7 +381,8 @@ def main():
         "data": "synthetic: seeded N(0,1) excitations and cotangents",
         "config": {"workload": args.workload, "ndim": wl["ndim"], "shape0": list(wl["shape0"]),
                    "depth": L, "final_shape": list(info["level_shapes"][-1]), "kernel": wl["kernel"],
-                   "length": wl["length"], "batch": batch, "precision": prec},
+                   "length": wl["length"], "batch": batch, "precision": prec,
+                   "launch": "hipgraph" if args.graph else "eager"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(tag, digest),
