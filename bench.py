@@ -114,9 +114,9 @@ def cpu_baseline(wl: dict, quiet: bool):
 def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     """Mixed 1-D/2-D/3-D forward/adjoint/metric requests on a pool of priors: the
     one-launch-per-request capacity first, then Poisson streams at 0.5, 0.8 and 1.2x that
-    rate through the served form (continuous batching, hipGraphs, 4 streams, 8 GB
-    arena) and through the plain form; the served form once more under a 256 MB arena,
-    and back to back for its saturated rate."""
+    rate through the served form (continuous batching, hipGraphs, 8 streams, 8 GB
+    arena) and through the plain form; at 0.8x also the served form under a 256 MB arena
+    and without graphs; the served forms back to back for their saturated rates."""
     import torch
 
     from paper_2402_16683_amd import serve as S
@@ -134,10 +134,11 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     capacity = n_requests / wall
     out = {"requests": n_requests, "priors": n_priors, "plain_capacity_req_per_s": capacity,
            "hbm_budget_bytes": budget, "build_s": build_s}
-    servers = {"served": S.Server(budget, max_batch=16, n_streams=4, use_graphs=True), "plain": plain,
-               "served_256MB": S.Server(256 << 20, max_batch=16, n_streams=4, use_graphs=True)}
+    servers = {"served": S.Server(budget, max_batch=16, n_streams=8, use_graphs=True), "plain": plain,
+               "served_256MB": S.Server(256 << 20, max_batch=16, n_streams=8, use_graphs=True),
+               "served_eager": S.Server(budget, max_batch=16, n_streams=8, use_graphs=False)}
     ids = {"plain": pid}
-    for name in ("served", "served_256MB"):   # capture each server's graphs before timing
+    for name in ("served", "served_256MB", "served_eager"):   # capture graphs before timing
         ids[name] = S.register_all(servers[name], plans)
         S.run_stream(servers[name], ids[name], pool, S.draw_stream(min(500, n_requests), n_priors, 0.0, seed=8),
                      pace=False)
@@ -165,14 +166,17 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
                "served": one("served", stream), "plain": one("plain", stream)}
         if factor == 0.8:
             row["served_256MB"] = one("served_256MB", stream)
+            row["served_eager"] = one("served_eager", stream)
             out.update({"arrival_rate_req_per_s": stream_rate, "served": row["served"], "plain": row["plain"],
-                        "served_256MB": row["served_256MB"]})
+                        "served_256MB": row["served_256MB"], "served_eager": row["served_eager"]})
         out["rates"].append(row)
     # saturation: the stream back to back
     sat = servers["served"]
     _, bs, wall = S.run_stream(sat, ids["served"], pool, base, pace=False)
     out["served_saturated_req_per_s"] = n_requests / wall
     out["graph_captures"] = sat.stats()["graph_captures"]
+    _, _, wall = S.run_stream(servers["served_eager"], ids["served_eager"], pool, base, pace=False)
+    out["served_eager_saturated_req_per_s"] = n_requests / wall
     for srv in servers.values():
         srv.close()
     del plans, pool
