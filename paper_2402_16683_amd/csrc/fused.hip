@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_fwd(FusedArgs g) {
   const TS* xi = static_cast<const TS*>(g.xi) + b * g.n_xi;
   TS* ws = static_cast<TS*>(g.ws) + b * g.ws_bs;
   // every input is fetched in one round before any level is computed
-  for (int64_t i = t; i < g.pre; i += kFusedThreads) xl[i] = load_acc(xi + i);
+  copy_widen(xl, xi, g.pre, t, kFusedThreads);
   for (int l = 0; l < g.K; ++l) {
     for (int e = t; e < NC * NW; e += kFusedThreads) mats[l * (NC * NW + NC * NC) + e] = static_cast<const TA*>(g.r[l])[e];
     for (int e = t; e < NC * NC; e += kFusedThreads)
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_adj(FusedArgs g) {
   const bool add = g.add != nullptr;
   if (add) {  // fetched with the cotangent, in one round
     const TS* ag = static_cast<const TS*>(g.add) + b * g.n_xi;
-    for (int64_t i = t; i < g.pre; i += kFusedThreads) al[i] = load_acc(ag + i);
+    copy_widen(al, ag, g.pre, t, kFusedThreads);
   }
   TS* ws = static_cast<TS*>(g.ws) + b * g.ws_bs;
   for (int l = 0; l < g.K; ++l) {
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_adj(FusedArgs g) {
   {  // the cotangent of level K
     const TS* y = static_cast<const TS*>(g.y) + b * g.y_bs;
     TA* yk = level_lds(fields, g, g.K);
-    for (int64_t i = t; i < g.size[g.K]; i += kFusedThreads) yk[i] = load_acc(y + i);
+    copy_widen(yk, y, g.size[g.K], t, kFusedThreads);
   }
   __syncthreads();
   for (int l = g.K - 1; l >= 0; --l) {

@@ -1,6 +1,7 @@
 // C ABI of the ICR library: configuration checks, the plan (level sizes, offsets,
 // device matrices), and the level-by-level drivers of the forward sweep, its
 // adjoint and the metric. Declarations and contracts are in include/icr.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
