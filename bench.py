@@ -78,7 +78,7 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic(kernel_tag: str, digest: str):
-    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if recorded for this build."""
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if recorded for the current kernel sources."""
     path = os.path.join(PROFILES, "traffic.json")
     if not os.path.exists(path):
         return None
@@ -226,7 +226,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -20,7 +20,7 @@ The adjoint L^T is the exact transpose of that sweep, and the metric of a
 Gaussian likelihood in standardized coordinates is M = L^T N^-1 L + 1 (section
 "Performance of NIFTy.re compared to NIFTy": the Fisher metric plus the identity).
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   * children sit at +-delta/4 per axis around their coarse pixel, so the fine grid
     has spacing delta/2 and n_{l+1} = 2 (n_l - 2); border coarse pixels only take
     part in windows;
