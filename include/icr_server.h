@@ -9,7 +9,8 @@
  * contiguous batch, run the batched sweep (a hipGraph captured once per (plan, op, batch
  * size) when use_graphs is set and the batch needs at most 1/32 of the arena; larger
  * batches, whose launch overhead is small against their run time, launch eagerly),
- * scatter the outputs, record a completion event. Requests
+ * scatter the outputs, record a completion event (a single request without a graph
+ * runs the sweep on its own buffers, only its workspace taken from the arena). Requests
  * that arrive while others run are admitted as streams and memory free up, so batches of
  * different priors overlap on the device. max_batch = 1, n_streams = 1, use_graphs = 0 is
  * the one-launch-per-request baseline.

@@ -11,6 +11,8 @@
 //      contiguous batch, run the batched sweep (replaying a hipGraph captured once per
 //      (plan, op, batch size) when graphs are enabled and the batch needs at most 1/32 of
 //      the arena; larger batches launch eagerly), scatter the outputs, record an event.
+//      A single request without a graph runs the sweep on its own buffers (only its
+//      workspace comes from the arena).
 // Requests that arrive while others run join the queue and are admitted as streams and
 // memory free up, so batches of different priors overlap on the device. With
 // max_batch = 1, one stream and no graphs the same server is the one-launch-per-request
@@ -218,9 +220,36 @@ size_t batch_bytes(const PlanEntry& pe, int op, int k) {
   return b;
 }
 
-bool carve(icr_server* s, const PlanEntry& pe, int op, int k, Buffers* b) {
+// Allocate `bytes` of the arena; if it is full, evict idle captured graphs (least
+// recently used first) until the request fits. Fails only while the memory is held by
+// batches in flight, which retire and free it.
+void* alloc_evicting(icr_server* s, size_t bytes) {
+  if (void* p = s->arena.alloc(bytes)) return p;
+  std::vector<std::pair<double, std::tuple<int, int, int>>> idle;
+  for (auto& kv : s->graphs)
+    for (Graph* h : kv.second)
+      if (!h->busy) idle.push_back({h->last_used, kv.first});
+  std::sort(idle.begin(), idle.end());
+  for (auto& cand : idle) {
+    auto& l2 = s->graphs[cand.second];
+    for (size_t i = 0; i < l2.size(); ++i) {
+      if (!l2[i]->busy && l2[i]->last_used == cand.first) {
+        (void)hipGraphExecDestroy(l2[i]->exec);
+        s->arena.release(l2[i]->buf.in);
+        delete l2[i];
+        l2.erase(l2.begin() + i);
+        break;
+      }
+    }
+    if (void* p = s->arena.alloc(bytes)) return p;
+  }
+  return nullptr;
+}
+
+// contiguous batch buffers: inputs, outputs, workspace (and weights) of k requests
+bool carve_evicting(icr_server* s, const PlanEntry& pe, int op, int k, Buffers* b) {
   const size_t total = batch_bytes(pe, op, k);
-  char* p = static_cast<char*>(s->arena.alloc(total));
+  char* p = static_cast<char*>(alloc_evicting(s, total));
   if (!p) return false;
   b->bytes = total;
   b->in = p; p += up(size_t(k) * in_elems(pe, op) * pe.elem);
@@ -258,29 +287,6 @@ hipError_t copy_rows(const std::vector<const void*>& ptrs, void* contiguous, int
 // Carve a batch's buffers; if the arena is full, evict idle captured graphs (least
 // recently used first) until the buffers fit. Fails only while the memory is held by
 // batches in flight, which retire and free it.
-bool carve_evicting(icr_server* s, const PlanEntry& pe, int op, int k, Buffers* b) {
-  if (carve(s, pe, op, k, b)) return true;
-  std::vector<std::pair<double, std::tuple<int, int, int>>> idle;
-  for (auto& kv : s->graphs)
-    for (Graph* h : kv.second)
-      if (!h->busy) idle.push_back({h->last_used, kv.first});
-  std::sort(idle.begin(), idle.end());
-  for (auto& cand : idle) {
-    auto& l2 = s->graphs[cand.second];
-    for (size_t i = 0; i < l2.size(); ++i) {
-      if (!l2[i]->busy && l2[i]->last_used == cand.first) {
-        (void)hipGraphExecDestroy(l2[i]->exec);
-        s->arena.release(l2[i]->buf.in);
-        delete l2[i];
-        l2.erase(l2.begin() + i);
-        break;
-      }
-    }
-    if (carve(s, pe, op, k, b)) return true;
-  }
-  return false;
-}
-
 Graph* find_graph(icr_server* s, const PlanEntry& pe, int plan_id, int op, int k, hipStream_t st, bool* oom) {
   auto& list = s->graphs[std::make_tuple(plan_id, op, k)];
   for (Graph* g : list)
@@ -312,6 +318,35 @@ Graph* find_graph(icr_server* s, const PlanEntry& pe, int plan_id, int op, int k
   return g;
 }
 
+// Record the batch's completion event and book it as in flight on stream `si`.
+bool finish_launch(icr_server* s, int si, Batch* b, const std::vector<int64_t>& ids, hipError_t e) {
+  hipStream_t st = s->streams[si];
+  const int k = static_cast<int>(ids.size());
+  if (s->event_pool.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    s->event_pool.push_back(ev);
+  }
+  b->done = s->event_pool.back();
+  s->event_pool.pop_back();
+  if (e == hipSuccess && b->done) e = hipEventRecord(b->done, st);
+  if (e != hipSuccess) s->error = std::string("batch launch: ") + hipGetErrorString(e);
+  if (b->graph) {
+    b->graph->busy = true;
+    b->graph->last_used = now_s();
+  }
+  const double t = now_s();
+  for (int64_t id : ids) {
+    s->requests[id].t_launch = t;
+    s->requests[id].batch_size = k;
+  }
+  s->inflight[si] = b;
+  ++s->batches;
+  s->batched_requests += k;
+  return true;
+}
+
+
 // Launch one batch on stream `si`; returns false if it could not be admitted (memory).
 bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
   const Request& r0 = s->requests[ids[0]];
@@ -338,6 +373,24 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
       return false;
     }
     buf = b->graph->buf;
+  } else if (k == 1) {
+    // one request without a graph: sweep its own buffers, only the workspace comes from
+    // the arena (no gather or scatter launch)
+    const size_t bytes = up(size_t(std::max<int64_t>(ws_elems(pe, op), 1)) * pe.elem);
+    void* ws = alloc_evicting(s, bytes);
+    if (!ws) {
+      delete b;
+      return false;
+    }
+    b->buf.in = ws;  // the arena allocation, released when the batch retires
+    b->buf.bytes = bytes;
+    Buffers d;
+    d.in = const_cast<void*>(r0.in);
+    d.out = r0.out;
+    d.ws = ws;
+    d.w = const_cast<void*>(r0.w);
+    const hipError_t e = sweep(pe, op, 1, d, st) == ICR_OK ? hipSuccess : hipErrorLaunchFailure;
+    return finish_launch(s, si, b, ids, e);
   } else {
     if (!carve_evicting(s, pe, op, k, &b->buf)) {
       delete b;
@@ -359,28 +412,7 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
     else if (sweep(pe, op, k, buf, st) != ICR_OK) e = hipErrorLaunchFailure;
   }
   if (e == hipSuccess) e = copy_rows(out_ptrs, buf.out, out_elems(pe, op) * pe.elem, false, st);
-  if (s->event_pool.empty()) {
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-    s->event_pool.push_back(ev);
-  }
-  b->done = s->event_pool.back();
-  s->event_pool.pop_back();
-  if (e == hipSuccess && b->done) e = hipEventRecord(b->done, st);
-  if (e != hipSuccess) s->error = std::string("batch launch: ") + hipGetErrorString(e);
-  if (b->graph) {
-    b->graph->busy = true;
-    b->graph->last_used = now_s();
-  }
-  const double t = now_s();
-  for (int64_t id : ids) {
-    s->requests[id].t_launch = t;
-    s->requests[id].batch_size = k;
-  }
-  s->inflight[si] = b;
-  ++s->batches;
-  s->batched_requests += k;
-  return true;
+  return finish_launch(s, si, b, ids, e);
 }
 
 void retire(icr_server* s) {
