@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--workload", default="icr3d_m52_10to388")
     ap.add_argument("--precision", default=None, help="f32 or bf16 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes for the all-cores oracle baseline (0: skip it)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--levels", action="store_true", help="also time every level's kernels")
     ap.add_argument("--serve-requests", type=int, default=10000,
@@ -109,6 +111,60 @@ def cpu_baseline(wl: dict, quiet: bool):
     return {"value": model.out_size / dt, "unit": "fine px/s", "cores": 1, "kind": "oracle",
             "sample": f"one sample of the full workload ({'x'.join(map(str, model.shapes[-1]))} final "
                       f"pixels), forward + adjoint, numpy FP64, 1 thread, {dt:.1f} s"}
+
+
+def host_info() -> dict:
+    """CPU model, logical CPUs and memory of the host (Linux /proc)."""
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gb"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def _oracle_sample(args):
+    """One oracle forward + adjoint in a worker process, one thread; returns seconds."""
+    key, seed = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import icr_oracle as O
+    wl = W.WORKLOADS[key]
+    model = O.build(O.ICRConfig(ndim=wl["ndim"], shape0=wl["shape0"], depth=wl["depth"],
+                                delta0=wl["delta0"], kernel=wl["kernel"], scale=wl["scale"],
+                                length=wl["length"], chart=wl["chart"],
+                                chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966))))
+    xi = W.standard_normal(model.n_xi, seed=seed)
+    y = W.standard_normal(model.out_size, seed=seed + 1)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        model.forward(xi)
+        model.adjoint(y)
+        return time.perf_counter() - t0, model.out_size
+
+
+def cpu_baseline_parallel(key: str, workers: int, quiet: bool) -> dict:
+    """The oracle on `workers` host cores at once: one independent sample per process."""
+    import multiprocessing as mp
+    log(f"cpu baseline: {workers} oracle samples in parallel ...", quiet)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_sample, [(key, 100 + 2 * i) for i in range(workers)])
+    wall = time.perf_counter() - t0
+    px = sum(n for _, n in res)
+    return {"value": px / wall, "unit": "fine px/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} independent samples of the full workload, one per process and core, "
+                      f"numpy FP64, {wall:.1f} s wall (process start included)"}
 
 
 def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
@@ -228,6 +284,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    # the all-cores oracle baseline runs first, before this process touches the GPU: its
+    # worker processes start from a process without any device state
+    par = None
+    if not args.no_cpu_baseline and args.cpu_workers > 0 and not args.copy_probe:
+        par = cpu_baseline_parallel(args.workload, args.cpu_workers, args.quiet)
     import torch
 
     from paper_2402_16683_amd import icr as B
@@ -407,6 +468,9 @@ def main():
         out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.quiet)
+        out["cpu_baseline"]["host"] = host_info()
+        if par is not None:
+            out["cpu_baseline_all_cores"] = par
     print(json.dumps(out), flush=True)
 
 

@@ -76,6 +76,7 @@ def test_forward_matches_oracle_per_level(c):
     tol_rms, tol_max = C.TOL[c["precision"]]
     for l, (g, r) in enumerate(zip(got_levels, ref_levels)):
         rms, mx = C.rel_errors(g, r)
+        print(f"[errors] {c['name']} forward s level {l}: rel-RMS {rms:.2e} rel-max {mx:.2e}")
         assert np.all(np.isfinite(g)), f"level {l} has unwritten/non-finite values"
         assert rms <= tol_rms and mx <= tol_max, f"level {l}: rel-RMS {rms:.3g}, rel-max {mx:.3g}"
     if c["precision"] == "bf16":
@@ -102,6 +103,7 @@ def test_adjoint_matches_oracle_per_level(c):
     offs = info["level_offsets"]
     for l in range(c["depth"] + 1):
         rms, mx = C.rel_errors(got[..., offs[l]:offs[l + 1]], ref[..., offs[l]:offs[l + 1]])
+        print(f"[errors] {c['name']} adjoint xi_bar level {l}: rel-RMS {rms:.2e} rel-max {mx:.2e}")
         assert rms <= tol_rms and mx <= tol_max, f"xi_bar level {l}: rel-RMS {rms:.3g}, rel-max {mx:.3g}"
     cot = _levels(C.to_numpy(ws), info, c["depth"])
     for l in range(c["depth"]):
