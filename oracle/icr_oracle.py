@@ -29,7 +29,8 @@ Readings where the paper is silent:
   * sqrt(D) is the lower Cholesky factor, and a pivot <= tau = 3^d eps k(0) is
     clamped (its column set to zero and counted) instead of failing;
   * the log-radial chart maps index coordinates (u, v) to
-    (r0 e^(g u) cos(a v), r0 e^(g u) sin(a v)).
+    (r0 e^(g u) cos(a v), r0 e^(g u) sin(a v)); the log-radial cylinder chart maps
+    (u, v, w) to (r0 e^(g u) cos(a v), r0 e^(g u) sin(a v), h w).
 
 Every function here is pinned by a test in tests/test_oracle_*.py against closed
 forms, invariants or library routines; none is "parity unpinned".
@@ -46,7 +47,7 @@ import numpy as np
 EPS64 = float(np.finfo(np.float64).eps)
 
 KERNELS = ("matern12", "matern32", "matern52", "sqexp")
-CHARTS = ("regular", "logradial2d")
+CHARTS = ("regular", "logradial2d", "logradial_cyl3d")
 
 
 class NotPositiveDefinite(ValueError):
@@ -140,6 +141,20 @@ def logradial_chart(points: np.ndarray, params) -> np.ndarray:
     r = r0 * np.exp(g * points[..., 0])
     th = a * points[..., 1]
     return np.stack([r * np.cos(th), r * np.sin(th)], axis=-1)
+
+
+def logradial_cylinder_chart(points: np.ndarray, params) -> np.ndarray:
+    """Map index-space points (u, v, w) to (r cos theta, r sin theta, h w).
+
+    r = r0 exp(g u), theta = a v and height h w with params = (r0, g, a, h): the
+    log-radial chart of the plane extended by a linear axis.
+    """
+    if len(params) < 4:
+        raise ValueError("the log-radial cylinder chart takes (r0, g, a, h)")
+    r0, g, a, h = (float(v) for v in params[:4])
+    r = r0 * np.exp(g * points[..., 0])
+    th = a * points[..., 1]
+    return np.stack([r * np.cos(th), r * np.sin(th), h * points[..., 2]], axis=-1)
 
 
 # ---------------------------------------------------------------------------
@@ -348,6 +363,10 @@ def _positions(cfg: ICRConfig, idx_points: np.ndarray) -> np.ndarray:
         if cfg.ndim != 2:
             raise ValueError("the log-radial chart is two-dimensional")
         return logradial_chart(idx_points, cfg.chart_params)
+    if cfg.chart == "logradial_cyl3d":
+        if cfg.ndim != 3:
+            raise ValueError("the log-radial cylinder chart is three-dimensional")
+        return logradial_cylinder_chart(idx_points, cfg.chart_params)
     raise ValueError(f"unknown chart {cfg.chart!r}")
 
 
