@@ -21,7 +21,7 @@ struct KernelSpec {
 
 struct ChartSpec {
   int chart;
-  double p0, p1, p2;
+  double p0, p1, p2, p3;
 };
 
 __device__ double kernel_value(const KernelSpec& k, double r) {
@@ -36,7 +36,8 @@ __device__ double kernel_value(const KernelSpec& k, double r) {
   return k.sigma2 * v;
 }
 
-// index-space point -> physical point (D = 2 for the log-radial chart)
+// index-space point -> physical point (D = 2 for the log-radial chart, D = 3 for the
+// log-radial cylinder: the same map of the first two axes plus a scaled third axis)
 template <int D>
 __device__ void chart_map(const ChartSpec& c, const double* x, double* y) {
   if (D == 2 && c.chart == ICR_CHART_LOGRADIAL_2D) {
@@ -44,6 +45,12 @@ __device__ void chart_map(const ChartSpec& c, const double* x, double* y) {
     const double th = c.p2 * x[1];
     y[0] = r * cos(th);
     y[1] = r * sin(th);
+  } else if (D == 3 && c.chart == ICR_CHART_LOGRADIAL_CYL_3D) {
+    const double r = c.p0 * exp(c.p1 * x[0]);
+    const double th = c.p2 * x[1];
+    y[0] = r * cos(th);
+    y[1] = r * sin(th);
+    y[D - 1] = c.p3 * x[D - 1];
   } else {
     for (int a = 0; a < D; ++a) y[a] = x[a];
   }
@@ -142,10 +149,11 @@ struct LevelGeom {
   double spacing[3];  // delta_l per axis
   int interior[3];    // interior coarse pixels per axis (natural order)
   int64_t nsets;
+  int shell;          // one set per interior index of the first axis, at pixel (c, 1, 1)
 };
 
 // One thread per set: a stationary level has one set, a charted level one per
-// interior coarse pixel (C order).
+// interior coarse pixel (C order) or one per radial shell.
 template <int D>
 __global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, double tau, int clamp,
                                    double* __restrict__ r64, double* __restrict__ s64,
@@ -157,6 +165,8 @@ __global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, dou
   double centre[D];
   if (cs.chart == ICR_CHART_REGULAR) {
     for (int a = 0; a < D; ++a) centre[a] = 0.0;  // only relative positions matter
+  } else if (g.shell) {
+    for (int a = 0; a < D; ++a) centre[a] = g.origin[a] + (a == 0 ? set + 1 : 1) * g.spacing[a];
   } else {
     int64_t rem = set;
     for (int a = D - 1; a >= 0; --a) {
@@ -326,7 +336,7 @@ KernelSpec kernel_spec(const icr_plan* p) {
 }
 ChartSpec chart_spec(const icr_plan* p) {
   return ChartSpec{p->cfg.chart, p->cfg.chart_params[0], p->cfg.chart_params[1],
-                   p->cfg.chart_params[2]};
+                   p->cfg.chart_params[2], p->cfg.chart_params[3]};
 }
 double tau_of(const icr_plan* p) {
   double t = 2.220446049250313e-16 * p->cfg.scale * p->cfg.scale;
@@ -378,6 +388,7 @@ hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int
     g.interior[a] = a < d ? p->shapes[level][3 - d + a] - 2 : 1;
   }
   g.nsets = p->lev[level].nsets;
+  g.shell = p->shell;
   const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
   const unsigned threads = 64;
   const unsigned blocks = static_cast<unsigned>((g.nsets + threads - 1) / threads);

@@ -46,13 +46,21 @@ icr_status check_config(const icr_config* c) {
   if (c->depth < 0 || c->depth > ICR_MAX_DEPTH)
     return fail(ICR_ERR_INVALID_ARG, "depth must be in [0, " + std::to_string(ICR_MAX_DEPTH) + "]");
   if (c->kernel < ICR_MATERN12 || c->kernel > ICR_SQEXP) return fail(ICR_ERR_INVALID_ARG, "unknown kernel");
-  if (c->chart != ICR_CHART_REGULAR && c->chart != ICR_CHART_LOGRADIAL_2D)
+  if (c->chart != ICR_CHART_REGULAR && c->chart != ICR_CHART_LOGRADIAL_2D &&
+      c->chart != ICR_CHART_LOGRADIAL_CYL_3D)
     return fail(ICR_ERR_INVALID_ARG, "unknown chart");
   if (c->chart == ICR_CHART_LOGRADIAL_2D) {
     if (c->ndim != 2) return fail(ICR_ERR_INVALID_ARG, "the log-radial chart needs ndim == 2");
     if (!finite_pos(c->chart_params[0]) || !std::isfinite(c->chart_params[1]) ||
         !std::isfinite(c->chart_params[2]))
       return fail(ICR_ERR_INVALID_ARG, "log-radial chart needs r0 > 0 and finite growth/angle");
+  }
+  if (c->chart == ICR_CHART_LOGRADIAL_CYL_3D) {
+    if (c->ndim != 3) return fail(ICR_ERR_INVALID_ARG, "the log-radial cylinder chart needs ndim == 3");
+    if (!finite_pos(c->chart_params[0]) || !std::isfinite(c->chart_params[1]) ||
+        !std::isfinite(c->chart_params[2]) || !finite_pos(c->chart_params[3]))
+      return fail(ICR_ERR_INVALID_ARG,
+                  "log-radial cylinder chart needs r0 > 0, finite growth/angle and height scale > 0");
   }
   if (c->precision < ICR_F64 || c->precision > ICR_BF16_F32ACC)
     return fail(ICR_ERR_INVALID_ARG, "unknown precision");
@@ -237,6 +245,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   p->depth = cfg->depth;
   p->precision = cfg->precision;
   p->charted = cfg->chart != ICR_CHART_REGULAR;
+  p->shell = cfg->chart == ICR_CHART_LOGRADIAL_CYL_3D;
   p->elem_bytes = elem_bytes_of(cfg->precision);
   const int d = p->ndim;
   for (int l = 0; l < kMaxLevels; ++l)
@@ -278,7 +287,9 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   size_t off_lev[ICR_MAX_DEPTH][5];
   for (int l = 0; l < p->depth; ++l) {
     int64_t nsets = 1;
-    if (p->charted)
+    if (p->shell)
+      nsets = p->shapes[l][3 - d] - 2;  // one set per radial shell (first axis)
+    else if (p->charted)
       for (int a = 0; a < d; ++a) nsets *= p->shapes[l][3 - d + a] - 2;
     p->lev[l].nsets = nsets;
     off_lev[l][0] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * 8);
@@ -375,6 +386,7 @@ icr_status icr_plan_get_info(const icr_plan* p, icr_plan_info* info) {
   info->workspace_elems = p->n_xi - p->n_out;
   info->metric_workspace_elems = p->n_xi;
   info->device_bytes = p->pool_bytes;
+  for (int l = 0; l < p->depth; ++l) info->level_sets[l] = p->lev[l].nsets;
   return ICR_OK;
 }
 

@@ -69,7 +69,7 @@ struct LevelMats {
   double* s64 = nullptr;  // [nsets][2^d][2^d], lower triangular
   void* r_c = nullptr;    // arithmetic type; stationary: [2^d][3^d]; charted: [2^d*3^d][nsets]
   void* s_c = nullptr;    // arithmetic type; stationary: [2^d][2^d]; charted: [2^d*2^d][nsets]
-  int64_t nsets = 0;
+  int64_t nsets = 0;      // 1; per interior coarse pixel (2-D chart); per radial shell (cylinder)
   // Stationary levels: host copies of the FP32 matrices, passed to the fast kernels by
   // value, and the reflection-sector form of R (see sector_kernel in build_f64.hip).
   double* sector64 = nullptr;  // device scratch: [3^d] coefficients, [3^d] off-pattern, [3^d] on-pattern
@@ -92,7 +92,8 @@ struct icr_plan {
   int ndim = 0;
   int depth = 0;
   int precision = 0;
-  int charted = 0;
+  int charted = 0;   // matrices per pixel or per shell instead of one set per level
+  int shell = 0;     // charted with one set per interior coarse index along the first axis
   int device = 0;
   int shapes[icr::kMaxLevels][3];  // level shapes, axes beyond ndim are 1 (stored leading)
   int64_t offsets[icr::kMaxLevels + 1];

@@ -1,5 +1,5 @@
 // One ICR refinement level, general form: any d in {1,2,3}, any precision,
-// shared (stationary) or per-pixel (charted) matrices, any alignment.
+// shared (stationary), per-pixel or per-shell (charted) matrices, any alignment.
 //
 // Forward (one thread per interior coarse pixel c and sample):
 //   s_{l+1}[2(c-1)+b] = sum_w R[b,w] s_l[c+w] + sum_{b'<=b} sqrtD[b,b'] xi_{l+1}[2(c-1)+b']
@@ -17,7 +17,9 @@ struct Geom {
   int nc[3];  // coarse shape, natural axis order (first D used)
   int nf[3];  // fine shape
   int mi[3];  // interior coarse pixels per axis
-  int64_t nsets;  // charted: number of per-pixel matrix sets (= prod mi), else 1
+  int64_t nsets;  // interior coarse pixels (= prod mi)
+  int64_t msets;  // charted: matrix sets, the stride between a set's entries
+  int shell;      // charted with one set per interior index of the first axis
 };
 
 template <int D>
@@ -72,8 +74,8 @@ __global__ void __launch_bounds__(256) refine_fwd_generic(Geom g, RefineFwdArgs 
     fidx[ib] = lin<D>(q, g.nf);
     fresh[ib] = load_acc(xi + fidx[ib]);
   }
-  const int64_t stride = kCharted ? g.nsets : 1;
-  const int64_t base = kCharted ? t : 0;
+  const int64_t stride = kCharted ? g.msets : 1;
+  const int64_t base = kCharted ? (g.shell ? c[0] - 1 : t) : 0;
   for (int ib = 0; ib < NC; ++ib) {
     TA acc = 0;
     for (int iw = 0; iw < NW; ++iw) acc += R[(ib * NW + iw) * stride + base] * win[iw];
@@ -107,7 +109,7 @@ __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoars
     for (int ax = D - 1; ax >= 0; --ax) { p[ax] = static_cast<int>(rem % g.nc[ax]); rem /= g.nc[ax]; }
   }
   const TS* y = static_cast<const TS*>(a.y) + b * a.y_bs;
-  const int64_t stride = kCharted ? g.nsets : 1;
+  const int64_t stride = kCharted ? g.msets : 1;
 
   // coarse cotangent: gather the blocks c = p - w that read p at window slot w. A block
   // outside the interior is read at a clamped (in-bounds) position and weighted by zero,
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoars
       int ci[D];
 #pragma unroll
       for (int ax = 0; ax < D; ++ax) ci[ax] = c[ax] - 1;
-      set = lin<D>(ci, g.mi);
+      set = g.shell ? ci[0] : lin<D>(ci, g.mi);
     }
     TA part = 0;
 #pragma unroll
@@ -152,7 +154,7 @@ __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoars
   if (kCharted) {
     int ci[D];
     for (int ax = 0; ax < D; ++ax) ci[ax] = p[ax] - 1;
-    set = lin<D>(ci, g.mi);
+    set = g.shell ? ci[0] : lin<D>(ci, g.mi);
   }
   TA yb[NC];
   int64_t fidx[NC];
@@ -182,6 +184,8 @@ Geom geom_of(const icr_plan* p, int level) {
   }
   g.nsets = 1;
   for (int a = 0; a < d; ++a) g.nsets *= g.mi[a];
+  g.msets = p->lev[level].nsets;
+  g.shell = p->shell;
   return g;
 }
 

@@ -33,7 +33,7 @@ STATUS = {0: "ICR_OK", 1: "ICR_ERR_INVALID_ARG", 2: "ICR_ERR_NOT_PD", 3: "ICR_ER
           4: "ICR_ERR_OUT_OF_MEMORY", 5: "ICR_ERR_UNSUPPORTED"}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 KERNELS = {"matern12": 0, "matern32": 1, "matern52": 2, "sqexp": 3}
-CHARTS = {"regular": 0, "logradial2d": 1}
+CHARTS = {"regular": 0, "logradial2d": 1, "logradial_cyl3d": 2}
 FLAG_NO_CLAMP = 1
 
 
@@ -53,7 +53,8 @@ class IcrPlanInfo(ctypes.Structure):
                 ("level_offsets", ctypes.c_int64 * (ICR_MAX_DEPTH + 2)),
                 ("n_xi", ctypes.c_int64), ("n_out", ctypes.c_int64),
                 ("workspace_elems", ctypes.c_int64), ("metric_workspace_elems", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64),
+                ("level_sets", ctypes.c_int64 * ICR_MAX_DEPTH)]
 
 
 class ICRError(RuntimeError):
@@ -198,7 +199,8 @@ def icr_plan_get_info(plan: Plan) -> dict:
         level_shapes=[tuple(info.level_shapes[l][a] for a in range(info.ndim)) for l in range(depth + 1)],
         level_offsets=[info.level_offsets[l] for l in range(depth + 2)],
         n_xi=info.n_xi, n_out=info.n_out, workspace_elems=info.workspace_elems,
-        metric_workspace_elems=info.metric_workspace_elems, device_bytes=info.device_bytes)
+        metric_workspace_elems=info.metric_workspace_elems, device_bytes=info.device_bytes,
+        level_sets=[info.level_sets[l] for l in range(depth)])
 
 
 def icr_plan_copy_level0(plan: Plan) -> np.ndarray:
@@ -209,11 +211,9 @@ def icr_plan_copy_level0(plan: Plan) -> np.ndarray:
 
 
 def icr_plan_copy_refinement(plan: Plan, level: int):
+    """R_l and sqrtD_l in FP64: one pair on a regular grid, else (level_sets[l], ...)."""
     d = plan.info["ndim"]
-    nsets = 1
-    if plan.info["chart"] != 0:
-        for n in plan.info["level_shapes"][level]:
-            nsets *= n - 2
+    nsets = plan.info["level_sets"][level]
     r = np.empty((nsets, 2 ** d, 3 ** d), dtype=np.float64)
     s = np.empty((nsets, 2 ** d, 2 ** d), dtype=np.float64)
     _check(load_library().icr_plan_copy_refinement(plan.handle, level, r.ctypes.data_as(ctypes.c_void_p),
@@ -234,10 +234,7 @@ def icr_plan_set_level0(plan: Plan, l00: np.ndarray, stream=None):
 
 def icr_plan_set_refinement(plan: Plan, level: int, r: np.ndarray, sqrtd: np.ndarray, stream=None):
     d = plan.info["ndim"]
-    nsets = 1
-    if plan.info["chart"] != 0:
-        for n in plan.info["level_shapes"][level]:
-            nsets *= n - 2
+    nsets = plan.info["level_sets"][level]
     ra = np.ascontiguousarray(np.reshape(r, (nsets, 2 ** d, 3 ** d)), dtype=np.float64)
     sa = np.ascontiguousarray(np.reshape(sqrtd, (nsets, 2 ** d, 2 ** d)), dtype=np.float64)
     _check(load_library().icr_plan_set_refinement(plan.handle, level, ra.ctypes.data_as(ctypes.c_void_p),

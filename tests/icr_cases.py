@@ -51,6 +51,22 @@ def gpu_plan(c, precision=None):
     return B.icr_build_matrices(cfg)
 
 
+def chart_positions(c, pts: np.ndarray) -> np.ndarray:
+    """Physical positions of index-space points under the case's chart (oracle maps)."""
+    if c["chart"] == "regular":
+        return pts
+    if c["chart"] == "logradial2d":
+        return O.logradial_chart(pts, c["chart_params"])
+    if c["chart"] == "logradial_cyl3d":
+        return O.logradial_cylinder_chart(pts, c["chart_params"])
+    raise ValueError(c["chart"])
+
+
+def is_shell(model) -> bool:
+    """Cylinder-chart models: the device keeps one matrix set per radial shell."""
+    return model.cfg.chart == "logradial_cyl3d"
+
+
 def rel_errors(got: np.ndarray, ref: np.ndarray):
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
@@ -82,13 +98,25 @@ def stored_values(a: np.ndarray, precision: str) -> np.ndarray:
 
 
 def upload_oracle_matrices(plan, model):
-    """Give the device plan the oracle's FP64 matrices (sweep-only comparisons)."""
+    """Give the device plan the oracle's FP64 matrices (sweep-only comparisons).
+
+    For a cylinder-chart model the device holds one set per radial shell: it gets the
+    oracle's set at pixel (u, 1, 1) of each shell, and the model's per-pixel sets are
+    replaced by those shell sets broadcast along the other axes, so that both sides
+    apply identical matrices."""
     from paper_2402_16683_amd import icr as B
     B.icr_plan_set_level0(plan, model.l00)
     d = model.cfg.ndim
     for l in range(model.cfg.depth):
-        r = np.reshape(model.r_mats[l], (-1, 2 ** d, 3 ** d))
-        s = np.reshape(model.sqrt_ds[l], (-1, 2 ** d, 2 ** d))
+        if is_shell(model):
+            r_sh = model.r_mats[l][:, 0, 0]
+            s_sh = model.sqrt_ds[l][:, 0, 0]
+            model.r_mats[l] = np.ascontiguousarray(np.broadcast_to(r_sh[:, None, None], model.r_mats[l].shape))
+            model.sqrt_ds[l] = np.ascontiguousarray(np.broadcast_to(s_sh[:, None, None], model.sqrt_ds[l].shape))
+            r, s = r_sh, s_sh
+        else:
+            r = np.reshape(model.r_mats[l], (-1, 2 ** d, 3 ** d))
+            s = np.reshape(model.sqrt_ds[l], (-1, 2 ** d, 2 ** d))
         B.icr_plan_set_refinement(plan, l, r, s)
 
 

@@ -34,7 +34,8 @@ def test_struct_layout_matches_the_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(icr_config), offsetof(icr_config, distances0),
          offsetof(icr_config, chart_params), sizeof(icr_plan_info), offsetof(icr_plan_info, n_xi));
-  printf("%zu %zu\n", offsetof(icr_plan_info, level_offsets), offsetof(icr_plan_info, device_bytes));
+  printf("%zu %zu %zu\n", offsetof(icr_plan_info, level_offsets), offsetof(icr_plan_info, device_bytes),
+         offsetof(icr_plan_info, level_sets));
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -43,7 +44,8 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.IcrConfig), B.IcrConfig.distances0.offset,
                     B.IcrConfig.chart_params.offset, ctypes.sizeof(B.IcrPlanInfo), B.IcrPlanInfo.n_xi.offset,
-                    B.IcrPlanInfo.level_offsets.offset, B.IcrPlanInfo.device_bytes.offset]
+                    B.IcrPlanInfo.level_offsets.offset, B.IcrPlanInfo.device_bytes.offset,
+                    B.IcrPlanInfo.level_sets.offset]
 
 
 def _build_status(**over):
@@ -66,6 +68,9 @@ def _build_status(**over):
     (dict(kernel=7), "kernel"),
     (dict(chart=5), "chart"),
     (dict(ndim=3, shape0=(5, 5, 5), distances0=(0.1,) * 3, chart="logradial2d"), "log-radial"),
+    (dict(chart="logradial_cyl3d", chart_params=(0.1, 2.3, 1.5, 1.0)), "cylinder chart needs ndim == 3"),
+    (dict(ndim=3, shape0=(5, 5, 5), distances0=(0.1,) * 3, chart="logradial_cyl3d",
+          chart_params=(0.1, 2.3, 1.5, 0.0)), "height scale"),
     (dict(precision=9), "precision"),
 ])
 def test_invalid_configs_are_rejected_before_any_device_work(over, needle):

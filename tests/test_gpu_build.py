@@ -28,23 +28,35 @@ CASES = [
     C.from_workload("icr2d_chart_24to1284", depth=4, name="2d_chart_24to324"),
     C.case(1, (7,), 6, (0.1,), "sqexp", 0.4, name="1d_se_deep"),
     C.case(3, (4, 5, 6), 2, (0.2, 0.15, 0.1), "matern12", 0.3, name="3d_m12_ragged"),
+    C.from_workload("icr3d_chart_10to388", depth=3, name="3d_chart_10to52"),
+    C.case(3, (6, 7, 5), 2, (1 / 6, 1 / 7, 1 / 5), "matern52", 0.2, chart="logradial_cyl3d",
+           chart_params=(0.2, 1.5, 1.2, 0.7), name="3d_chart_ragged"),
 ]
 
 
 def _window_geometry(c, model, level):
-    """Physical window / child positions of every set of a level (oracle geometry)."""
+    """Physical window / child positions of every set the device keeps for a level
+    (oracle geometry) and the oracle's matrices of the same sets. The cylinder chart
+    keeps one set per radial shell u, built at pixel (u, 1, 1)."""
     d = c["ndim"]
     spac = O.level_spacings(c["delta0"], c["depth"])[level]
     org = O.level_origins(c["delta0"], c["depth"])[level]
     wins = O.window_offsets(d).astype(float)
     kids = O.child_offsets(d).astype(float)
     if c["chart"] == "regular":
-        return (wins * spac)[None], ((kids - 0.5) * spac / 2)[None]
+        return (wins * spac)[None], ((kids - 0.5) * spac / 2)[None], model.r_mats[level], model.sqrt_ds[level]
     n_int = tuple(n - 2 for n in model.shapes[level])
-    centre = org + (O.grid_indices(n_int) + 1) * spac
-    wp = O.logradial_chart(centre[:, None, :] + wins[None] * spac, c["chart_params"])
-    kp = O.logradial_chart(centre[:, None, :] + (kids[None] - 0.5) * spac / 2, c["chart_params"])
-    return wp, kp
+    if C.is_shell(model):
+        idx = np.ones((n_int[0], d))
+        idx[:, 0] = np.arange(1, n_int[0] + 1)
+        r_ora, s_ora = model.r_mats[level][:, 0, 0], model.sqrt_ds[level][:, 0, 0]
+    else:
+        idx = O.grid_indices(n_int) + 1
+        r_ora, s_ora = model.r_mats[level], model.sqrt_ds[level]
+    centre = org + idx * spac
+    wp = C.chart_positions(c, centre[:, None, :] + wins[None] * spac)
+    kp = C.chart_positions(c, centre[:, None, :] + (kids[None] - 0.5) * spac / 2)
+    return wp, kp, r_ora, s_ora
 
 
 @pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
@@ -57,7 +69,8 @@ def test_refinement_matrices_by_residuals_and_effect(c):
         r_gpu, s_gpu = B.icr_plan_copy_refinement(plan, l)
         r_gpu = r_gpu.reshape(-1, 2 ** c["ndim"], 3 ** c["ndim"])
         s_gpu = s_gpu.reshape(-1, 2 ** c["ndim"], 2 ** c["ndim"])
-        wp, kp = _window_geometry(c, model, l)
+        wp, kp, r_mod, s_mod = _window_geometry(c, model, l)
+        assert r_gpu.shape[0] == plan.info["level_sets"][l] == wp.shape[0]
         k = lambda a, b: O.kernel_values(c["kernel"], O.pairwise_distance(a, b), c["scale"], c["length"])
         kcc, kfc, kff = k(wp, wp), k(kp, wp), k(kp, kp)
         # backward-stable solve: residual ~ eps |K_cc| |R|
@@ -68,13 +81,13 @@ def test_refinement_matrices_by_residuals_and_effect(c):
         d_err = np.abs(s_gpu @ np.swapaxes(s_gpu, -1, -2) - d_gpu).max()
         assert d_err <= 10 * tau + 100 * EPS * c["scale"] ** 2, f"level {l}: sqrtD residual {d_err:.3g}"
         assert np.allclose(np.triu(s_gpu, 1), 0.0) and np.all(np.diagonal(s_gpu, axis1=-2, axis2=-1) >= 0)
-        r_ora = np.reshape(model.r_mats[l], r_gpu.shape)
+        r_ora = np.reshape(r_mod, r_gpu.shape)
         dr = r_gpu - r_ora
         num = np.einsum("sbw,swv,sbv->s", dr, kcc, dr)
         den = np.einsum("sbw,swv,sbv->s", r_ora, kcc, r_ora)
         eff = np.sqrt(np.max(num / den))
         assert eff <= 1e-9, f"level {l}: effect of R differs by {eff:.3g}"
-        s_ora = np.reshape(model.sqrt_ds[l], s_gpu.shape)
+        s_ora = np.reshape(s_mod, s_gpu.shape)
         cov_gpu = s_gpu @ np.swapaxes(s_gpu, -1, -2)
         cov_ora = s_ora @ np.swapaxes(s_ora, -1, -2)
         assert np.abs(cov_gpu - cov_ora).max() <= 10 * tau + 1e3 * EPS * c["scale"] ** 2
@@ -88,8 +101,7 @@ def test_level0_factor(c):
     l00 = B.icr_plan_copy_level0(plan)
     assert np.allclose(np.triu(l00, 1), 0.0)
     pos = O.grid_indices(c["shape0"]) * np.asarray(c["delta0"])
-    if c["chart"] != "regular":
-        pos = O.logradial_chart(pos, c["chart_params"])
+    pos = C.chart_positions(c, pos)
     k00 = O.kernel_values(c["kernel"], O.pairwise_distance(pos, pos), c["scale"], c["length"])
     n = k00.shape[0]
     assert np.abs(l00 @ l00.T - k00).max() <= 1e3 * n * EPS * c["scale"] ** 2

@@ -1,0 +1,155 @@
+"""The 3-D log-radial cylinder chart at its full size (10^3 -> 388^3, FP32), checked on
+sampled blocks against matrices the oracle builds for those pixels alone.
+
+The full per-pixel oracle model would need one matrix set per interior coarse pixel
+(7.3 million at the last level), so each level is checked in isolation: the device's
+own input of the level (the previous level's field from the forward workspace, or
+the fine cotangent from the adjoint workspace) and the oracle's R and sqrtD of the
+sampled pixel, conditioned on the charted positions of its window and children,
+give the expected fine block (forward) or excitation and coarse cotangents
+(adjoint) in FP64. This covers the per-shell storage of the matrices, the device
+build at every shell and the kernels that apply them at the launch configuration
+the benchmark times. Tolerances: FP32 rounding of the stored matrices and of sums of
+35 (forward block), 8 (excitation cotangent), up to 216 (coarse cotangent) and 1000
+(level 0) products, relative to the sum of the magnitudes of the terms; a set taken
+from a neighbouring shell is off by ~1e-3.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import icr_oracle as O
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+CASE = C.from_workload("icr3d_chart_10to388", name="3d_chart_full_f32")
+WINS = O.window_offsets(3)
+KIDS = O.child_offsets(3)
+
+_state = {}
+
+
+def _oracle_set(level, cidx):
+    """Oracle R (8 x 27) and sqrtD (8 x 8) of interior coarse pixel cidx of a level."""
+    spac = O.level_spacings(CASE["delta0"], CASE["depth"])[level]
+    org = O.level_origins(CASE["delta0"], CASE["depth"])[level]
+    centre = org + np.asarray(cidx, dtype=float) * spac
+    wp = C.chart_positions(CASE, centre + WINS * spac)
+    kp = C.chart_positions(CASE, centre + (KIDS - 0.5) * spac / 2)
+    tau = O.pivot_threshold(3, CASE["scale"])
+    r, s, _ = O.conditional_matrices(CASE["kernel"], CASE["scale"], CASE["length"], wp, kp, tau)
+    return r, s
+
+
+def _samples(shape, n, seed):
+    """Interior coarse pixels: the eight corners of the interior box plus random ones."""
+    rng = np.random.default_rng(seed)
+    lo, hi = (1, 1, 1), tuple(v - 2 for v in shape)
+    pts = [tuple(c) for c in itertools.product(*zip(lo, hi))]
+    pts += [tuple(int(rng.integers(1, v - 1)) for v in shape) for _ in range(n)]
+    return pts
+
+
+def _block(field, c):
+    return field[2 * (c[0] - 1):2 * c[0], 2 * (c[1] - 1):2 * c[1], 2 * (c[2] - 1):2 * c[2]].reshape(8)
+
+
+def _window(field, c):
+    return field[c[0] - 1:c[0] + 2, c[1] - 1:c[1] + 2, c[2] - 1:c[2] + 2].reshape(27)
+
+
+def _setup():
+    if not _state:
+        import torch
+        from paper_2402_16683_amd import icr as B
+        plan = C.gpu_plan(CASE)
+        info = plan.info
+        assert info["level_sets"] == [s[0] - 2 for s in info["level_shapes"][:-1]]
+        xi = W.standard_normal_f32(info["n_xi"], seed=0)
+        y = W.standard_normal_f32(info["n_out"], seed=1)
+        xi_d = torch.from_numpy(xi).cuda()
+        y_d = torch.from_numpy(y).cuda()
+        ws_f = torch.full((info["workspace_elems"],), float("nan"), dtype=torch.float32, device="cuda")
+        ws_a = torch.full_like(ws_f, float("nan"))
+        s = B.icr_forward(plan, xi_d, workspace=ws_f)
+        xb = B.icr_adjoint(plan, y_d, workspace=ws_a)
+        torch.cuda.synchronize()
+        offs = info["level_offsets"]
+        shapes = info["level_shapes"]
+        fields, cots, xis, xbars = [], [], [], []
+        ws_f, ws_a, s, xb = (t.cpu().numpy().astype(np.float64) for t in (ws_f, ws_a, s, xb))
+        for l in range(CASE["depth"] + 1):
+            sl = slice(offs[l], offs[l + 1])
+            xis.append(xi[sl].astype(np.float64).reshape(shapes[l]))
+            xbars.append(xb[sl].reshape(shapes[l]))
+            if l < CASE["depth"]:
+                fields.append(ws_f[sl].reshape(shapes[l]))
+                cots.append(ws_a[sl].reshape(shapes[l]))
+        fields.append(s.reshape(shapes[-1]))
+        cots.append(y.astype(np.float64).reshape(shapes[-1]))
+        _state.update(plan=plan, fields=fields, cots=cots, xis=xis, xbars=xbars, shapes=shapes)
+    return _state
+
+
+@pytest.mark.parametrize("level", [0, 3, 5])
+def test_forward_blocks_match_the_oracle_matrices(level):
+    st = _setup()
+    coarse, fine, xi_f = st["fields"][level], st["fields"][level + 1], st["xis"][level + 1]
+    worst = 0.0
+    for c in _samples(st["shapes"][level], 40, seed=level):
+        r, s = _oracle_set(level, c)
+        win, fresh = _window(coarse, c), _block(xi_f, c)
+        expect = r @ win + s @ fresh
+        scale = np.abs(r) @ np.abs(win) + np.abs(s) @ np.abs(fresh)
+        err = np.max(np.abs(_block(fine, c) - expect) / scale)
+        worst = max(worst, err)
+    print(f"[errors] chart3d forward level {level}->{level + 1}: max |err| / (|R||s| + |S||xi|) {worst:.2e}")
+    assert worst <= 5e-6
+
+
+@pytest.mark.parametrize("level", [0, 3, 5])
+def test_adjoint_blocks_match_the_oracle_matrices(level):
+    st = _setup()
+    y_f = st["cots"][level + 1]
+    nc = st["shapes"][level]
+    worst_xi = worst_s = 0.0
+    for p in _samples(nc, 30, seed=10 + level):
+        # excitation cotangent of the block spawned by p
+        r, s = _oracle_set(level, p)
+        yb = _block(y_f, p)
+        err = np.max(np.abs(_block(st["xbars"][level + 1], p) - s.T @ yb) / (np.abs(s.T) @ np.abs(yb)))
+        worst_xi = max(worst_xi, err)
+        # coarse cotangent of p: every interior block c = p - w that reads p at slot w
+        acc = mag = 0.0
+        for iw, w in enumerate(WINS):
+            c = tuple(int(v) for v in np.asarray(p) - w)
+            if not all(1 <= c[a] <= nc[a] - 2 for a in range(3)):
+                continue
+            rc, _ = _oracle_set(level, c)
+            yc = _block(y_f, c)
+            acc += rc[:, iw] @ yc
+            mag += np.abs(rc[:, iw]) @ np.abs(yc)
+        got = st["cots"][level][p]
+        worst_s = max(worst_s, abs(got - acc) / mag)
+    print(f"[errors] chart3d adjoint level {level + 1}->{level}: xi_bar {worst_xi:.2e}, s_bar {worst_s:.2e}")
+    assert worst_xi <= 5e-6 and worst_s <= 1e-5
+
+
+def test_level0_and_sets_per_shell():
+    st = _setup()
+    model0 = O.build(O.ICRConfig(ndim=3, shape0=CASE["shape0"], depth=0, delta0=CASE["delta0"],
+                                 kernel=CASE["kernel"], length=CASE["length"], chart=CASE["chart"],
+                                 chart_params=CASE["chart_params"]))
+    expect = model0.l00 @ st["xis"][0].reshape(-1)
+    got = st["fields"][0].reshape(-1)
+    scale = np.abs(model0.l00) @ np.abs(st["xis"][0].reshape(-1))
+    assert np.max(np.abs(got - expect) / scale) <= 1e-5
+    from paper_2402_16683_amd import icr as B
+    r_gpu, _ = B.icr_plan_copy_refinement(st["plan"], 5)
+    assert r_gpu.shape == (194, 8, 27)
+    # the shells differ (the chart is not stationary along its radial axis)
+    assert np.max(np.abs(r_gpu[0] - r_gpu[-1])) > 1e-3

@@ -39,6 +39,11 @@ CASES = [
     C.case(1, (7,), 4, (0.1,), "sqexp", 0.4, batch=4, name="1d_se_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=3, name="2d_chart_24to164_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=2, precision="f64", name="2d_chart_24to84_f64"),
+    C.from_workload("icr3d_chart_10to388", depth=3, name="3d_chart_10to52_f32"),
+    C.from_workload("icr3d_chart_10to388", depth=3, precision="bf16", name="3d_chart_10to52_bf16"),
+    C.from_workload("icr3d_chart_10to388", depth=2, precision="f64", name="3d_chart_10to28_f64"),
+    C.case(3, (6, 7, 5), 2, (1 / 6, 1 / 7, 1 / 5), "matern52", 0.2, chart="logradial_cyl3d",
+           chart_params=(0.2, 1.5, 1.2, 0.7), batch=2, name="3d_chart_ragged_f32"),
     C.case(2, (6, 6), 0, (0.2, 0.2), "matern52", 0.5, batch=2, name="2d_depth0_f32"),
     C.case(3, (3, 3, 3), 1, (0.2, 0.2, 0.2), "matern52", 0.5, precision="f64", name="3d_min_f64"),
 ]

@@ -22,6 +22,9 @@ CASES = [
     C.from_workload("icr3d_m52_10to388", depth=4, batch=2, name="3d_m52_10to100_b2_f32"),
     C.from_workload("icr3d_m52_10to388", depth=4, precision="bf16", name="3d_m52_10to100_bf16"),
     C.from_workload("icr2d_chart_24to1284", depth=4, name="2d_chart_24to324_f32"),
+    C.from_workload("icr3d_chart_10to388", depth=4, batch=2, name="3d_chart_10to100_b2_f32"),
+    C.from_workload("icr3d_chart_10to388", depth=3, precision="bf16", name="3d_chart_10to52_bf16"),
+    C.from_workload("icr3d_chart_10to388", depth=3, precision="f64", name="3d_chart_10to52_f64"),
     C.case(3, (4, 5, 6), 3, (0.2, 0.15, 0.1), "sqexp", 0.5, precision="f64", name="3d_se_ragged_f64"),
 ]
 

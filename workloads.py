@@ -37,6 +37,13 @@ WORKLOADS = {
                                  chart="logradial2d",
                                  chart_params=(0.1, math.log(10.0), 0.5 * math.pi),
                                  precision="f32"),
+    # 3-D log-radial cylinder chart (radius 0.1 -> 1 over the level-0 box, a quarter
+    # turn, height 1), Matern-3/2 length 0.05 (physical units), 10^3 -> 388^3
+    "icr3d_chart_10to388": dict(ndim=3, shape0=(10, 10, 10), depth=6, delta0=(0.1,) * 3,
+                                kernel="matern32", scale=1.0, length=0.05, batch=1,
+                                chart="logradial_cyl3d",
+                                chart_params=(0.1, math.log(10.0), 0.5 * math.pi, 1.0),
+                                precision="f32"),
 }
 
 
