@@ -331,6 +331,54 @@ __global__ void sector_kernel(const double* __restrict__ r64, double* __restrict
   out[2 * NW + t] = on;
 }
 
+// Shell-charted 3-D levels (one set per coarse plane): R is invariant under reflecting
+// the second and third axes (angle and height of the cylinder chart) but not the
+// first. Transforming only those two axes as in sector_kernel, M = Q_yx R P_yx^-1
+// couples child sector (sy, sx) of z-child bz only with the window channels
+// (wz, ty, tx) of the matching pattern, so R = B_yx C P_yx with 2 x 3 x 9 coefficients
+// C[ty tx][bz][wz] = M / 4 (B_yx the butterflies of the two axes; the six values of a
+// channel are adjacent). One thread per set writes C and sqrtD (packed by rows) to the
+// FP32 table tab[set][kShellStride] and
+// the largest off-pattern and on-pattern |M| of the set to chk[set][2].
+__global__ void shell_sector_kernel(const double* __restrict__ r64, const double* __restrict__ s64,
+                                    int64_t nsets, float* __restrict__ tab, double* __restrict__ chk) {
+  const int64_t set = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (set >= nsets) return;
+  const double pinv[3][3] = {{0.5, 0.0, -0.5}, {0.0, 1.0, 0.0}, {0.5, 0.0, 0.5}};
+  const double* R = r64 + set * 8 * 27;
+  float* out = tab + set * kShellStride;
+  double off = 0.0, on = 0.0;
+  for (int bz = 0; bz < 2; ++bz)
+    for (int wz = 0; wz < 3; ++wz)
+      for (int ty = 0; ty < 3; ++ty)
+        for (int tx = 0; tx < 3; ++tx) {
+          const int own = ((ty == 2) << 1) | (tx == 2);
+          double coef = 0.0;
+          for (int sg = 0; sg < 4; ++sg) {
+            const int sy = sg >> 1, sx = sg & 1;
+            double m = 0.0;
+            for (int by = 0; by < 2; ++by)
+              for (int bx = 0; bx < 2; ++bx) {
+                const double q = ((sy == 1 && by == 0) ? -1.0 : 1.0) * ((sx == 1 && bx == 0) ? -1.0 : 1.0);
+                for (int wy = 0; wy < 3; ++wy)
+                  for (int wx = 0; wx < 3; ++wx) {
+                    const double pv = pinv[wy][ty] * pinv[wx][tx];
+                    if (pv != 0.0) m += q * R[(bz * 4 + by * 2 + bx) * 27 + wz * 9 + wy * 3 + wx] * pv;
+                  }
+              }
+            if (sg == own) { on = fmax(on, fabs(m)); coef = m / 4.0; }
+            else off = fmax(off, fabs(m));
+          }
+          out[(ty * 3 + tx) * 6 + bz * 3 + wz] = static_cast<float>(coef);
+        }
+  const double* S = s64 + set * 64;
+  for (int c = 0; c < 8; ++c)
+    for (int cp = 0; cp <= c; ++cp) out[54 + c * (c + 1) / 2 + cp] = static_cast<float>(S[c * 8 + cp]);
+  for (int e = 90; e < kShellStride; ++e) out[e] = 0.0f;
+  chk[2 * set] = off;
+  chk[2 * set + 1] = on;
+}
+
 KernelSpec kernel_spec(const icr_plan* p) {
   return KernelSpec{p->cfg.kernel, p->cfg.scale * p->cfg.scale, p->cfg.length};
 }
@@ -429,6 +477,14 @@ hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st) {
     case 2: sector_kernel<2><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
     default: sector_kernel<3><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_sector(const icr_plan* p, int level, hipStream_t st) {
+  const LevelMats& m = p->lev[level];
+  const unsigned threads = 64;
+  const unsigned blocks = static_cast<unsigned>((m.nsets + threads - 1) / threads);
+  shell_sector_kernel<<<blocks, threads, 0, st>>>(m.r64, m.s64, m.nsets, m.shell_tab, m.shell_chk);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "host_checks.h"
 #include "icr_internal.h"
@@ -190,6 +191,21 @@ icr_status refresh_host_copies(icr_plan* p, int level) {
   icr::LevelMats& m = p->lev[level];
   m.sector_ok = false;
   m.sector_asym = 1.0;
+  m.shell_ok = false;
+  m.shell_asym = 1.0;
+  if (p->shell && p->precision != ICR_F64) {
+    std::vector<double> chk(static_cast<size_t>(2 * m.nsets));
+    ICR_HIP_TRY(hipMemcpy(chk.data(), m.shell_chk, sizeof(double) * chk.size(), hipMemcpyDeviceToHost));
+    double worst = 0.0;
+    for (int64_t s = 0; s < m.nsets; ++s) {
+      const double off = chk[2 * s], on = chk[2 * s + 1];
+      worst = std::fmax(worst, on > 0.0 ? off / on : 1.0);
+      if (!std::isfinite(off) || !std::isfinite(on)) worst = 1.0;
+    }
+    m.shell_asym = worst;
+    m.shell_ok = worst <= icr::kSectorTolerance;
+    return ICR_OK;
+  }
   if (p->charted || p->precision == ICR_F64) return ICR_OK;
   const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
   ICR_HIP_TRY(hipMemcpy(m.h_r, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost));
@@ -284,7 +300,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   const size_t off_l64 = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * 8);
   const size_t off_lc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
   const size_t off_uc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
-  size_t off_lev[ICR_MAX_DEPTH][5];
+  size_t off_lev[ICR_MAX_DEPTH][7];
   for (int l = 0; l < p->depth; ++l) {
     int64_t nsets = 1;
     if (p->shell)
@@ -297,6 +313,9 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][2] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * ab);
     off_lev[l][3] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * ab);
     off_lev[l][4] = bytes; bytes = align_up(bytes + size_t(3) * nw * 8);
+    const int64_t shell_sets = p->shell ? nsets : 0;
+    off_lev[l][5] = bytes; bytes = align_up(bytes + size_t(shell_sets) * icr::kShellStride * 4);
+    off_lev[l][6] = bytes; bytes = align_up(bytes + size_t(shell_sets) * 2 * 8);
   }
   const size_t off_status = bytes; bytes = align_up(bytes + sizeof(int32_t) * (kMaxLevels + 1));
 
@@ -318,6 +337,10 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     p->lev[l].r_c = base + off_lev[l][2];
     p->lev[l].s_c = base + off_lev[l][3];
     p->lev[l].sector64 = reinterpret_cast<double*>(base + off_lev[l][4]);
+    if (p->shell) {
+      p->lev[l].shell_tab = reinterpret_cast<float*>(base + off_lev[l][5]);
+      p->lev[l].shell_chk = reinterpret_cast<double*>(base + off_lev[l][6]);
+    }
   }
   int32_t* status = reinterpret_cast<int32_t*>(base + off_status);
   int32_t* counts = status + 1;
@@ -341,6 +364,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     BUILD_TRY(icr::launch_build_level(p, l, counts + 1 + l, status, st));
     BUILD_TRY(icr::launch_level_convert(p, l, st));
     if (!p->charted) BUILD_TRY(icr::launch_sector(p, l, st));
+    if (p->shell) BUILD_TRY(icr::launch_shell_sector(p, l, st));
   }
   int32_t host_status[kMaxLevels + 1];
   BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
@@ -430,6 +454,7 @@ icr_status icr_plan_set_refinement(icr_plan* p, int32_t level, const double* r, 
   ICR_HIP_TRY(hipMemcpyAsync(m.s64, sqrtd, size_t(m.nsets) * nc * nc * 8, hipMemcpyHostToDevice, st));
   ICR_HIP_TRY(icr::launch_level_convert(p, level, st));
   if (!p->charted) ICR_HIP_TRY(icr::launch_sector(p, level, st));
+  if (p->shell) ICR_HIP_TRY(icr::launch_shell_sector(p, level, st));
   ICR_HIP_TRY(hipStreamSynchronize(st));
   return refresh_host_copies(p, level);
 }

@@ -78,7 +78,16 @@ struct LevelMats {
   float h_sector[27];
   double sector_asym = 1.0;    // max off-pattern / max on-pattern entry of Q R P^-1
   bool sector_ok = false;      // R is reflection-symmetric to FP32 precision
+  // Shell-charted 3-D levels: per set the reflection-sector coefficients of the second
+  // and third axes with the first kept dense, and sqrtD (see shell_sector_kernel).
+  float* shell_tab = nullptr;   // device, FP32 [nsets][kShellStride]
+  double* shell_chk = nullptr;  // device, [nsets][2]: max off-pattern, max on-pattern |M|
+  double shell_asym = 1.0;      // max over sets of off-pattern / on-pattern
+  bool shell_ok = false;        // every set is symmetric in the two axes to FP32 precision
 };
+
+// Floats per set of a shell table: C[9][2][3], sqrtD lower (36), padding to 16 bytes.
+constexpr int kShellStride = 96;
 
 // R is applied in the reflection-sector basis only when its asymmetric part is below
 // FP32 rounding of R itself.
@@ -129,6 +138,7 @@ hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int
                               hipStream_t st);
 hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st);
 hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st);
+hipError_t launch_shell_sector(const icr_plan* p, int level, hipStream_t st);
 
 // level 0 apply: out = L00 in (forward) / U00 in (+ add) (adjoint); w optional
 struct Level0Args {

@@ -1,5 +1,7 @@
 // 3-D refinement level in the reflection-sector basis, FP32 arithmetic with FP32 or
-// bfloat16 storage, for stationary levels whose R is reflection-symmetric.
+// bfloat16 storage, for stationary levels whose R is reflection-symmetric, and for
+// shell-charted levels (one R per coarse plane along z) whose R is symmetric under
+// reflecting y and x: there z stays dense and each plane reads its own coefficients.
 //
 // R = B C P (see sector_kernel in build_f64.hip): P takes each axis of the 3x3x3
 // window to even/odd channels (e, m, o) = (s_-1 + s_+1, s_0, s_+1 - s_-1), C has
@@ -38,6 +40,29 @@ struct Sector3 {
 };
 
 __device__ __forceinline__ int sd(int b, int bp) { return b * (b + 1) / 2 + bp; }
+
+// The matrices the kernels apply to the blocks of a coarse plane. A stationary level
+// passes its one sector set by value. A shell-charted level (one set per coarse plane
+// along z, where R keeps the reflection symmetry of y and x only) passes a table with
+// one row per plane: C[ty tx][bz][wz] (z dense, y and x in sector form) and sqrtD.
+struct StationaryMats {
+  Sector3 k;
+};
+struct ShellMats {
+  const float* tab;  // [nz - 2][kShellStride]: C[ty tx][bz][wz] (54), sqrtD lower by rows (36), padding
+  int nsets;
+};
+// A plane's row is the same for every lane of a workgroup (all lanes march through
+// the same planes): read it through the constant address space, which lets the
+// compiler use scalar loads (the table is never written while a sweep runs).
+typedef const float __attribute__((address_space(4))) const_float;
+__device__ __forceinline__ const const_float* shell_row(const ShellMats& m, int set) {
+  return (const const_float*)(m.tab + static_cast<int64_t>(set) * kShellStride);
+}
+template <typename M>
+constexpr bool kIsShell = false;
+template <>
+constexpr bool kIsShell<ShellMats> = true;
 
 // The four coarse values x = 2q .. 2q+3 of rows y-1, y, y+1 of one plane.
 struct Raw3 {
@@ -109,6 +134,41 @@ __device__ __forceinline__ void sector_forward(const float (&T0)[9], const float
   }
 }
 
+// Shell-charted block: y and x in sector form, z dense. Y[bz][sy sx] collects, per
+// window channel (ty, tx), the three window planes with that plane's coefficients;
+// the y and x butterflies then give out[bz*4 + by*2 + bx].
+template <typename P>
+__device__ __forceinline__ void shell_forward(const float (&T0)[9], const float (&T1)[9],
+                                              const float (&T2)[9], P c, float (&out)[8]) {
+  float Y[2][4];
+#pragma unroll
+  for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) Y[bz][s] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int sg = ((j / 3 == 2) << 1) | (j % 3 == 2);
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz)
+      Y[bz][sg] = fmaf(c[j * 6 + bz * 3], T0[j],
+                       fmaf(c[j * 6 + bz * 3 + 1], T1[j], fmaf(c[j * 6 + bz * 3 + 2], T2[j], Y[bz][sg])));
+  }
+#pragma unroll
+  for (int bz = 0; bz < 2; ++bz) {
+    float A[2][2];
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {  // x: (sy, sx) -> (sy, bx)
+      A[sy][0] = Y[bz][sy * 2] - Y[bz][sy * 2 + 1];
+      A[sy][1] = Y[bz][sy * 2] + Y[bz][sy * 2 + 1];
+    }
+#pragma unroll
+    for (int bx = 0; bx < 2; ++bx) {  // y: (sy, bx) -> (by, bx)
+      out[bz * 4 + bx] = A[0][bx] - A[1][bx];
+      out[bz * 4 + 2 + bx] = A[0][bx] + A[1][bx];
+    }
+  }
+}
+
 struct Fwd3Geom {
   int nz, ny, nx;  // coarse shape
   int pairs;       // (nx - 2) / 2 pixel pairs per interior row
@@ -122,13 +182,14 @@ struct Fwd3Geom {
 // The z loop is unrolled by two with ping-pong load buffers, and every load goes to a
 // clamped in-bounds address: loaded registers are never copied or loaded under a
 // branch, so the next step's loads stay in flight while the current step computes.
-template <typename TS, bool kW>
-__global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, Sector3 k) {
+template <typename TS, bool kW, typename M>
+__global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, M m) {
   // plane-major order (no XCD renumbering): the forward's only shared data is the
   // small coarse level, and this order measured faster on the 388^3 level
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.rows, g.zchunk, g.nfy, g.nfx, g.xy_blocks, a.s_in, a.s_in_bs, a.xi,
              a.xi_bs, a.s_out, a.s_out_bs);
   if (kW) fetch_args(a.w, a.w_bs);
+  if constexpr (kIsShell<M>) fetch_args(m.tab);
   const int tile = static_cast<int>(blockIdx.x);
   // no early exit: threads past the last pair work on the last pair and store nothing,
   // so every kernel argument can be fetched in one round at the start (an exit branch
@@ -173,8 +234,19 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
   auto compute_step = [&](int z, const Step& st) {
     plane_stage(st.raw, T2);
     float o[2][8];
-    sector_forward(T0[0], T1[0], T2[0], k, o[0]);
-    sector_forward(T0[1], T1[1], T2[1], k, o[1]);
+    float S[36];
+    if constexpr (kIsShell<M>) {
+      const auto c = shell_row(m, z - 1);
+      shell_forward(T0[0], T1[0], T2[0], c, o[0]);
+      shell_forward(T0[1], T1[1], T2[1], c, o[1]);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) S[e] = c[54 + e];
+    } else {
+      sector_forward(T0[0], T1[0], T2[0], m.k, o[0]);
+      sector_forward(T0[1], T1[1], T2[1], m.k, o[1]);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) S[e] = m.k.s[e];
+    }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       float x[8];
@@ -188,7 +260,7 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int cp = 0; cp <= c; ++cp) o[p][c] = fmaf(k.s[sd(c, cp)], x[cp], o[p][c]);
+        for (int cp = 0; cp <= c; ++cp) o[p][c] = fmaf(S[sd(c, cp)], x[cp], o[p][c]);
     }
 #pragma unroll
     for (int bz = 0; bz < 2; ++bz)
@@ -247,8 +319,8 @@ struct Adj3Geom {
 };
 
 // Tile: kTP block pairs (x) by kTR block rows (y), halo ring included.
-template <typename TS, bool kAdd, int kTP, int kTR>
-__global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, RefineAdjArgs a, Sector3 k) {
+template <typename TS, bool kAdd, int kTP, int kTR, typename M>
+__global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, RefineAdjArgs a, M m) {
   constexpr int kOP = kTP - 2;     // owned pairs per tile (first and last lane of a row are halo)
   constexpr int kOR = kTR - 2;     // owned rows per tile
   constexpr int kAdjThreads = kTP * kTR;
@@ -257,6 +329,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.xtiles, g.zchunk, g.nfy, g.nfx, g.xy_tiles, g.nwg, a.y, a.y_bs, a.xi_bar,
              a.xi_bar_bs, a.s_bar, a.s_bar_bs);
   if (kAdd) fetch_args(a.add, a.add_bs);
+  if constexpr (kIsShell<M>) fetch_args(m.tab, m.nsets);
   const int t = threadIdx.x;
   const int i = t % kTP, j = t / kTP;
   const int tile = xcd_tile(blockIdx.x, g.nwg);
@@ -305,6 +378,16 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
 
   auto process = [&](int zb, const Plane& pl) {
     const bool ok = blocks_ok && zb >= 1 && zb <= g.nz - 2;
+    float S[36];
+    const const_float* cz = nullptr;  // shell: this block plane's row (clamped, uniform)
+    if constexpr (kIsShell<M>) {
+      cz = shell_row(m, min(max(zb - 1, 0), m.nsets - 1));
+#pragma unroll
+      for (int e = 0; e < 36; ++e) S[e] = cz[54 + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 36; ++e) S[e] = m.k.s[e];
+    }
     float yv[2][8];
 #pragma unroll
     for (int bz = 0; bz < 2; ++bz)
@@ -324,7 +407,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
         for (int cp = 0; cp < 8; ++cp) {
           float v = 0.0f;
 #pragma unroll
-          for (int c = cp; c < 8; ++c) v = fmaf(k.s[sd(c, cp)], yv[p][c], v);
+          for (int c = cp; c < 8; ++c) v = fmaf(S[sd(c, cp)], yv[p][c], v);
           xo[p][cp] = v;
         }
 #pragma unroll
@@ -342,6 +425,35 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
     }
     // sectors (Q), channels (C^T) and the z stage of P^T
     float G[2][9];
+    if constexpr (kIsShell<M>) {
+      // the plane's sqrtD and C rows are scalar values: keep their loads in two groups so
+      // that both never need registers at the same time
+      __builtin_amdgcn_sched_barrier(0);
+      // y and x sectors per z child, then per channel (ty, tx) the three window planes
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        float Ys[2][4];
+#pragma unroll
+        for (int bz = 0; bz < 2; ++bz) {
+          const float* y = yv[p] + bz * 4;
+          const float sx0 = y[0] + y[1], dx0 = y[1] - y[0], sx1 = y[2] + y[3], dx1 = y[3] - y[2];
+          Ys[bz][0] = sx0 + sx1;
+          Ys[bz][1] = dx0 + dx1;
+          Ys[bz][2] = sx1 - sx0;
+          Ys[bz][3] = dx1 - dx0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 9; ++jj) {
+          const int sg = ((jj / 3 == 2) << 1) | (jj % 3 == 2);
+          const float u0 = fmaf(cz[jj * 6], Ys[0][sg], cz[jj * 6 + 3] * Ys[1][sg]);      // slot z-1
+          const float u1 = fmaf(cz[jj * 6 + 1], Ys[0][sg], cz[jj * 6 + 4] * Ys[1][sg]);  // slot 0
+          const float u2 = fmaf(cz[jj * 6 + 2], Ys[0][sg], cz[jj * 6 + 5] * Ys[1][sg]);  // slot z+1
+          G[p][jj] = A0[p][jj] + u0;
+          A0[p][jj] = A1[p][jj] + u1;
+          A1[p][jj] = u2;
+        }
+      }
+    } else {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       float A[8], Bv[8], Ys[8];
@@ -365,13 +477,14 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
 #pragma unroll
       for (int jj = 0; jj < 9; ++jj) {
         const int sy = jj / 3 == 2, sx = jj % 3 == 2;
-        const float ue = k.c[jj] * Ys[(sy << 1) | sx];
-        const float um = k.c[9 + jj] * Ys[(sy << 1) | sx];
-        const float uo = k.c[18 + jj] * Ys[4 | (sy << 1) | sx];
+        const float ue = m.k.c[jj] * Ys[(sy << 1) | sx];
+        const float um = m.k.c[9 + jj] * Ys[(sy << 1) | sx];
+        const float uo = m.k.c[18 + jj] * Ys[4 | (sy << 1) | sx];
         G[p][jj] = A0[p][jj] + (ue - uo);   // window slot z-1 of this block: coarse zb-1
         A0[p][jj] = A1[p][jj] + um;          // slot 0: coarse zb
         A1[p][jj] = ue + uo;                 // slot z+1: coarse zb+1
       }
+    }
     }
     if (zb >= z0 + 1) {  // coarse plane zb - 1 is complete in G (uniform branch)
       const int zc = zb - 1;
@@ -442,8 +555,10 @@ bool aligned_to(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(
 // Can this level run in the sector kernels? (3-D, FP32 arithmetic, stationary and
 // reflection-symmetric, an even coarse x extent, vector-aligned rows and batches.)
 bool sector_eligible(const icr_plan* p, int level) {
-  if (p->ndim != 3 || p->charted || p->precision == ICR_F64) return false;
-  if (!p->lev[level].sector_ok) return false;
+  if (p->ndim != 3 || p->precision == ICR_F64) return false;
+  const bool stationary = !p->charted && p->lev[level].sector_ok;
+  const bool shell = p->shell && p->lev[level].shell_ok;
+  if (!stationary && !shell) return false;
   const int* nc = p->shapes[level];
   if (nc[2] % 2 != 0 || nc[2] < 4) return false;
   const int64_t nf = int64_t(p->shapes[level + 1][0]) * p->shapes[level + 1][1] * p->shapes[level + 1][2];
@@ -472,13 +587,17 @@ int64_t pick_chunks(int64_t xy_blocks, int planes, int64_t batch, int64_t slots)
   return n;
 }
 
-template <typename TS>
-hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
-  const LevelMats& m = p->lev[level];
-  Sector3 k;
-  for (int t = 0; t < 27; ++t) k.c[t] = m.h_sector[t];
+StationaryMats stationary_mats(const LevelMats& m) {
+  StationaryMats s;
+  for (int t = 0; t < 27; ++t) s.k.c[t] = m.h_sector[t];
   for (int c = 0; c < 8; ++c)
-    for (int cp = 0; cp <= c; ++cp) k.s[c * (c + 1) / 2 + cp] = m.h_s[c * 8 + cp];
+    for (int cp = 0; cp <= c; ++cp) s.k.s[c * (c + 1) / 2 + cp] = m.h_s[c * 8 + cp];
+  return s;
+}
+ShellMats shell_mats(const LevelMats& m) { return ShellMats{m.shell_tab, static_cast<int>(m.nsets)}; }
+
+template <typename TS, typename M>
+hipError_t fwd_launch(const icr_plan* p, int level, const M& k, const RefineFwdArgs& a, hipStream_t st) {
   Fwd3Geom g;
   g.nz = p->shapes[level][0]; g.ny = p->shapes[level][1]; g.nx = p->shapes[level][2];
   g.pairs = (g.nx - 2) / 2;
@@ -487,7 +606,7 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
   g.nfx = p->shapes[level + 1][2];
   const int64_t xy_blocks = (int64_t(g.rows) * g.pairs + 255) / 256;
   static const int64_t slots =
-      resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false>), 256);
+      resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false, M>), 256);
   const int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
   g.zchunk = static_cast<int>((g.nz - 2 + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz - 2 + g.zchunk - 1) / g.zchunk;
@@ -501,22 +620,18 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
     c.s_out = static_cast<TS*>(a.s_out) + b0 * a.s_out_bs;
     if (a.w) c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
     const dim3 grid(static_cast<unsigned>(g.nwg), static_cast<unsigned>(c.batch));
-    if (a.w) refine3_fwd_sector<TS, true><<<grid, 256, 0, st>>>(g, c, k);
-    else refine3_fwd_sector<TS, false><<<grid, 256, 0, st>>>(g, c, k);
+    if (a.w) refine3_fwd_sector<TS, true, M><<<grid, 256, 0, st>>>(g, c, k);
+    else refine3_fwd_sector<TS, false, M><<<grid, 256, 0, st>>>(g, c, k);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <typename TS, int kTP, int kTR>
-hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+template <typename TS, int kTP, int kTR, typename M>
+hipError_t adj_launch_tile(const icr_plan* p, int level, const M& k, const RefineAdjArgs& a,
+                           hipStream_t st) {
   constexpr int kOP = kTP - 2, kOR = kTR - 2;  // as in the kernel
-  const LevelMats& m = p->lev[level];
-  Sector3 k;
-  for (int t = 0; t < 27; ++t) k.c[t] = m.h_sector[t];
-  for (int c = 0; c < 8; ++c)
-    for (int cp = 0; cp <= c; ++cp) k.s[c * (c + 1) / 2 + cp] = m.h_s[c * 8 + cp];
   Adj3Geom g;
   g.nz = p->shapes[level][0]; g.ny = p->shapes[level][1]; g.nx = p->shapes[level][2];
   g.pairs = (g.nx - 2) / 2;
@@ -526,7 +641,7 @@ hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a,
   g.nfx = p->shapes[level + 1][2];
   const int64_t xy_blocks = int64_t(g.xtiles) * ytiles;
   static const int64_t slots =
-      resident_workgroups(reinterpret_cast<const void*>(refine3_adj_sector<TS, false, kTP, kTR>), kTP * kTR);
+      resident_workgroups(reinterpret_cast<const void*>(refine3_adj_sector<TS, false, kTP, kTR, M>), kTP * kTR);
   const int64_t chunks = pick_chunks(xy_blocks, g.nz, a.batch < 65535 ? a.batch : 65535, slots);
   g.zchunk = static_cast<int>((g.nz + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz + g.zchunk - 1) / g.zchunk;
@@ -540,8 +655,8 @@ hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a,
     c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
     if (a.add) c.add = static_cast<const TS*>(a.add) + b0 * a.add_bs;
     const dim3 grid(static_cast<unsigned>(g.nwg), static_cast<unsigned>(c.batch));
-    if (a.add) refine3_adj_sector<TS, true, kTP, kTR><<<grid, kTP * kTR, 0, st>>>(g, c, k);
-    else refine3_adj_sector<TS, false, kTP, kTR><<<grid, kTP * kTR, 0, st>>>(g, c, k);
+    if (a.add) refine3_adj_sector<TS, true, kTP, kTR, M><<<grid, kTP * kTR, 0, st>>>(g, c, k);
+    else refine3_adj_sector<TS, false, kTP, kTR, M><<<grid, kTP * kTR, 0, st>>>(g, c, k);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -553,7 +668,15 @@ hipError_t adj_launch_tile(const icr_plan* p, int level, const RefineAdjArgs& a,
 // the 388^3 level.
 template <typename TS>
 hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
-  return adj_launch_tile<TS, 16, 32>(p, level, a, st);
+  const LevelMats& m = p->lev[level];
+  if (p->shell) return adj_launch_tile<TS, 16, 32>(p, level, shell_mats(m), a, st);
+  return adj_launch_tile<TS, 16, 32>(p, level, stationary_mats(m), a, st);
+}
+template <typename TS>
+hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
+  const LevelMats& m = p->lev[level];
+  if (p->shell) return fwd_launch<TS>(p, level, shell_mats(m), a, st);
+  return fwd_launch<TS>(p, level, stationary_mats(m), a, st);
 }
 
 }  // namespace
