@@ -19,6 +19,10 @@ of every latent parameter is N(0, 1)) level by level:
 The adjoint L^T is the exact transpose of that sweep, and the metric of a
 Gaussian likelihood in standardized coordinates is M = L^T N^-1 L + 1 (section
 "Performance of NIFTy.re compared to NIFTy": the Fisher metric plus the identity).
+The gradient of <ybar, L xi> with respect to the kernel's scale and length scale
+(hyper_grad) follows the level recursion by the chain rule, with the derivatives of
+R = K_fc K_cc^-1, D and their Cholesky factors written out in closed form (the
+paper values automatic differentiation of the model, section "Gaussian Processes").
 
 Readings where the paper is silent:
   * children sit at +-delta/4 per axis around their coarse pixel, so the fine grid
@@ -370,6 +374,41 @@ def _positions(cfg: ICRConfig, idx_points: np.ndarray) -> np.ndarray:
     raise ValueError(f"unknown chart {cfg.chart!r}")
 
 
+def _level0_positions(cfg: ICRConfig, shape0) -> np.ndarray:
+    """Physical positions of the level-0 pixels in C order."""
+    spac = level_spacings(cfg.delta0, 0)[0]
+    return _positions(cfg, grid_indices(shape0) * spac)
+
+
+def _window_positions(cfg: ICRConfig, shapes, l: int):
+    """Physical window (3^d) and child (2^d) positions of every matrix set of level l.
+
+    Stationary grid: one set, relative to the coarse pixel, shapes (1, 3^d, d) and
+    (1, 2^d, d). Chart: one set per interior coarse pixel in C order.
+    """
+    d = cfg.ndim
+    dl = level_spacings(cfg.delta0, cfg.depth)[l]
+    wins = window_offsets(d).astype(np.float64)
+    kids = child_offsets(d).astype(np.float64)
+    if cfg.chart == "regular":
+        # stationary: one set per level, geometry relative to the coarse pixel
+        return (wins * dl)[None], ((kids - 0.5) * dl / 2.0)[None]
+    org = level_origins(cfg.delta0, cfg.depth)[l]
+    n_int = tuple(n - 2 for n in shapes[l])
+    centre = org + (grid_indices(n_int) + 1) * dl                # (P, d)
+    win_idx = centre[:, None, :] + wins[None] * dl               # (P, 3^d, d)
+    kid_idx = centre[:, None, :] + (kids[None] - 0.5) * dl / 2.0
+    return _positions(cfg, win_idx), _positions(cfg, kid_idx)
+
+
+def _set_shape(cfg: ICRConfig, shapes, l: int, mat: np.ndarray) -> np.ndarray:
+    """A level's stack of sets as stored: (2^d, .) when stationary, else per pixel."""
+    if cfg.chart == "regular":
+        return mat[0]
+    n_int = tuple(n - 2 for n in shapes[l])
+    return mat.reshape(n_int + mat.shape[-2:])
+
+
 def build(cfg: ICRConfig) -> ICROracle:
     """Level sizes, level-0 Cholesky factor and per-level R, sqrt(D) in FP64."""
     if cfg.ndim not in (1, 2, 3):
@@ -382,38 +421,128 @@ def build(cfg: ICRConfig) -> ICROracle:
     sizes = [int(np.prod(s)) for s in model.shapes]
     model.offsets = [int(v) for v in np.concatenate([[0], np.cumsum(sizes)[:-1]])]
     model.n_xi = int(sum(sizes))
-    spac = level_spacings(cfg.delta0, cfg.depth)
-    org = level_origins(cfg.delta0, cfg.depth)
     tau = pivot_threshold(d, cfg.scale)
 
     # level 0: dense Cholesky of the kernel over all n_0^d pixels, C order
-    x0 = _positions(cfg, org[0] + grid_indices(model.shapes[0]) * spac[0])
+    x0 = _level0_positions(cfg, model.shapes[0])
     k00 = kernel_values(cfg.kernel, pairwise_distance(x0, x0), cfg.scale, cfg.length)
     model.l00, c0 = clamped_cholesky(k00, tau, cfg.clamp)
     model.clamped = [int(c0)]
 
-    wins = window_offsets(d).astype(np.float64)
-    kids = child_offsets(d).astype(np.float64)
     for l in range(cfg.depth):
-        dl = spac[l]
-        if cfg.chart == "regular":
-            # stationary: one set per level, geometry relative to the coarse pixel
-            win_pos = wins * dl
-            child_pos = (kids - 0.5) * dl / 2.0
-        else:
-            n_int = tuple(n - 2 for n in model.shapes[l])
-            centre = org[l] + (grid_indices(n_int) + 1) * dl             # (P, d)
-            win_idx = centre[:, None, :] + wins[None] * dl               # (P, 3^d, d)
-            kid_idx = centre[:, None, :] + (kids[None] - 0.5) * dl / 2.0
-            win_pos = _positions(cfg, win_idx)
-            child_pos = _positions(cfg, kid_idx)
+        win_pos, child_pos = _window_positions(cfg, model.shapes, l)
         r_mat, sqrt_d, cnt = conditional_matrices(cfg.kernel, cfg.scale, cfg.length,
                                                   win_pos, child_pos, tau, cfg.clamp)
-        if cfg.chart != "regular":
-            n_int = tuple(n - 2 for n in model.shapes[l])
-            r_mat = r_mat.reshape(n_int + r_mat.shape[-2:])
-            sqrt_d = sqrt_d.reshape(n_int + sqrt_d.shape[-2:])
-        model.r_mats.append(r_mat)
-        model.sqrt_ds.append(sqrt_d)
+        model.r_mats.append(_set_shape(cfg, model.shapes, l, r_mat))
+        model.sqrt_ds.append(_set_shape(cfg, model.shapes, l, sqrt_d))
         model.clamped.append(int(np.sum(cnt)))
     return model
+
+
+# ---------------------------------------------------------------------------
+# Gradients with respect to the kernel hyperparameters (scale sigma, length l)
+# ---------------------------------------------------------------------------
+#
+# L depends on theta = (sigma, l) through K_00 and every level's R and sqrt(D). For
+# E = <ybar, L xi> the chain rule through the level recursion
+#   s_0 = L_00 xi_0,   s_{l+1} = R_l s_l[window] + sqrt(D_l) xi_{l+1}
+# gives dE/dtheta = sum_l <sbar_{l+1}, dR_l s_l[window] + d sqrt(D_l) xi_{l+1}>
+#                   + <sbar_0, dL_00 xi_0>,
+# with sbar_l the level cotangents of the adjoint sweep. Every covariance is
+# proportional to sigma^2, so R does not depend on sigma, sqrt(D) and L_00 are
+# proportional to sigma, and dE/dsigma = <ybar, L xi> / sigma.
+
+def kernel_length_derivative(kind: str, r, scale: float, length: float) -> np.ndarray:
+    """d k(r) / d length of the kernels of kernel_values (closed forms)."""
+    t = np.asarray(r, dtype=np.float64) / float(length)
+    if kind == "matern12":
+        dk = np.exp(-t) * t
+    elif kind == "matern32":
+        a = math.sqrt(3.0) * t
+        dk = a * a * np.exp(-a)
+    elif kind == "matern52":
+        a = math.sqrt(5.0) * t
+        dk = a * a * (1.0 + a) / 3.0 * np.exp(-a)
+    elif kind == "sqexp":
+        dk = t * t * np.exp(-0.5 * t * t)
+    else:
+        raise ValueError(f"unknown kernel {kind!r}")
+    return float(scale) ** 2 * dk / float(length)
+
+
+def cholesky_derivative(low: np.ndarray, da: np.ndarray) -> np.ndarray:
+    """Directional derivative of the lower Cholesky factor L of A along symmetric dA.
+
+    From dA = dL L^T + L dL^T with dL lower: L^-1 dA L^-T = Phi + Phi^T where
+    Phi = L^-1 dL is lower, so Phi is the lower triangle of X = L^-1 dA L^-T with its
+    diagonal halved and dL = L Phi. A clamped (zero) column makes L singular; its
+    derivative is undefined and NotPositiveDefinite is raised.
+    """
+    low = np.asarray(low, dtype=np.float64)
+    if np.any(np.diagonal(low, axis1=-2, axis2=-1) <= 0.0):
+        raise NotPositiveDefinite("the factor has a clamped column: no derivative")
+    x = np.linalg.solve(low, da)                                   # L^-1 dA
+    x = np.linalg.solve(low, np.swapaxes(x, -1, -2))               # L^-1 (L^-1 dA)^T = L^-1 dA L^-T
+    x = 0.5 * (x + np.swapaxes(x, -1, -2))
+    n = low.shape[-1]
+    phi = np.tril(x) - 0.5 * np.eye(n) * np.diagonal(x, axis1=-2, axis2=-1)[..., None, :]
+    return low @ phi
+
+
+def conditional_matrices_length_derivative(kind, scale, length, win_pos, child_pos, r_mat, sqrt_d):
+    """d R / d length and d sqrt(D) / d length of conditional_matrices' results.
+
+    R K_cc = K_fc gives dR = (dK_fc - R dK_cc) K_cc^-1, and D = K_ff - R K_cf gives
+    dD = dK_ff - dR K_cf - R dK_cf (symmetrised); sqrt(D) follows cholesky_derivative.
+    """
+    dist_cc = pairwise_distance(win_pos, win_pos)
+    dist_fc = pairwise_distance(child_pos, win_pos)
+    dist_ff = pairwise_distance(child_pos, child_pos)
+    k_cc = kernel_values(kind, dist_cc, scale, length)
+    k_fc = kernel_values(kind, dist_fc, scale, length)
+    dk_cc = kernel_length_derivative(kind, dist_cc, scale, length)
+    dk_fc = kernel_length_derivative(kind, dist_fc, scale, length)
+    dk_ff = kernel_length_derivative(kind, dist_ff, scale, length)
+    rhs = np.swapaxes(dk_fc - r_mat @ dk_cc, -1, -2)
+    d_r = np.swapaxes(np.linalg.solve(k_cc, rhs), -1, -2)
+    d_d = dk_ff - d_r @ np.swapaxes(k_fc, -1, -2) - r_mat @ np.swapaxes(dk_fc, -1, -2)
+    d_d = 0.5 * (d_d + np.swapaxes(d_d, -1, -2))
+    return d_r, cholesky_derivative(sqrt_d, d_d)
+
+
+def length_derivatives(model: ICROracle):
+    """d L_00, [d R_l], [d sqrt(D_l)] with respect to the length scale, shaped as stored."""
+    cfg = model.cfg
+    x0 = _level0_positions(cfg, model.shapes[0])
+    dist0 = pairwise_distance(x0, x0)
+    d_l00 = cholesky_derivative(model.l00, kernel_length_derivative(cfg.kernel, dist0, cfg.scale, cfg.length))
+    d_r, d_s = [], []
+    for l in range(cfg.depth):
+        win_pos, child_pos = _window_positions(cfg, model.shapes, l)
+        nset = win_pos.shape[0]
+        r_mat = np.reshape(model.r_mats[l], (nset,) + model.r_mats[l].shape[-2:])
+        s_mat = np.reshape(model.sqrt_ds[l], (nset,) + model.sqrt_ds[l].shape[-2:])
+        dr, ds = conditional_matrices_length_derivative(cfg.kernel, cfg.scale, cfg.length, win_pos,
+                                                        child_pos, r_mat, s_mat)
+        d_r.append(_set_shape(cfg, model.shapes, l, dr))
+        d_s.append(_set_shape(cfg, model.shapes, l, ds))
+    return d_l00, d_r, d_s
+
+
+def hyper_grad(model: ICROracle, xi: np.ndarray, ybar: np.ndarray) -> np.ndarray:
+    """(dE/dsigma, dE/dlength) of E = <ybar, L xi> per sample, shape (..., 2)."""
+    d = model.cfg.ndim
+    xi = np.asarray(xi, dtype=np.float64)
+    ybar = np.asarray(ybar, dtype=np.float64)
+    batch = xi.shape[:-1]
+    s_final, s_levels = model.forward(xi, return_levels=True)
+    _, cot = model.adjoint(ybar, return_levels=True)
+    g_sigma = np.sum(ybar * s_final, axis=-1) / model.cfg.scale
+    d_l00, d_r, d_s = length_derivatives(model)
+    g_len = np.sum(cot[0] * (xi[..., model.level_slice(0)] @ d_l00.T), axis=-1)
+    for l in range(model.cfg.depth):
+        s_l = s_levels[l].reshape(batch + model.shapes[l])
+        xi_f = xi[..., model.level_slice(l + 1)].reshape(batch + model.shapes[l + 1])
+        t = refine(s_l, xi_f, d_r[l], d_s[l], d).reshape(batch + (-1,))
+        g_len = g_len + np.sum(cot[l + 1] * t, axis=-1)
+    return np.stack([g_sigma, g_len], axis=-1)
