@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests in the served-mode stream (0: skip the served measurement)")
     ap.add_argument("--serve-priors", type=int, default=24)
+    ap.add_argument("--hypergrad-steps", type=int, default=20,
+                    help="timed hyperparameter-gradient evaluations (0: skip that measurement)")
     ap.add_argument("--cg-iters", type=int, default=None,
                     help="CG iterations on the metric (default: 200 for a charted workload, else none)")
     ap.add_argument("--graph", action="store_true",
@@ -278,6 +280,55 @@ def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
     return out
 
 
+def hyper_grad_bench(B, wl: dict, prec: str, steps: int, quiet: bool) -> dict:
+    """Hyperparameter gradients on the workload: a plan built with the length
+    derivatives, then per step icr_forward + icr_adjoint + icr_hyper_grad (the full
+    cost of dE/d(scale, length) for E = <ybar, L xi>), and the contraction alone."""
+    import torch
+    cfg = B.make_config(wl["ndim"], wl["shape0"], wl["depth"], wl["delta0"], kernel=wl["kernel"],
+                        scale=wl["scale"], length=wl["length"], chart=wl["chart"],
+                        chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966)),
+                        precision=prec, hypergrad=True)
+    t0 = time.perf_counter()
+    plan = B.icr_build_matrices(cfg)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info
+    batch = wl["batch"]
+    xi = torch.from_numpy(W.standard_normal_f32(info["n_xi"], seed=0, batch=batch)).cuda().to(plan.dtype)
+    y = torch.from_numpy(W.standard_normal_f32(info["n_out"], seed=1, batch=batch)).cuda().to(plan.dtype)
+    ws_f = B.workspace_for(plan, batch)
+    ws_a = B.workspace_for(plan, batch)
+    s = torch.empty((batch, info["n_out"]), dtype=plan.dtype, device="cuda")
+    xb = torch.empty((batch, info["n_xi"]), dtype=plan.dtype, device="cuda")
+    grad = torch.empty((batch, 2), dtype=torch.float64, device="cuda")
+    hws = torch.empty((batch, info["hypergrad_workspace_elems"]), dtype=torch.float64, device="cuda")
+
+    def full():
+        B.icr_forward(plan, xi, s, ws_f)
+        B.icr_adjoint(plan, y, xb, ws_a)
+        B.icr_hyper_grad(plan, xi, s, ws_f, y, ws_a, grad, hws)
+
+    def contraction():
+        B.icr_hyper_grad(plan, xi, s, ws_f, y, ws_a, grad, hws)
+
+    out = {"build_ms_with_derivatives": build_ms}
+    for name, fn in (("ms_per_gradient", full), ("ms_contraction", contraction)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+    out["gradient"] = [float(v) for v in grad[0].cpu()]
+    log(f"hyper_grad: {out['ms_per_gradient']:.3f} ms per gradient (forward + adjoint + contraction), "
+        f"contraction {out['ms_contraction']:.3f} ms, build with derivatives {build_ms:.0f} ms", quiet)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -464,6 +515,8 @@ def main():
     cg_iters = args.cg_iters if args.cg_iters is not None else (200 if wl["chart"] != "regular" else 0)
     if cg_iters > 0 and not args.copy_probe and prec != "bf16":
         out["cg"] = cg_solve(B, plan, wl, cg_iters, args.quiet)
+    if args.hypergrad_steps > 0 and not args.copy_probe:
+        out["hyper_grad"] = hyper_grad_bench(B, wl, prec, args.hypergrad_steps, args.quiet)
     if args.serve_requests > 0 and not args.copy_probe:
         out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
     if not args.no_cpu_baseline:

@@ -82,6 +82,10 @@ typedef enum icr_chart {
 
 /* Build flags */
 #define ICR_FLAG_NO_CLAMP 1  /* fail with ICR_ERR_NOT_PD instead of clamping a pivot */
+#define ICR_FLAG_HYPERGRAD 2 /* also build the length-scale derivatives of L_00, R and sqrtD
+                                (FP64, on the device) for icr_hyper_grad; the build returns
+                                ICR_ERR_NOT_PD if any pivot had to be clamped (the derivative
+                                of a clamped factor is undefined) */
 
 /*
  * Prior description. Index-space pixel i of level l sits at o_l + i delta_l per
@@ -123,6 +127,8 @@ typedef struct icr_plan_info {
   int64_t level_sets[ICR_MAX_DEPTH]; /* matrix sets of refinement l -> l+1: 1 on a regular
                                         grid, prod(n_l - 2) under the 2-D chart, n_l,0 - 2
                                         (radial shells) under the cylinder chart */
+  int64_t hypergrad_workspace_elems; /* doubles of workspace per sample for icr_hyper_grad
+                                        (0 unless built with ICR_FLAG_HYPERGRAD) */
 } icr_plan_info;
 
 /*
@@ -202,6 +208,30 @@ icr_status icr_adjoint(const icr_plan* plan, int64_t batch, const void* s_bar, v
 icr_status icr_metric_apply(const icr_plan* plan, int64_t batch, const void* w,
                             int64_t w_batch_stride, const void* v, void* out,
                             void* workspace, void* hip_stream);
+
+/*
+ * Gradient of E = <s_bar, L(theta) xi> with respect to the kernel hyperparameters
+ * theta = (scale sigma, length), per sample, from the results of one icr_forward and
+ * one icr_adjoint (the paper learns kernel parameters by differentiating the model,
+ * section "Gaussian Processes"). With the level cotangents sbar_l of the adjoint sweep,
+ *   dE/dlength = <sbar_0, dL_00 xi_0> + sum_l <sbar_{l+1}, dR_l s_l[window] + dsqrtD_l xi_{l+1}>,
+ *   dE/dsigma  = <s_bar, s> / sigma   (R does not depend on sigma; L_00, sqrtD scale with it),
+ * where dR, dsqrtD, dL_00 are the FP64 length derivatives built with ICR_FLAG_HYPERGRAD.
+ * Chaining through a loss: pass the loss gradient with respect to s as s_bar.
+ *   xi          [batch][n_xi]  the excitations of the forward call.
+ *   s           [batch][n_out] its output.
+ *   s_levels    [batch][workspace_elems] its workspace (levels s_0 .. s_{L-1}).
+ *   s_bar       [batch][n_out] the adjoint's input cotangent.
+ *   sbar_levels [batch][workspace_elems] the adjoint's workspace (sbar_0 .. sbar_{L-1}).
+ *   grad        device double [batch][2]: (dE/dsigma, dE/dlength).
+ *   workspace   device double [batch][hypergrad_workspace_elems] (partial sums).
+ * Sums run in FP64 in a fixed order (bitwise reproducible); per-term products are in
+ * the plan's arithmetic type. Returns ICR_ERR_UNSUPPORTED for a plan built without
+ * ICR_FLAG_HYPERGRAD. Asynchronous on hip_stream; allocates nothing.
+ */
+icr_status icr_hyper_grad(const icr_plan* plan, int64_t batch, const void* xi, const void* s,
+                          const void* s_levels, const void* s_bar, const void* sbar_levels,
+                          double* grad, double* workspace, void* hip_stream);
 
 /*
  * Conjugate gradients on the metric M = L^T (w * L .) + 1 for `batch` independent right-

@@ -36,6 +36,19 @@ __device__ double kernel_value(const KernelSpec& k, double r) {
   return k.sigma2 * v;
 }
 
+// d k(r) / d length of the kernels above (closed forms; the scale only multiplies)
+__device__ double kernel_dlength(const KernelSpec& k, double r) {
+  const double t = r / k.length;
+  double v;
+  switch (k.kind) {
+    case ICR_MATERN12: v = t * exp(-t); break;
+    case ICR_MATERN32: { const double a = 1.7320508075688772 * t; v = a * a * exp(-a); break; }
+    case ICR_MATERN52: { const double a = 2.23606797749979 * t; v = a * a * (1.0 + a) / 3.0 * exp(-a); break; }
+    default: v = t * t * exp(-0.5 * t * t); break;
+  }
+  return k.sigma2 * v / k.length;
+}
+
 // index-space point -> physical point (D = 2 for the log-radial chart, D = 3 for the
 // log-radial cylinder: the same map of the first two axes plus a scaled third axis)
 template <int D>
@@ -67,9 +80,15 @@ __device__ double distance(const double* a, const double* b) {
 // positions. Writes R [NC][NW] and sqrtD [NC][NC] (lower). Returns the number of
 // clamped pivots, or -1 if K_cc is not positive definite or a pivot of D needed
 // clamping with clamping disabled.
+// Derivatives with respect to the length scale of a window's R and sqrtD (dr_out,
+// ds_out; skipped when null): R K_cc = K_fc gives dR = (dK_fc - R dK_cc) K_cc^-1,
+// D = K_ff - R K_cf gives dD = dK_ff - dR K_cf - R dK_cf, and with dD = dS S^T + S dS^T,
+// dS = S Phi(S^-1 dD S^-T), Phi the lower triangle with its diagonal halved. A clamped
+// column of sqrtD (zero pivot) leaves dS undefined: returns -2 then.
 template <int D>
 __device__ int condition_window(const KernelSpec& ks, const double* win, const double* kid,
-                                double tau, bool clamp, double* r_out, double* s_out) {
+                                double tau, bool clamp, double* r_out, double* s_out,
+                                double* dr_out = nullptr, double* ds_out = nullptr) {
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
   double lc[NW * NW];   // K_cc, factorised in place (lower)
@@ -141,7 +160,69 @@ __device__ int condition_window(const KernelSpec& ks, const double* win, const d
       s_out[i * NC + j] = v / root;
     }
   }
-  return clamped;
+  if (!dr_out) return clamped;
+  if (clamped > 0) return -2;
+  // dR rows: K_cc dR[b,:]^T = dK_fc[b,:]^T - dK_cc R[b,:]^T, solved with the factor of K_cc
+  for (int b = 0; b < NC; ++b) {
+    double* x = dr_out + b * NW;
+    for (int i = 0; i < NW; ++i) {
+      double v = kernel_dlength(ks, distance<D>(kid + b * D, win + i * D));
+      for (int j = 0; j < NW; ++j) v -= kernel_dlength(ks, distance<D>(win + i * D, win + j * D)) * r_out[b * NW + j];
+      x[i] = v;
+    }
+    for (int i = 0; i < NW; ++i) {
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= lc[i * NW + k] * x[k];
+      x[i] = v / lc[i * NW + i];
+    }
+    for (int i = NW - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < NW; ++k) v -= lc[k * NW + i] * x[k];
+      x[i] = v / lc[i * NW + i];
+    }
+  }
+  // dD (symmetrised) into dm
+  for (int b = 0; b < NC; ++b)
+    for (int c = 0; c < NC; ++c) {
+      double v = kernel_dlength(ks, distance<D>(kid + b * D, kid + c * D));
+      for (int w = 0; w < NW; ++w)
+        v -= dr_out[b * NW + w] * kfc[c * NW + w] +
+             r_out[b * NW + w] * kernel_dlength(ks, distance<D>(kid + c * D, win + w * D));
+      dm[b * NC + c] = v;
+    }
+  for (int b = 0; b < NC; ++b)
+    for (int c = 0; c < b; ++c) {
+      const double m = 0.5 * (dm[b * NC + c] + dm[c * NC + b]);
+      dm[b * NC + c] = m;
+      dm[c * NC + b] = m;
+    }
+  // X = S^-1 dD (columns), then Y = S^-1 X^T = S^-1 dD S^-T (symmetric)
+  double x[NC * NC];
+  for (int c = 0; c < NC; ++c)
+    for (int i = 0; i < NC; ++i) {
+      double v = dm[i * NC + c];
+      for (int k = 0; k < i; ++k) v -= s_out[i * NC + k] * x[k * NC + c];
+      x[i * NC + c] = v / s_out[i * NC + i];
+    }
+  for (int c = 0; c < NC; ++c)
+    for (int i = 0; i < NC; ++i) {
+      double v = x[c * NC + i];
+      for (int k = 0; k < i; ++k) v -= s_out[i * NC + k] * dm[k * NC + c];
+      dm[i * NC + c] = v / s_out[i * NC + i];
+    }
+  // dS = S Phi(Y)
+  for (int i = 0; i < NC; ++i)
+    for (int j = 0; j < NC; ++j) {
+      double v = 0.0;
+      if (j <= i) {
+        for (int k = j; k <= i; ++k) {
+          const double y = 0.5 * (dm[k * NC + j] + dm[j * NC + k]);
+          v += s_out[i * NC + k] * (k == j ? 0.5 * y : y);
+        }
+      }
+      ds_out[i * NC + j] = v;
+    }
+  return 0;
 }
 
 struct LevelGeom {
@@ -157,6 +238,7 @@ struct LevelGeom {
 template <int D>
 __global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, double tau, int clamp,
                                    double* __restrict__ r64, double* __restrict__ s64,
+                                   double* __restrict__ dr64, double* __restrict__ ds64,
                                    int32_t* __restrict__ count, int32_t* __restrict__ status) {
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
@@ -192,13 +274,15 @@ __global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, dou
     chart_map<D>(cs, pt, kid + b * D);
   }
   const int n = condition_window<D>(ks, win, kid, tau, clamp != 0, r64 + set * NC * NW,
-                                    s64 + set * NC * NC);
-  if (n < 0) atomicOr(status, 1);
+                                    s64 + set * NC * NC, dr64 ? dr64 + set * NC * NW : nullptr,
+                                    ds64 ? ds64 + set * NC * NC : nullptr);
+  if (n == -2) atomicOr(status, 4);
+  else if (n < 0) atomicOr(status, 1);
   else if (n > 0) atomicAdd(count, n);
 }
 
-// K_00[i][j] = k(|x_i - x_j|) over the level-0 pixels in C order.
-template <int D>
+// K_00[i][j] = k(|x_i - x_j|) over the level-0 pixels in C order (kDeriv: d k / d length).
+template <int D, bool kDeriv = false>
 __global__ void build_k00_kernel(KernelSpec ks, ChartSpec cs, int n0a, int n0b, int n0c,
                                  double d0, double d1, double d2, int64_t n, double* __restrict__ a) {
   const int64_t i = static_cast<int64_t>(blockIdx.y);
@@ -216,7 +300,44 @@ __global__ void build_k00_kernel(KernelSpec ks, ChartSpec cs, int n0a, int n0b, 
   }
   chart_map<D>(cs, xi, pi);
   chart_map<D>(cs, xj, pj);
-  a[i * n + j] = kernel_value(ks, distance<D>(pi, pj));
+  a[i * n + j] = kDeriv ? kernel_dlength(ks, distance<D>(pi, pj)) : kernel_value(ks, distance<D>(pi, pj));
+}
+
+// Derivative of the level-0 factor along dK_00 (dL = L Phi(L^-1 dK L^-T), as for sqrtD),
+// in three passes over n x n FP64 matrices. 1: one thread per column j overwrites dK
+// with X = L^-1 dK by forward substitution down its own column (no sharing between
+// threads). 2: one thread per column j writes Y = L^-1 X^T, reading row j of X.
+// 3: one thread per element (i, j <= i) of dL = L Phi(Y).
+__global__ void dl00_solve_kernel(const double* __restrict__ low, double* __restrict__ a, int64_t n) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int64_t i = 0; i < n; ++i) {
+    double v = a[i * n + j];
+    for (int64_t k = 0; k < i; ++k) v -= low[i * n + k] * a[k * n + j];
+    a[i * n + j] = v / low[i * n + i];
+  }
+}
+__global__ void dl00_solve_t_kernel(const double* __restrict__ low, const double* __restrict__ x,
+                                    double* __restrict__ y, int64_t n) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int64_t i = 0; i < n; ++i) {
+    double v = x[j * n + i];
+    for (int64_t k = 0; k < i; ++k) v -= low[i * n + k] * y[k * n + j];
+    y[i * n + j] = v / low[i * n + i];
+  }
+}
+__global__ void dl00_product_kernel(const double* __restrict__ low, const double* __restrict__ y,
+                                    double* __restrict__ dl, int64_t n) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v = 0.0;
+  for (int64_t k = j; k <= i; ++k) {
+    const double s = 0.5 * (y[k * n + j] + y[j * n + k]);
+    v += low[i * n + k] * (k == j ? 0.5 * s : s);
+  }
+  dl[i * n + j] = v;  // zero above the diagonal (empty sum)
 }
 
 // Right-looking Cholesky of the n x n matrix a (row-major, in place, lower), one
@@ -407,6 +528,29 @@ hipError_t launch_build_k00(const icr_plan* p, double* a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dL_00 / d length into p->dl00_64 (plans built for hyperparameter gradients); scratch
+// holds 2 n0^2 doubles.
+hipError_t launch_level0_length_derivative(const icr_plan* p, double* scratch, hipStream_t st) {
+  const int64_t n = p->n0;
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n));
+  const int* s = p->cfg.shape0;
+  const double* d = p->cfg.distances0;
+  double* a = scratch;
+  double* y = scratch + n * n;
+  switch (p->ndim) {
+    case 1: build_k00_kernel<1, true><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], 1, 1, d[0], 0, 0, n, a); break;
+    case 2: build_k00_kernel<2, true><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], s[1], 1, d[0], d[1], 0, n, a); break;
+    default: build_k00_kernel<3, true><<<grid, 256, 0, st>>>(kernel_spec(p), chart_spec(p), s[0], s[1], s[2], d[0], d[1], d[2], n, a); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned cols = static_cast<unsigned>((n + 63) / 64);
+  dl00_solve_kernel<<<cols, 64, 0, st>>>(p->l00_64, a, n);
+  dl00_solve_t_kernel<<<cols, 64, 0, st>>>(p->l00_64, a, y, n);
+  dl00_product_kernel<<<grid, 256, 0, st>>>(p->l00_64, y, p->dl00_64, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cholesky_level0(const icr_plan* p, double* a, int32_t* counts, int32_t* status,
                                   hipStream_t st) {
   const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
@@ -442,9 +586,9 @@ hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int
   const unsigned blocks = static_cast<unsigned>((g.nsets + threads - 1) / threads);
   const LevelMats& m = p->lev[level];
   switch (d) {
-    case 1: build_level_kernel<1><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
-    case 2: build_level_kernel<2><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
-    default: build_level_kernel<3><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, counts, status); break;
+    case 1: build_level_kernel<1><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, m.dr64, m.ds64, counts, status); break;
+    case 2: build_level_kernel<2><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, m.dr64, m.ds64, counts, status); break;
+    default: build_level_kernel<3><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, m.dr64, m.ds64, counts, status); break;
   }
   return hipGetLastError();
 }
@@ -454,10 +598,11 @@ hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st) {
   const int nc = 1 << p->ndim;
   const int nw = pow3(p->ndim);
   const unsigned threads = 256;
-  for (int which = 0; which < 2; ++which) {
-    const int entries = which == 0 ? nc * nw : nc * nc;
-    const double* src = which == 0 ? m.r64 : m.s64;
-    void* dst = which == 0 ? m.r_c : m.s_c;
+  const int parts = m.dr64 ? 4 : 2;  // R, sqrtD and, for hyperparameter gradients, their derivatives
+  for (int which = 0; which < parts; ++which) {
+    const int entries = which % 2 == 0 ? nc * nw : nc * nc;
+    const double* src = which == 0 ? m.r64 : which == 1 ? m.s64 : which == 2 ? m.dr64 : m.ds64;
+    void* dst = which == 0 ? m.r_c : which == 1 ? m.s_c : which == 2 ? m.dr_c : m.ds_c;
     const int64_t total = m.nsets * entries;
     const unsigned blocks = static_cast<unsigned>((total + threads - 1) / threads);
     if (p->precision == ICR_F64)

@@ -65,7 +65,7 @@ icr_status check_config(const icr_config* c) {
   }
   if (c->precision < ICR_F64 || c->precision > ICR_BF16_F32ACC)
     return fail(ICR_ERR_INVALID_ARG, "unknown precision");
-  if (c->flags & ~ICR_FLAG_NO_CLAMP) return fail(ICR_ERR_INVALID_ARG, "unknown flag bits");
+  if (c->flags & ~(ICR_FLAG_NO_CLAMP | ICR_FLAG_HYPERGRAD)) return fail(ICR_ERR_INVALID_ARG, "unknown flag bits");
   if (c->reserved != 0) return fail(ICR_ERR_INVALID_ARG, "reserved must be 0");
   if (!finite_pos(c->scale) || !finite_pos(c->length))
     return fail(ICR_ERR_INVALID_ARG, "scale and length must be finite and > 0");
@@ -262,6 +262,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   p->precision = cfg->precision;
   p->charted = cfg->chart != ICR_CHART_REGULAR;
   p->shell = cfg->chart == ICR_CHART_LOGRADIAL_CYL_3D;
+  p->hypergrad = (cfg->flags & ICR_FLAG_HYPERGRAD) ? 1 : 0;
   p->elem_bytes = elem_bytes_of(cfg->precision);
   const int d = p->ndim;
   for (int l = 0; l < kMaxLevels; ++l)
@@ -300,7 +301,8 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   const size_t off_l64 = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * 8);
   const size_t off_lc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
   const size_t off_uc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
-  size_t off_lev[ICR_MAX_DEPTH][7];
+  const size_t off_dl00 = bytes; bytes = align_up(bytes + (p->hypergrad ? size_t(p->n0) * p->n0 * 8 : 0));
+  size_t off_lev[ICR_MAX_DEPTH][11];
   for (int l = 0; l < p->depth; ++l) {
     int64_t nsets = 1;
     if (p->shell)
@@ -316,6 +318,11 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     const int64_t shell_sets = p->shell ? nsets : 0;
     off_lev[l][5] = bytes; bytes = align_up(bytes + size_t(shell_sets) * icr::kShellStride * 4);
     off_lev[l][6] = bytes; bytes = align_up(bytes + size_t(shell_sets) * 2 * 8);
+    const int64_t dsets = p->hypergrad ? nsets : 0;
+    off_lev[l][7] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * 8);
+    off_lev[l][8] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * 8);
+    off_lev[l][9] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * ab);
+    off_lev[l][10] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * ab);
   }
   const size_t off_status = bytes; bytes = align_up(bytes + sizeof(int32_t) * (kMaxLevels + 1));
 
@@ -331,6 +338,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   p->l00_64 = reinterpret_cast<double*>(base + off_l64);
   p->l00_c = base + off_lc;
   p->u00_c = base + off_uc;
+  if (p->hypergrad) p->dl00_64 = reinterpret_cast<double*>(base + off_dl00);
   for (int l = 0; l < p->depth; ++l) {
     p->lev[l].r64 = reinterpret_cast<double*>(base + off_lev[l][0]);
     p->lev[l].s64 = reinterpret_cast<double*>(base + off_lev[l][1]);
@@ -340,6 +348,12 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     if (p->shell) {
       p->lev[l].shell_tab = reinterpret_cast<float*>(base + off_lev[l][5]);
       p->lev[l].shell_chk = reinterpret_cast<double*>(base + off_lev[l][6]);
+    }
+    if (p->hypergrad) {
+      p->lev[l].dr64 = reinterpret_cast<double*>(base + off_lev[l][7]);
+      p->lev[l].ds64 = reinterpret_cast<double*>(base + off_lev[l][8]);
+      p->lev[l].dr_c = base + off_lev[l][9];
+      p->lev[l].ds_c = base + off_lev[l][10];
     }
   }
   int32_t* status = reinterpret_cast<int32_t*>(base + off_status);
@@ -360,6 +374,15 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   BUILD_TRY(icr::launch_build_k00(p, p->l00_64, st));
   BUILD_TRY(icr::launch_cholesky_level0(p, p->l00_64, counts + 0, status, st));
   BUILD_TRY(icr::launch_level0_convert(p, st));
+  double* dl_scratch = nullptr;  // 2 n0^2 doubles for the level-0 derivative, freed after the build
+  if (p->hypergrad) {
+    BUILD_TRY(hipMalloc(&dl_scratch, sizeof(double) * 2 * size_t(p->n0) * p->n0));
+    const hipError_t e = icr::launch_level0_length_derivative(p, dl_scratch, st);
+    if (e != hipSuccess) {
+      (void)hipFree(dl_scratch);
+      return bail(ICR_ERR_HIP, std::string("level-0 length derivative: ") + hipGetErrorString(e));
+    }
+  }
   for (int l = 0; l < p->depth; ++l) {
     BUILD_TRY(icr::launch_build_level(p, l, counts + 1 + l, status, st));
     BUILD_TRY(icr::launch_level_convert(p, l, st));
@@ -368,7 +391,11 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   }
   int32_t host_status[kMaxLevels + 1];
   BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
-  BUILD_TRY(hipStreamSynchronize(st));
+  {
+    const hipError_t e = hipStreamSynchronize(st);
+    if (dl_scratch) (void)hipFree(dl_scratch);
+    if (e != hipSuccess) return bail(ICR_ERR_HIP, std::string("build: ") + hipGetErrorString(e));
+  }
 #undef BUILD_TRY
   for (int l = 0; l <= p->depth; ++l) p->clamped[l] = host_status[1 + l];
   for (int l = 0; l < p->depth; ++l) {
@@ -381,6 +408,13 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   }
   if (host_status[0] & 2)
     return bail(ICR_ERR_NOT_PD, "K_00 is not positive definite (a pivot needed clamping; clamping disabled)");
+  if (p->hypergrad) {
+    bool clamped = (host_status[0] & 4) != 0;
+    for (int l = 0; l <= p->depth; ++l) clamped = clamped || p->clamped[l] > 0;
+    if (clamped)
+      return bail(ICR_ERR_NOT_PD,
+                  "hyperparameter gradients need factors without clamped pivots (their derivative is undefined)");
+  }
   if (host_status[0] & 1)
     return bail(ICR_ERR_NOT_PD,
                 "a window covariance K_cc is not positive definite, or a pivot of D needed "
@@ -411,6 +445,7 @@ icr_status icr_plan_get_info(const icr_plan* p, icr_plan_info* info) {
   info->metric_workspace_elems = p->n_xi;
   info->device_bytes = p->pool_bytes;
   for (int l = 0; l < p->depth; ++l) info->level_sets[l] = p->lev[l].nsets;
+  info->hypergrad_workspace_elems = p->hypergrad ? icr::hypergrad_partials(p) : 0;
   return ICR_OK;
 }
 
@@ -517,6 +552,26 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   if (r != ICR_OK) return r;
   return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
                      v, st);
+}
+
+icr_status icr_hyper_grad(const icr_plan* p, int64_t batch, const void* xi, const void* s,
+                          const void* s_levels, const void* s_bar, const void* sbar_levels,
+                          double* grad, double* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  if (!p->hypergrad) return fail(ICR_ERR_UNSUPPORTED, "the plan was built without ICR_FLAG_HYPERGRAD");
+  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "at most 65535 samples per call");
+  const int el = p->elem_bytes;
+  const bool levels = p->depth > 0;
+  if (!xi || !s || !s_bar || !grad || !workspace || (levels && (!s_levels || !sbar_levels)))
+    return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (!aligned(xi, el) || !aligned(s, el) || !aligned(s_bar, el) || (levels && !aligned(s_levels, el)) ||
+      (levels && !aligned(sbar_levels, el)) || !aligned(grad, 8) || !aligned(workspace, 8))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  ICR_HIP_TRY(icr::launch_hyper_grad(p, batch, xi, s, s_levels, s_bar, sbar_levels, grad, workspace,
+                                     static_cast<hipStream_t>(hip_stream)));
+  return ICR_OK;
 }
 
 icr_status icr_cg_workspace_bytes(const icr_plan* p, int64_t batch, int64_t* bytes) {

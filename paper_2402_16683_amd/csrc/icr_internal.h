@@ -70,6 +70,11 @@ struct LevelMats {
   void* r_c = nullptr;    // arithmetic type; stationary: [2^d][3^d]; charted: [2^d*3^d][nsets]
   void* s_c = nullptr;    // arithmetic type; stationary: [2^d][2^d]; charted: [2^d*2^d][nsets]
   int64_t nsets = 0;      // 1; per interior coarse pixel (2-D chart); per radial shell (cylinder)
+  // plans built for hyperparameter gradients: d/d length of R and sqrtD, same layouts
+  double* dr64 = nullptr;
+  double* ds64 = nullptr;
+  void* dr_c = nullptr;
+  void* ds_c = nullptr;
   // Stationary levels: host copies of the FP32 matrices, passed to the fast kernels by
   // value, and the reflection-sector form of R (see sector_kernel in build_f64.hip).
   double* sector64 = nullptr;  // device scratch: [3^d] coefficients, [3^d] off-pattern, [3^d] on-pattern
@@ -113,6 +118,8 @@ struct icr_plan {
   double* l00_64 = nullptr;  // [n0][n0] lower Cholesky factor of K_00
   void* l00_c = nullptr;     // arithmetic type, row-major lower
   void* u00_c = nullptr;     // arithmetic type, row-major upper (= L00^T)
+  double* dl00_64 = nullptr; // [n0][n0] d L00 / d length (plans built for hyperparameter gradients)
+  int hypergrad = 0;         // built with ICR_FLAG_HYPERGRAD
   icr::LevelMats lev[ICR_MAX_DEPTH];
   int32_t clamped[icr::kMaxLevels];
   void* pool = nullptr;      // the one device allocation the plan owns
@@ -137,6 +144,12 @@ hipError_t launch_level0_convert(const icr_plan* p, hipStream_t st);
 hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int32_t* status,
                               hipStream_t st);
 hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st);
+hipError_t launch_level0_length_derivative(const icr_plan* p, double* scratch, hipStream_t st);
+// Hyperparameter gradients (hypergrad.hip)
+int64_t hypergrad_partials(const icr_plan* p);
+hipError_t launch_hyper_grad(const icr_plan* p, int64_t batch, const void* xi, const void* s,
+                             const void* s_levels, const void* s_bar, const void* sbar_levels,
+                             double* grad, double* partials, hipStream_t st);
 hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st);
 hipError_t launch_shell_sector(const icr_plan* p, int level, hipStream_t st);
 

@@ -35,6 +35,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 KERNELS = {"matern12": 0, "matern32": 1, "matern52": 2, "sqexp": 3}
 CHARTS = {"regular": 0, "logradial2d": 1, "logradial_cyl3d": 2}
 FLAG_NO_CLAMP = 1
+FLAG_HYPERGRAD = 2
 
 
 class IcrConfig(ctypes.Structure):
@@ -54,7 +55,8 @@ class IcrPlanInfo(ctypes.Structure):
                 ("n_xi", ctypes.c_int64), ("n_out", ctypes.c_int64),
                 ("workspace_elems", ctypes.c_int64), ("metric_workspace_elems", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64),
-                ("level_sets", ctypes.c_int64 * ICR_MAX_DEPTH)]
+                ("level_sets", ctypes.c_int64 * ICR_MAX_DEPTH),
+                ("hypergrad_workspace_elems", ctypes.c_int64)]
 
 
 class ICRError(RuntimeError):
@@ -93,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_cg_workspace_bytes": [vp, i64, ctypes.POINTER(i64)],
         "icr_cg_metric": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
         "icr_adjoint_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
+        "icr_hyper_grad": [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp],
         "icr_plan_destroy": [vp],
     }
     for name, args in sigs.items():
@@ -136,7 +139,7 @@ def _stream_handle(stream):
 
 def make_config(ndim, shape0, depth, distances0, kernel="matern32", scale=1.0, length=0.1,
                 chart="regular", chart_params=(0.1, math.log(10.0), 0.5 * math.pi),
-                precision="f32", clamp=True) -> IcrConfig:
+                precision="f32", clamp=True, hypergrad=False) -> IcrConfig:
     c = IcrConfig()
     c.ndim = ndim
     for a in range(3):
@@ -146,7 +149,7 @@ def make_config(ndim, shape0, depth, distances0, kernel="matern32", scale=1.0, l
     c.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     c.chart = CHARTS[chart] if isinstance(chart, str) else int(chart)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    c.flags = 0 if clamp else FLAG_NO_CLAMP
+    c.flags = (0 if clamp else FLAG_NO_CLAMP) | (FLAG_HYPERGRAD if hypergrad else 0)
     c.reserved = 0
     c.scale = scale
     c.length = length
@@ -200,7 +203,8 @@ def icr_plan_get_info(plan: Plan) -> dict:
         level_offsets=[info.level_offsets[l] for l in range(depth + 2)],
         n_xi=info.n_xi, n_out=info.n_out, workspace_elems=info.workspace_elems,
         metric_workspace_elems=info.metric_workspace_elems, device_bytes=info.device_bytes,
-        level_sets=[info.level_sets[l] for l in range(depth)])
+        level_sets=[info.level_sets[l] for l in range(depth)],
+        hypergrad_workspace_elems=info.hypergrad_workspace_elems)
 
 
 def icr_plan_copy_level0(plan: Plan) -> np.ndarray:
@@ -319,6 +323,37 @@ def _ptr(t):
 
 def _stride(t):
     return 0 if t is None else (t.stride(0) if t.dim() > 1 else t.numel())
+
+
+def icr_hyper_grad(plan: Plan, xi, s, s_levels, s_bar, sbar_levels, grad=None, workspace=None, stream=None):
+    """(dE/dsigma, dE/dlength) of E = <s_bar, L xi> per sample, float64 (batch, 2), from a
+    forward (xi -> s, workspace s_levels) and an adjoint (s_bar, workspace sbar_levels)."""
+    import torch
+    for t, name in ((xi, "xi"), (s, "s"), (s_bar, "s_bar"), (s_levels, "s_levels"), (sbar_levels, "sbar_levels")):
+        _check_tensor(t, plan, name)
+    batch = _batch_of(xi, plan.info["n_xi"])
+    if grad is None:
+        grad = torch.empty((batch, 2), dtype=torch.float64, device=xi.device)
+    if workspace is None:
+        workspace = torch.empty((batch, max(plan.info["hypergrad_workspace_elems"], 1)), dtype=torch.float64,
+                                device=xi.device)
+    if grad.dtype != torch.float64 or grad.numel() < 2 * batch or workspace.dtype != torch.float64:
+        raise ValueError("grad and workspace must be float64 device tensors")
+    _check(load_library().icr_hyper_grad(plan.handle, batch, xi.data_ptr(), s.data_ptr(), s_levels.data_ptr(),
+                                         s_bar.data_ptr(), sbar_levels.data_ptr(), grad.data_ptr(),
+                                         workspace.data_ptr(), _stream_handle(stream)))
+    return grad
+
+
+def hyper_grad(plan: Plan, xi, s_bar, stream=None):
+    """Forward, adjoint and icr_hyper_grad in one call: returns (s, xi_bar, grad)."""
+    batch = _batch_of(xi, plan.info["n_xi"])
+    ws_f = workspace_for(plan, batch)
+    ws_a = workspace_for(plan, batch)
+    s = icr_forward(plan, xi, workspace=ws_f, stream=stream)
+    xi_bar = icr_adjoint(plan, s_bar, workspace=ws_a, stream=stream)
+    grad = icr_hyper_grad(plan, xi, s, ws_f, s_bar, ws_a, stream=stream)
+    return s, xi_bar, grad
 
 
 def icr_forward_level(plan: Plan, level: int, s_coarse, xi_fine, s_fine, stream=None):

@@ -89,6 +89,7 @@ def test_hot_calls_reject_a_null_plan_and_negative_batch():
     assert "plan" in B.icr_last_error()
     assert lib.icr_adjoint(None, 1, None, None, None, None) == 1
     assert lib.icr_metric_apply(None, 1, None, 0, None, None, None, None) == 1
+    assert lib.icr_hyper_grad(None, 1, None, None, None, None, None, None, None, None) == 1
     assert lib.icr_plan_destroy(None) == 0 and B.icr_last_error() == ""
     info = B.IcrPlanInfo()
     assert lib.icr_plan_get_info(None, ctypes.byref(info)) == 1

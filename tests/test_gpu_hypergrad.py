@@ -1,0 +1,155 @@
+"""Gradients with respect to the kernel hyperparameters (scale, length scale).
+
+The device result of icr_hyper_grad (FP64 length derivatives of L00, R and sqrtD built
+on the device, contracted with the forward's levels and the adjoint's cotangents) is
+compared with the oracle's hyper_grad on the same inputs. Bound: the difference is at
+most tol times the sum of the magnitudes of all terms of the contraction (computed
+with the oracle's derivative matrices), tol = 1e-9 (FP64), 1e-5 (FP32), 1e-2 (BF16
+storage of every level). A second check needs no oracle at all: central differences
+of <ybar, L(theta) xi> over FP64 device plans built at theta +- h.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import icr_oracle as O
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-9, "f32": 1e-5, "bf16": 1e-2}
+
+CASES = [
+    C.from_workload("icr1d_m32_12to260", batch=2, name="1d_m32_full_f64"),
+    C.case(2, (8, 7), 3, (0.06, 0.07), "matern52", 0.2, batch=2, name="2d_m52_f32"),
+    C.from_workload("icr3d_m52_10to388", depth=3, name="3d_m52_10to52_f32"),
+    C.from_workload("icr3d_m52_10to388", depth=2, precision="bf16", name="3d_m52_10to28_bf16"),
+    C.from_workload("icr3d_m52_10to388", depth=2, precision="f64", name="3d_m52_10to28_f64"),
+    C.from_workload("icr2d_chart_24to1284", depth=2, name="2d_chart_24to84_f32"),
+    C.from_workload("icr3d_chart_10to388", depth=2, name="3d_chart_10to28_f32"),
+    C.from_workload("icr3d_m52_10to388", name="3d_m52_full_f32"),
+]
+
+
+def _plan(c, **over):
+    from paper_2402_16683_amd import icr as B
+    kw = dict(kernel=c["kernel"], scale=c["scale"], length=c["length"], chart=c["chart"],
+              chart_params=c["chart_params"], precision=c["precision"], clamp=c["clamp"], hypergrad=True)
+    kw.update(over)
+    return B.icr_build_matrices(B.make_config(c["ndim"], c["shape0"], c["depth"], c["delta0"], **kw))
+
+
+def _magnitudes(model, xi, y):
+    """Sum of |terms| of both gradients (scale of the rounding bound)."""
+    d = model.cfg.ndim
+    batch = xi.shape[:-1]
+    s_final, s_levels = model.forward(xi, return_levels=True)
+    _, cot = model.adjoint(y, return_levels=True)
+    mag_sigma = np.sum(np.abs(y * s_final), axis=-1) / model.cfg.scale
+    d_l00, d_r, d_s = O.length_derivatives(model)
+    mag = np.sum(np.abs(cot[0]) * (np.abs(xi[..., model.level_slice(0)]) @ np.abs(d_l00).T), axis=-1)
+    for l in range(model.cfg.depth):
+        s_l = np.abs(s_levels[l]).reshape(batch + model.shapes[l])
+        xi_f = np.abs(xi[..., model.level_slice(l + 1)]).reshape(batch + model.shapes[l + 1])
+        t = O.refine(s_l, xi_f, np.abs(d_r[l]), np.abs(d_s[l]), d).reshape(batch + (-1,))
+        mag = mag + np.sum(np.abs(cot[l + 1]) * t, axis=-1)
+    return np.stack([mag_sigma, mag], axis=-1)
+
+
+@pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
+def test_hyper_grad_matches_the_oracle(c):
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan = _plan(c)
+    info = plan.info
+    nb = c["batch"]
+    xi = W.standard_normal(info["n_xi"], seed=30, batch=nb)
+    y = W.standard_normal(info["n_out"], seed=31, batch=nb)
+    xi_d, y_d = C.to_device(xi, plan), C.to_device(y, plan)
+    s, xb, g = B.hyper_grad(plan, xi_d, y_d)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    model = C.oracle_model(c)
+    xs, ys = C.stored_values(xi, c["precision"]), C.stored_values(y, c["precision"])
+    ref = O.hyper_grad(model, xs, ys)
+    mag = _magnitudes(model, xs, ys)
+    err = np.abs(g - ref) / mag
+    print(f"[errors] {c['name']} hyper_grad: sigma {err[:, 0].max():.2e}, length {err[:, 1].max():.2e} "
+          f"(of the term magnitudes); relative to |g|: {np.max(np.abs(g - ref) / np.abs(ref)):.2e}")
+    assert np.all(np.isfinite(g))
+    assert np.all(err <= TOL[c["precision"]])
+    # bitwise reproducible
+    _, _, g2 = B.hyper_grad(plan, xi_d, y_d)
+    assert np.array_equal(g2.cpu().numpy(), g)
+
+
+@pytest.mark.parametrize("c", [CASES[0], CASES[1], C.case(3, (5, 6, 5), 1, (0.2, 0.15, 0.2), "matern32", 0.4,
+                                                         chart="logradial_cyl3d",
+                                                         chart_params=(0.1, math.log(10.0), math.pi / 2, 1.0),
+                                                         name="3d_chart_small")],
+                         ids=["1d", "2d", "chart3d"])
+def test_hyper_grad_matches_device_finite_differences(c):
+    """Central differences of <ybar, L(theta) xi> over FP64 device plans at theta +- h."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = dict(c, precision="f64", batch=1)
+    plan = _plan(c)
+    info = plan.info
+    xi = torch.from_numpy(W.standard_normal(info["n_xi"], seed=40)).cuda()
+    y = torch.from_numpy(W.standard_normal(info["n_out"], seed=41)).cuda()
+    _, _, g = B.hyper_grad(plan, xi, y)
+
+    def energy(**over):
+        p = _plan(c, hypergrad=False, **over)
+        return float(torch.dot(B.icr_forward(p, xi), y))
+
+    hs, hl = 1e-6 * c["scale"], 1e-6 * c["length"]
+    fd_s = (energy(scale=c["scale"] + hs) - energy(scale=c["scale"] - hs)) / (2 * hs)
+    fd_l = (energy(length=c["length"] + hl) - energy(length=c["length"] - hl)) / (2 * hl)
+    g = g.cpu().numpy()[0]
+    assert g[0] == pytest.approx(fd_s, rel=1e-6)
+    assert g[1] == pytest.approx(fd_l, rel=1e-5, abs=1e-7 * abs(fd_l) + 1e-9)
+
+
+def test_autograd_returns_hyperparameter_gradients():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    from paper_2402_16683_amd.autograd import icr_sample_hyper
+    c = CASES[1]
+    plan = _plan(dict(c, precision="f64"))
+    info = plan.info
+    xi = torch.from_numpy(W.standard_normal(info["n_xi"], seed=50, batch=2)).cuda().requires_grad_(True)
+    theta = torch.tensor([c["scale"], c["length"]], dtype=torch.float64, requires_grad=True)
+    target = torch.from_numpy(W.standard_normal(info["n_out"], seed=51, batch=2)).cuda()
+    s = icr_sample_hyper(plan, xi, theta)
+    loss = 0.5 * ((s - target) ** 2).sum()
+    loss.backward()
+    grad_s = (s - target).detach()
+    _, xb, g = B.hyper_grad(plan, xi.detach(), grad_s.contiguous())
+    assert torch.allclose(xi.grad, xb, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(theta.grad.numpy(), g.sum(0).cpu().numpy(), rtol=1e-12)
+    with pytest.raises(ValueError):
+        icr_sample_hyper(plan, xi, torch.tensor([c["scale"], 2 * c["length"]], dtype=torch.float64))
+
+
+def test_hyper_grad_needs_the_flag_and_unclamped_factors():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = CASES[1]
+    plan = _plan(c, hypergrad=False)
+    info = plan.info
+    assert info["hypergrad_workspace_elems"] == 0
+    xi = torch.zeros((1, info["n_xi"]), device="cuda")
+    y = torch.zeros((1, info["n_out"]), device="cuda")
+    ws = B.workspace_for(plan, 1)
+    with pytest.raises(B.ICRError) as exc:
+        B.icr_hyper_grad(plan, xi, y, ws, y, ws)
+    assert exc.value.status == 5
+    # the squared-exponential workload clamps pivots of its last level's D
+    se = C.from_workload("icr2d_se_16to1540_b16")
+    with pytest.raises(B.ICRError) as exc:
+        _plan(se)
+    assert exc.value.status == 2 and "clamped" in str(exc.value)
