@@ -622,6 +622,13 @@ hipError_t launch_sector(const icr_plan* p, int level, hipStream_t st) {
     case 2: sector_kernel<2><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
     default: sector_kernel<3><<<1, 64, 0, st>>>(m.r64, m.sector64); break;
   }
+  if (m.dr64 && m.dsector64) {  // the length derivative of R has the same symmetry
+    switch (p->ndim) {
+      case 1: sector_kernel<1><<<1, 64, 0, st>>>(m.dr64, m.dsector64); break;
+      case 2: sector_kernel<2><<<1, 64, 0, st>>>(m.dr64, m.dsector64); break;
+      default: sector_kernel<3><<<1, 64, 0, st>>>(m.dr64, m.dsector64); break;
+    }
+  }
   return hipGetLastError();
 }
 
@@ -630,6 +637,8 @@ hipError_t launch_shell_sector(const icr_plan* p, int level, hipStream_t st) {
   const unsigned threads = 64;
   const unsigned blocks = static_cast<unsigned>((m.nsets + threads - 1) / threads);
   shell_sector_kernel<<<blocks, threads, 0, st>>>(m.r64, m.s64, m.nsets, m.shell_tab, m.shell_chk);
+  if (m.dr64 && m.dshell_tab)
+    shell_sector_kernel<<<blocks, threads, 0, st>>>(m.dr64, m.ds64, m.nsets, m.dshell_tab, m.dshell_chk);
   return hipGetLastError();
 }
 

@@ -185,41 +185,71 @@ hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_
   return hipSuccess;
 }
 
-// Host copies of a stationary level's FP32 matrices and its sector form (the fast
-// kernels take them by value). Synchronous; called at build and after set_refinement.
-icr_status refresh_host_copies(icr_plan* p, int level) {
-  icr::LevelMats& m = p->lev[level];
-  m.sector_ok = false;
-  m.sector_asym = 1.0;
-  m.shell_ok = false;
-  m.shell_asym = 1.0;
-  if (p->shell && p->precision != ICR_F64) {
-    std::vector<double> chk(static_cast<size_t>(2 * m.nsets));
-    ICR_HIP_TRY(hipMemcpy(chk.data(), m.shell_chk, sizeof(double) * chk.size(), hipMemcpyDeviceToHost));
-    double worst = 0.0;
-    for (int64_t s = 0; s < m.nsets; ++s) {
-      const double off = chk[2 * s], on = chk[2 * s + 1];
-      worst = std::fmax(worst, on > 0.0 ? off / on : 1.0);
-      if (!std::isfinite(off) || !std::isfinite(on)) worst = 1.0;
-    }
-    m.shell_asym = worst;
-    m.shell_ok = worst <= icr::kSectorTolerance;
-    return ICR_OK;
+// Worst off-pattern / on-pattern ratio over a shell table's sets (device check array).
+icr_status shell_asymmetry(const double* dev_chk, int64_t nsets, double* worst) {
+  std::vector<double> chk(static_cast<size_t>(2 * nsets));
+  ICR_HIP_TRY(hipMemcpy(chk.data(), dev_chk, sizeof(double) * chk.size(), hipMemcpyDeviceToHost));
+  double w = 0.0;
+  for (int64_t s = 0; s < nsets; ++s) {
+    const double off = chk[2 * s], on = chk[2 * s + 1];
+    w = std::fmax(w, on > 0.0 ? off / on : 1.0);
+    if (!std::isfinite(off) || !std::isfinite(on)) w = 1.0;
   }
-  if (p->charted || p->precision == ICR_F64) return ICR_OK;
-  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
-  ICR_HIP_TRY(hipMemcpy(m.h_r, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost));
-  ICR_HIP_TRY(hipMemcpy(m.h_s, m.s_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
+  *worst = w;
+  return ICR_OK;
+}
+
+// Sector coefficients (FP32) and the off / on-pattern ratio of a device sector array.
+icr_status sector_host(const double* dev_sector, int nw, float* coef, double* asym) {
   double sec[3 * 27];
-  ICR_HIP_TRY(hipMemcpy(sec, m.sector64, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost));
+  ICR_HIP_TRY(hipMemcpy(sec, dev_sector, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost));
   double off = 0.0, on = 0.0;
   for (int t = 0; t < nw; ++t) {
-    m.h_sector[t] = static_cast<float>(sec[t]);
+    coef[t] = static_cast<float>(sec[t]);
     off = std::fmax(off, sec[nw + t]);
     on = std::fmax(on, sec[2 * nw + t]);
   }
-  m.sector_asym = on > 0.0 ? off / on : 1.0;
-  m.sector_ok = std::isfinite(m.sector_asym) && m.sector_asym <= icr::kSectorTolerance;
+  *asym = on > 0.0 ? off / on : 1.0;
+  return ICR_OK;
+}
+
+// Host copies of a stationary level's FP32 matrices and its sector form (the fast
+// kernels take them by value), and the symmetry checks of the sector and shell forms
+// (also of the length derivatives on plans built for hyperparameter gradients).
+// Synchronous; called at build and after set_refinement.
+icr_status refresh_host_copies(icr_plan* p, int level) {
+  icr::LevelMats& m = p->lev[level];
+  m.sector_ok = m.shell_ok = m.dsector_ok = m.dshell_ok = false;
+  m.sector_asym = 1.0;
+  m.shell_asym = 1.0;
+  if (p->precision == ICR_F64) return ICR_OK;
+  const auto ok = [](double asym) { return std::isfinite(asym) && asym <= icr::kSectorTolerance; };
+  if (p->shell) {
+    icr_status r = shell_asymmetry(m.shell_chk, m.nsets, &m.shell_asym);
+    if (r != ICR_OK) return r;
+    m.shell_ok = ok(m.shell_asym);
+    if (m.dshell_tab) {
+      double asym = 1.0;
+      r = shell_asymmetry(m.dshell_chk, m.nsets, &asym);
+      if (r != ICR_OK) return r;
+      m.dshell_ok = ok(asym);
+    }
+    return ICR_OK;
+  }
+  if (p->charted) return ICR_OK;
+  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
+  ICR_HIP_TRY(hipMemcpy(m.h_r, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost));
+  ICR_HIP_TRY(hipMemcpy(m.h_s, m.s_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
+  icr_status r = sector_host(m.sector64, nw, m.h_sector, &m.sector_asym);
+  if (r != ICR_OK) return r;
+  m.sector_ok = ok(m.sector_asym);
+  if (m.dsector64) {
+    ICR_HIP_TRY(hipMemcpy(m.h_ds, m.ds_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
+    double asym = 1.0;
+    r = sector_host(m.dsector64, nw, m.h_dsector, &asym);
+    if (r != ICR_OK) return r;
+    m.dsector_ok = ok(asym);
+  }
   return ICR_OK;
 }
 
@@ -302,7 +332,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   const size_t off_lc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
   const size_t off_uc = bytes; bytes = align_up(bytes + size_t(p->n0) * p->n0 * ab);
   const size_t off_dl00 = bytes; bytes = align_up(bytes + (p->hypergrad ? size_t(p->n0) * p->n0 * 8 : 0));
-  size_t off_lev[ICR_MAX_DEPTH][11];
+  size_t off_lev[ICR_MAX_DEPTH][14];
   for (int l = 0; l < p->depth; ++l) {
     int64_t nsets = 1;
     if (p->shell)
@@ -323,6 +353,10 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][8] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * 8);
     off_lev[l][9] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * ab);
     off_lev[l][10] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * ab);
+    off_lev[l][11] = bytes; bytes = align_up(bytes + (p->hypergrad && !p->charted ? size_t(3) * nw * 8 : 0));
+    const int64_t dshell = p->hypergrad && p->shell ? nsets : 0;
+    off_lev[l][12] = bytes; bytes = align_up(bytes + size_t(dshell) * icr::kShellStride * 4);
+    off_lev[l][13] = bytes; bytes = align_up(bytes + size_t(dshell) * 2 * 8);
   }
   const size_t off_status = bytes; bytes = align_up(bytes + sizeof(int32_t) * (kMaxLevels + 1));
 
@@ -354,6 +388,11 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
       p->lev[l].ds64 = reinterpret_cast<double*>(base + off_lev[l][8]);
       p->lev[l].dr_c = base + off_lev[l][9];
       p->lev[l].ds_c = base + off_lev[l][10];
+      if (!p->charted) p->lev[l].dsector64 = reinterpret_cast<double*>(base + off_lev[l][11]);
+      if (p->shell) {
+        p->lev[l].dshell_tab = reinterpret_cast<float*>(base + off_lev[l][12]);
+        p->lev[l].dshell_chk = reinterpret_cast<double*>(base + off_lev[l][13]);
+      }
     }
   }
   int32_t* status = reinterpret_cast<int32_t*>(base + off_status);

@@ -89,6 +89,15 @@ struct LevelMats {
   double* shell_chk = nullptr;  // device, [nsets][2]: max off-pattern, max on-pattern |M|
   double shell_asym = 1.0;      // max over sets of off-pattern / on-pattern
   bool shell_ok = false;        // every set is symmetric in the two axes to FP32 precision
+  // Plans built for hyperparameter gradients: the same fast-kernel forms of dR / dsqrtD
+  // (d / d length), used by the gradient contraction.
+  double* dsector64 = nullptr;
+  float h_dsector[27];
+  float h_ds[8 * 8];
+  bool dsector_ok = false;
+  float* dshell_tab = nullptr;
+  double* dshell_chk = nullptr;
+  bool dshell_ok = false;
 };
 
 // Floats per set of a shell table: C[9][2][3], sqrtD lower (36), padding to 16 bytes.
@@ -171,6 +180,11 @@ struct RefineFwdArgs {
   void* s_out; int64_t s_out_bs;       // fine field, level l+1
   const void* w; int64_t w_bs;         // optional: s_out *= w (arithmetic type)
   int64_t batch;
+  // gradient contraction (try_refine3_dot_sector): instead of storing the fine field,
+  // sum <dot, fine field> per workgroup into partial[b * partial_bs + workgroup]
+  const void* dot = nullptr; int64_t dot_bs = 0;
+  double* partial = nullptr; int64_t partial_bs = 0;
+  double* partial_sig = nullptr;       // and <dot, value sqrtD xi>, same layout
 };
 struct RefineAdjArgs {
   const void* y; int64_t y_bs;          // fine cotangent, level l+1
@@ -181,6 +195,12 @@ struct RefineAdjArgs {
 };
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st);
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
+// The 3-D fast forward with the derivative matrices of the level and a dot-product
+// epilogue (a.dot, a.partial, a.partial_sig); reports the workgroups per sample
+// (partial sums written to each) in *wgs. False when the level or the buffers do not qualify or more than max_wgs
+// workgroups per sample would be needed.
+bool try_refine3_dot_sector(const icr_plan* p, int level, const RefineFwdArgs& a, int64_t max_wgs,
+                            hipStream_t st, hipError_t* err, int64_t* wgs);
 hipError_t launch_refine_fwd_generic(const icr_plan* p, int level, const RefineFwdArgs& a,
                                      hipStream_t st);
 // Specialised kernels: return false (launching nothing) when the level or the buffers

@@ -25,6 +25,8 @@
 // the neighbouring rows through LDS, inside a tile of block pairs whose outer ring
 // (halo) is recomputed by each tile.
 // Every coarse cotangent is summed by one thread in a fixed order.
+#include <algorithm>
+
 #include "icr_internal.h"
 #include "sweep_io.h"
 
@@ -56,13 +58,27 @@ struct ShellMats {
 // the same planes): read it through the constant address space, which lets the
 // compiler use scalar loads (the table is never written while a sweep runs).
 typedef const float __attribute__((address_space(4))) const_float;
-__device__ __forceinline__ const const_float* shell_row(const ShellMats& m, int set) {
+template <typename M>
+__device__ __forceinline__ const const_float* shell_row(const M& m, int set) {
   return (const const_float*)(m.tab + static_cast<int64_t>(set) * kShellStride);
 }
+// The gradient contraction's matrices: the length derivatives of the level in the same
+// form, plus the value sqrtD (its product with the excitations gives the scale term).
+struct DotStationary {
+  Sector3 k;      // derivative: sector coefficients of dR, dsqrtD
+  float sv[36];   // value sqrtD, lower by rows
+};
+struct DotShell {
+  const float* tab;   // derivative table (rows as in ShellMats)
+  int nsets;
+  const float* vtab;  // value table
+};
 template <typename M>
 constexpr bool kIsShell = false;
 template <>
 constexpr bool kIsShell<ShellMats> = true;
+template <>
+constexpr bool kIsShell<DotShell> = true;
 
 // The four coarse values x = 2q .. 2q+3 of rows y-1, y, y+1 of one plane.
 struct Raw3 {
@@ -182,13 +198,18 @@ struct Fwd3Geom {
 // The z loop is unrolled by two with ping-pong load buffers, and every load goes to a
 // clamped in-bounds address: loaded registers are never copied or loaded under a
 // branch, so the next step's loads stay in flight while the current step computes.
-template <typename TS, bool kW, typename M>
+// kDot: the gradient contraction. The kernel applies the level's derivative matrices
+// and, instead of storing the fine block, adds <cotangent block, block> to an FP64 sum
+// per lane (in z order), and <cotangent block, value sqrtD xi block> to a second one;
+// both are reduced over the workgroup by a fixed tree.
+template <typename TS, bool kW, typename M, bool kDot = false>
 __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, M m) {
   // plane-major order (no XCD renumbering): the forward's only shared data is the
   // small coarse level, and this order measured faster on the 388^3 level
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.rows, g.zchunk, g.nfy, g.nfx, g.xy_blocks, a.s_in, a.s_in_bs, a.xi,
              a.xi_bs, a.s_out, a.s_out_bs);
   if (kW) fetch_args(a.w, a.w_bs);
+  if (kDot) fetch_args(a.dot, a.dot_bs, a.partial, a.partial_bs, a.partial_sig);
   if constexpr (kIsShell<M>) fetch_args(m.tab);
   const int tile = static_cast<int>(blockIdx.x);
   // no early exit: threads past the last pair work on the last pair and store nothing,
@@ -207,6 +228,8 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
   const TS* xi = static_cast<const TS*>(a.xi) + b * a.xi_bs;
   TS* so = static_cast<TS*>(a.s_out) + b * a.s_out_bs;
   const float* w = kW ? static_cast<const float*>(a.w) + b * a.w_bs : nullptr;
+  const TS* cot = kDot ? static_cast<const TS*>(a.dot) + b * a.dot_bs : nullptr;
+  double dot_acc = 0.0, sig_acc = 0.0;
   const int64_t cplane = static_cast<int64_t>(g.ny) * g.nx;
   const int64_t fplane = static_cast<int64_t>(g.nfy) * g.nfx;
   const int64_t frow = static_cast<int64_t>(2 * (y - 1)) * g.nfx + 4 * q;
@@ -214,7 +237,7 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
   struct Step {
     Raw3 raw;            // coarse plane z + 1
     float4 xr[2][2];     // excitations of the pair's children in plane z
-    float4 wr[2][2];     // metric weights (kW)
+    float4 wr[2][2];     // metric weights (kW) or the cotangent rows (kDot)
   };
   auto fine_off = [&](int z, int bz, int by) {
     return (2 * (z - 1) + bz) * fplane + frow + by * g.nfx;
@@ -228,12 +251,14 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
       for (int by = 0; by < 2; ++by) {
         st.xr[bz][by] = ld4_stream<TS>(xi + fine_off(zc, bz, by));
         if (kW) st.wr[bz][by] = *reinterpret_cast<const float4*>(w + fine_off(zc, bz, by));
+        if (kDot) st.wr[bz][by] = ld4_stream<TS>(cot + fine_off(zc, bz, by));
       }
   };
   float T0[2][9], T1[2][9], T2[2][9];
   auto compute_step = [&](int z, const Step& st) {
     plane_stage(st.raw, T2);
     float o[2][8];
+    float u[2][8];  // kDot: value sqrtD times the excitations
     float S[36];
     if constexpr (kIsShell<M>) {
       const auto c = shell_row(m, z - 1);
@@ -261,6 +286,24 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
       for (int c = 0; c < 8; ++c)
 #pragma unroll
         for (int cp = 0; cp <= c; ++cp) o[p][c] = fmaf(S[sd(c, cp)], x[cp], o[p][c]);
+      if constexpr (kDot) {
+        float Sv[36];
+        if constexpr (kIsShell<M>) {
+          const const_float* vr = (const const_float*)(m.vtab + static_cast<int64_t>(z - 1) * kShellStride);
+#pragma unroll
+          for (int e = 0; e < 36; ++e) Sv[e] = vr[54 + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 36; ++e) Sv[e] = m.sv[e];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          float v = 0.0f;
+#pragma unroll
+          for (int cp = 0; cp <= c; ++cp) v = fmaf(Sv[sd(c, cp)], x[cp], v);
+          u[p][c] = v;
+        }
+      }
     }
 #pragma unroll
     for (int bz = 0; bz < 2; ++bz)
@@ -272,7 +315,16 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
           const float4 ww = st.wr[bz][by];
           v.x *= ww.x; v.y *= ww.y; v.z *= ww.z; v.w *= ww.w;
         }
-        if (valid) st4_stream<TS>(so + fine_off(z, bz, by), v);
+        if (kDot) {
+          const float4 cv = st.wr[bz][by];
+          if (valid) {
+            dot_acc += (double(cv.x) * v.x + double(cv.y) * v.y) + (double(cv.z) * v.z + double(cv.w) * v.w);
+            sig_acc += (double(cv.x) * u[0][h] + double(cv.y) * u[0][h + 1]) +
+                       (double(cv.z) * u[1][h] + double(cv.w) * u[1][h + 1]);
+          }
+        } else if (valid) {
+          st4_stream<TS>(so + fine_off(z, bz, by), v);
+        }
       }
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -302,6 +354,23 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
     load_step(z + 4, sb2);
     __builtin_amdgcn_sched_barrier(0);
     compute_step(z + 2, sc2);
+  }
+  if constexpr (kDot) {  // fixed-order trees over the workgroup
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = dot_acc;
+    red[1][threadIdx.x] = sig_acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (static_cast<int>(threadIdx.x) < s) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + s];
+        red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      a.partial[b * a.partial_bs + blockIdx.x] = red[0][0];
+      a.partial_sig[b * a.partial_bs + blockIdx.x] = red[1][0];
+    }
   }
 }
 
@@ -679,7 +748,85 @@ hipError_t fwd_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipS
   return fwd_launch<TS>(p, level, stationary_mats(m), a, st);
 }
 
+// The derivative matrices of a level (plans built for hyperparameter gradients) and its
+// value sqrtD.
+DotStationary dstationary_mats(const LevelMats& m) {
+  DotStationary s;
+  for (int t = 0; t < 27; ++t) s.k.c[t] = m.h_dsector[t];
+  for (int c = 0; c < 8; ++c)
+    for (int cp = 0; cp <= c; ++cp) {
+      s.k.s[c * (c + 1) / 2 + cp] = m.h_ds[c * 8 + cp];
+      s.sv[c * (c + 1) / 2 + cp] = m.h_s[c * 8 + cp];
+    }
+  return s;
+}
+DotShell dshell_mats(const LevelMats& m) { return DotShell{m.dshell_tab, static_cast<int>(m.nsets), m.shell_tab}; }
+
+template <typename TS, typename M>
+hipError_t fwd_dot_launch(const icr_plan* p, int level, const M& k, const RefineFwdArgs& a, int64_t max_wgs,
+                          hipStream_t st, int64_t* wgs) {
+  Fwd3Geom g;
+  g.nz = p->shapes[level][0]; g.ny = p->shapes[level][1]; g.nx = p->shapes[level][2];
+  g.pairs = (g.nx - 2) / 2;
+  g.rows = g.ny - 2;
+  g.nfy = p->shapes[level + 1][1];
+  g.nfx = p->shapes[level + 1][2];
+  const int64_t xy_blocks = (int64_t(g.rows) * g.pairs + 255) / 256;
+  static const int64_t slots =
+      resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false, M, true>), 256);
+  int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
+  chunks = std::min<int64_t>(chunks, max_wgs / xy_blocks);  // caller checked max_wgs >= xy_blocks
+  g.zchunk = static_cast<int>((g.nz - 2 + chunks - 1) / chunks);
+  const int64_t nchunks = (g.nz - 2 + g.zchunk - 1) / g.zchunk;
+  g.xy_blocks = static_cast<int>(xy_blocks);
+  g.nwg = static_cast<int>(xy_blocks * nchunks);
+  *wgs = g.nwg;
+  for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
+    RefineFwdArgs c = a;
+    c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
+    c.s_in = static_cast<const TS*>(a.s_in) + b0 * a.s_in_bs;
+    c.xi = static_cast<const TS*>(a.xi) + b0 * a.xi_bs;
+    c.dot = static_cast<const TS*>(a.dot) + b0 * a.dot_bs;
+    c.partial = a.partial + b0 * a.partial_bs;
+    c.partial_sig = a.partial_sig + b0 * a.partial_bs;
+    const dim3 grid(static_cast<unsigned>(g.nwg), static_cast<unsigned>(c.batch));
+    refine3_fwd_sector<TS, false, M, true><<<grid, 256, 0, st>>>(g, c, k);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TS>
+hipError_t dot_launch(const icr_plan* p, int level, const RefineFwdArgs& a, int64_t max_wgs, hipStream_t st,
+                      int64_t* wgs) {
+  const LevelMats& m = p->lev[level];
+  if (p->shell) return fwd_dot_launch<TS>(p, level, dshell_mats(m), a, max_wgs, st, wgs);
+  return fwd_dot_launch<TS>(p, level, dstationary_mats(m), a, max_wgs, st, wgs);
+}
+
 }  // namespace
+
+bool try_refine3_dot_sector(const icr_plan* p, int level, const RefineFwdArgs& a, int64_t max_wgs,
+                            hipStream_t st, hipError_t* err, int64_t* wgs) {
+  if (p->ndim != 3 || p->precision == ICR_F64) return false;
+  const LevelMats& m = p->lev[level];
+  const bool stationary = !p->charted && m.dsector_ok;
+  const bool shell = p->shell && m.dshell_ok;
+  if (!stationary && !shell) return false;
+  const int* nc = p->shapes[level];
+  if (nc[2] % 2 != 0 || nc[2] < 4) return false;
+  const int64_t nf = int64_t(p->shapes[level + 1][0]) * p->shapes[level + 1][1] * p->shapes[level + 1][2];
+  if (nf >= (int64_t(1) << 31)) return false;
+  const int64_t xy_blocks = (int64_t(nc[1] - 2) * ((nc[2] - 2) / 2) + 255) / 256;
+  if (xy_blocks > max_wgs) return false;
+  const int el = p->elem_bytes;
+  if (!aligned_to(a.xi, 4 * el) || !aligned_to(a.dot, 4 * el) || !aligned_to(a.s_in, 2 * el)) return false;
+  if (a.xi_bs % 4 || a.dot_bs % 4 || a.s_in_bs % 2) return false;
+  *err = p->precision == ICR_F32 ? dot_launch<float>(p, level, a, max_wgs, st, wgs)
+                                 : dot_launch<bf16_t>(p, level, a, max_wgs, st, wgs);
+  return true;
+}
 
 bool try_refine3_fwd_sector(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st,
                             hipError_t* err) {
