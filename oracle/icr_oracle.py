@@ -546,3 +546,63 @@ def hyper_grad(model: ICROracle, xi: np.ndarray, ybar: np.ndarray) -> np.ndarray
         t = refine(s_l, xi_f, d_r[l], d_s[l], d).reshape(batch + (-1,))
         g_len = g_len + np.sum(cot[l + 1] * t, axis=-1)
     return np.stack([g_sigma, g_len], axis=-1)
+
+
+# ---------------------------------------------------------------------------
+# Metric Gaussian Variational Inference around the ICR prior
+# ---------------------------------------------------------------------------
+#
+# Section "Variational Inference": MGVI approximates the posterior by samples drawn
+# around an expansion point with the Fisher metric plus the prior curvature, and
+# alternates between drawing samples and minimising the KL divergence over the
+# expansion point (antithetically mirrored samples, CG for the samples, a Newton-CG
+# minimiser for the KL). Here the likelihood is Gaussian with inverse noise variance
+# w per final pixel, so the energy H(xi) = 1/2 (d - L xi)^T W (d - L xi) + 1/2 xi^T xi
+# has gradient M xi - L^T W d and the metric M = L^T W L + 1 everywhere:
+#  * a sample: r = eta + L^T (sqrt(w) * eta') with eta, eta' standard normal has
+#    covariance M, so delta = M^-1 r (CG) has covariance M^-1, and mean +- delta is an
+#    antithetic pair;
+#  * the KL over antithetic pairs has gradient mean over the pairs of grad H(mean +- delta)
+#    = M mean - L^T W d, and one Newton step mean - M^-1 (M mean - L^T W d) (CG).
+
+def conjugate_gradient(apply, b: np.ndarray, iterations: int) -> np.ndarray:
+    """Textbook CG from x_0 = 0 for exactly `iterations` steps (Hestenes & Stiefel 1952)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    for _ in range(iterations):
+        if rr == 0.0:
+            break
+        q = apply(p)
+        alpha = rr / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x
+
+
+def weighted_adjoint(model: ICROracle, w: np.ndarray, power: float, y: np.ndarray, add=None) -> np.ndarray:
+    """L^T (w^power * y) (+ add)."""
+    out = model.adjoint(np.asarray(w, dtype=np.float64) ** power * np.asarray(y, dtype=np.float64))
+    return out if add is None else out + np.asarray(add, dtype=np.float64)
+
+
+def mgvi_draw(model: ICROracle, w: np.ndarray, eta_xi: np.ndarray, eta_data: np.ndarray, iterations: int):
+    """One MGVI sample displacement delta = M^-1 (eta + L^T (sqrt(w) eta')) by CG; mean +- delta."""
+    r = weighted_adjoint(model, w, 0.5, eta_data, add=eta_xi)
+    return conjugate_gradient(lambda v: model.metric(w, v), r, iterations)
+
+
+def energy_gradient(model: ICROracle, w: np.ndarray, d: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """grad H(xi) = L^T W (L xi - d) + xi."""
+    return model.adjoint(np.asarray(w) * (model.forward(xi) - np.asarray(d))) + xi
+
+
+def mgvi_newton_step(model: ICROracle, w: np.ndarray, b: np.ndarray, mean: np.ndarray, iterations: int):
+    """mean - M^-1 g with g = M mean - b, b = L^T W d (CG for M^-1 g)."""
+    g = model.metric(w, mean) - b
+    return mean - conjugate_gradient(lambda v: model.metric(w, v), g, iterations)

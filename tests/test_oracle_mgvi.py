@@ -1,0 +1,64 @@
+"""Pins of the oracle's MGVI pieces on tiny grids, against dense linear algebra.
+
+The sample map (eta, eta') -> r must have covariance exactly M = I + L^T W L, CG must
+reach the dense solve, the antithetic pair's mean gradient must equal the gradient at
+the mean, and one Newton step must land on the dense posterior mean M^-1 L^T W d.
+"""
+
+import numpy as np
+
+from oracle import icr_oracle as O
+
+CFG = O.ICRConfig(ndim=2, shape0=(6, 5), depth=1, delta0=(1 / 6, 1 / 5), kernel="matern32", length=0.3)
+
+
+def _setup():
+    m = O.build(CFG)
+    rng = np.random.default_rng(17)
+    w = (rng.random(m.out_size) < 0.7) / 0.1 ** 2
+    lmat = m.dense()
+    mmat = lmat.T @ (w[:, None] * lmat) + np.eye(m.n_xi)
+    return m, rng, w, lmat, mmat
+
+
+def test_sample_right_hand_side_has_the_metric_as_covariance():
+    m, rng, w, lmat, mmat = _setup()
+    # the linear map (eta, eta') -> r, column by column
+    cols = [O.weighted_adjoint(m, w, 0.5, np.zeros(m.out_size), add=e) for e in np.eye(m.n_xi)]
+    cols += [O.weighted_adjoint(m, w, 0.5, e, add=np.zeros(m.n_xi)) for e in np.eye(m.out_size)]
+    a = np.stack(cols, axis=1)
+    np.testing.assert_allclose(a @ a.T, mmat, atol=1e-9 * np.abs(mmat).max())
+
+
+def test_cg_reaches_the_dense_solve():
+    m, rng, w, lmat, mmat = _setup()
+    b = rng.standard_normal(m.n_xi)
+    x = O.conjugate_gradient(lambda v: m.metric(w, v), b, 400)
+    np.testing.assert_allclose(x, np.linalg.solve(mmat, b), rtol=1e-8, atol=1e-10)
+
+
+def test_drawn_sample_solves_the_metric_system():
+    m, rng, w, lmat, mmat = _setup()
+    eta, eta_d = rng.standard_normal(m.n_xi), rng.standard_normal(m.out_size)
+    delta = O.mgvi_draw(m, w, eta, eta_d, 400)
+    r = eta + lmat.T @ (np.sqrt(w) * eta_d)
+    np.testing.assert_allclose(mmat @ delta, r, rtol=1e-8, atol=1e-8)
+
+
+def test_antithetic_pair_gradient_equals_the_gradient_at_the_mean():
+    m, rng, w, lmat, mmat = _setup()
+    d = rng.standard_normal(m.out_size)
+    mean, delta = rng.standard_normal((2, m.n_xi))
+    g = 0.5 * (O.energy_gradient(m, w, d, mean + delta) + O.energy_gradient(m, w, d, mean - delta))
+    dense = lmat.T @ (w * (lmat @ mean - d)) + mean
+    np.testing.assert_allclose(g, dense, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(g, mmat @ mean - lmat.T @ (w * d), rtol=1e-10, atol=1e-9)
+
+
+def test_one_newton_step_reaches_the_posterior_mean():
+    m, rng, w, lmat, mmat = _setup()
+    d = rng.standard_normal(m.out_size)
+    b = O.weighted_adjoint(m, w, 1.0, d)
+    np.testing.assert_allclose(b, lmat.T @ (w * d), rtol=1e-10, atol=1e-10)
+    mean = O.mgvi_newton_step(m, w, b, rng.standard_normal(m.n_xi), 400)
+    np.testing.assert_allclose(mean, np.linalg.solve(mmat, lmat.T @ (w * d)), rtol=1e-8, atol=1e-9)
