@@ -280,6 +280,46 @@ def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
     return out
 
 
+def mgvi_bench(B, plan, wl: dict, pairs: int, quiet: bool) -> dict:
+    """One MGVI iteration on the workload as the paper configures it: `pairs`
+    antithetic sample pairs, each delta by 100 CG steps on the metric, then one
+    Newton-CG step of the expansion point with 35 CG steps (mask Bernoulli(0.7),
+    noise sigma 0.1, data from a truth drawn with seed 2)."""
+    import torch
+    info = plan.info
+    n_xi, n_out = info["n_xi"], info["n_out"]
+    mask = torch.from_numpy(W.bernoulli_mask(n_out, 0.7, seed=4)).cuda().to(plan.acc_dtype)
+    w = mask / 0.01
+    xi_true = torch.from_numpy(W.standard_normal_f32(n_xi, seed=2)).cuda().to(plan.dtype)
+    noise = torch.from_numpy(W.standard_normal_f32(n_out, seed=3)).cuda().to(plan.dtype)
+    s = B.icr_forward(plan, xi_true[None])[0]
+    d = (mask.to(plan.dtype) * s + 0.1 * noise).contiguous()
+    # the standard-normal draws are inputs: drawn and uploaded before the timed region
+    eta = torch.from_numpy(W.standard_normal_f32(n_xi, seed=7, batch=pairs)).cuda().to(plan.dtype)
+    eta_d = torch.from_numpy(W.standard_normal_f32(n_out, seed=8, batch=pairs)).cuda().to(plan.dtype)
+    b = B.icr_weighted_adjoint(plan, w, d[None], half=False)
+    mean = torch.zeros((1, n_xi), dtype=plan.dtype, device="cuda")
+    wss = (B.workspace_for(plan, pairs, metric=True),
+           torch.empty(B.icr_cg_workspace_bytes(plan, pairs), dtype=torch.uint8, device="cuda"),
+           torch.empty(B.icr_mgvi_workspace_bytes(plan, 1), dtype=torch.uint8, device="cuda"))
+    B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(2):
+        B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 2
+    products = pairs * 100 + 35 + 1   # metric products on single samples (the samples' CG runs batched)
+    out = {"antithetic_pairs": pairs, "sample_cg_iterations": 100, "newton_cg_iterations": 35,
+           "ms_per_iteration": ms, "sample_metric_products_per_iteration": products,
+           "us_per_sample_metric_product": ms * 1e3 / products,
+           "data": "draws eta seed 7, eta' seed 8 (uploaded before timing); truth seed 2, noise seed 3, mask seed 4"}
+    log(f"mgvi: {ms:.1f} ms per iteration ({pairs} pairs x 100 CG steps + Newton 35 CG steps)", quiet)
+    return out
+
+
 def hyper_grad_bench(B, wl: dict, prec: str, steps: int, quiet: bool) -> dict:
     """Hyperparameter gradients on the workload: a plan built with the length
     derivatives, then per step icr_forward + icr_adjoint + icr_hyper_grad (the full
@@ -515,6 +555,7 @@ def main():
     cg_iters = args.cg_iters if args.cg_iters is not None else (200 if wl["chart"] != "regular" else 0)
     if cg_iters > 0 and not args.copy_probe and prec != "bf16":
         out["cg"] = cg_solve(B, plan, wl, cg_iters, args.quiet)
+        out["mgvi"] = mgvi_bench(B, plan, wl, 3, args.quiet)
     if args.hypergrad_steps > 0 and not args.copy_probe:
         out["hyper_grad"] = hyper_grad_bench(B, wl, prec, args.hypergrad_steps, args.quiet)
     if args.serve_requests > 0 and not args.copy_probe:

@@ -252,6 +252,35 @@ icr_status icr_cg_metric(const icr_plan* plan, int64_t batch, const void* w, int
                          void* workspace, void* hip_stream);
 
 /*
+ * Metric Gaussian Variational Inference around this prior with a Gaussian likelihood
+ * (inverse noise variance w per final pixel), section "Variational Inference". MGVI
+ * draws antithetic samples mean +- delta, delta = M^-1 r with r = eta + L^T (sqrt(w)
+ * eta') for standard-normal eta (n_xi) and eta' (n_out), so that delta has covariance
+ * M^-1 (solve with icr_cg_metric), and moves the expansion point by Newton-CG on the KL
+ * divergence, whose gradient over antithetic pairs is M mean - L^T W d.
+ *
+ * icr_weighted_adjoint: out = L^T (w^p * y) + add with p = 1/2 (half != 0: the sample
+ * right-hand side, add = eta, y = eta') or p = 1 (half == 0: b = L^T W d with y = d,
+ * add = NULL).
+ *   w, w_batch_stride as for icr_metric_apply; y [batch][n_out]; add NULL or
+ *   [batch][n_xi]; out [batch][n_xi]; workspace [batch][metric_workspace_elems]
+ *   (storage type; must not overlap the other buffers).
+ * icr_mgvi_newton_step: mean <- mean - M^-1 (M mean - b) for `batch` independent
+ * problems, M^-1 by `iterations` CG steps from 0 (icr_cg_metric's iteration);
+ * residual_norms as for icr_cg_metric. FP64 and FP32 plans only.
+ *   b, mean   [batch][n_xi]; workspace device, icr_mgvi_workspace_bytes, 256-byte aligned.
+ * Random numbers are inputs: the caller draws eta, eta'. Asynchronous on hip_stream;
+ * no allocation.
+ */
+icr_status icr_weighted_adjoint(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
+                                int32_t half, const void* y, const void* add, void* out, void* workspace,
+                                void* hip_stream);
+icr_status icr_mgvi_workspace_bytes(const icr_plan* plan, int64_t batch, int64_t* bytes);
+icr_status icr_mgvi_newton_step(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
+                                const void* b, void* mean, int32_t iterations, double* residual_norms,
+                                void* workspace, void* hip_stream);
+
+/*
  * One level of the sweep, for callers that pipeline or shard levels themselves
  * (icr_forward and icr_adjoint are these calls in sequence). Strides are elements
  * between consecutive samples and must be >= the level's size.

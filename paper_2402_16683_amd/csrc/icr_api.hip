@@ -646,6 +646,79 @@ icr_status icr_cg_metric(const icr_plan* p, int64_t batch, const void* w, int64_
   return ICR_OK;
 }
 
+icr_status icr_weighted_adjoint(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                                int32_t half, const void* y, const void* add, void* out, void* workspace,
+                                void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "at most 65535 samples per call");
+  const int el = p->elem_bytes;
+  const int ab = acc_bytes_of(p->precision);
+  if (!w || !y || !out || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(y, el) || !aligned(out, el) || !aligned(workspace, el) || !aligned(w, ab) || (add && !aligned(add, el)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  const size_t nx = size_t(batch) * p->n_xi * el;
+  if (icr::overlaps(out, nx, workspace, nx) || (add && icr::overlaps(add, nx, workspace, nx)) ||
+      icr::overlaps(y, size_t(batch) * p->n_out * el, workspace, nx))
+    return fail(ICR_ERR_INVALID_ARG, "workspace overlaps a buffer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // the weighted cotangent at the front of each sample's workspace row, the sweep's
+  // levels behind it
+  ICR_HIP_TRY(icr::launch_weight(p, batch, w, w_batch_stride, y, p->n_out, workspace, p->n_xi, p->n_out, half != 0,
+                                 st));
+  return run_adjoint(p, batch, workspace, p->n_xi, out, at(workspace, p->n_out, el), p->n_xi, add, st);
+}
+
+icr_status icr_mgvi_workspace_bytes(const icr_plan* p, int64_t batch, int64_t* bytes) {
+  icr::clear_error();
+  if (!p || !bytes || batch < 0) return fail(ICR_ERR_INVALID_ARG, "plan or bytes is NULL, or batch < 0");
+  const int64_t vec = (batch * p->n_xi * p->elem_bytes + 255) & ~int64_t(255);
+  *bytes = 2 * vec + icr::cg_workspace_bytes(p, batch);
+  return ICR_OK;
+}
+
+icr_status icr_mgvi_newton_step(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                                const void* b, void* mean, int32_t iterations, double* residual_norms,
+                                void* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK) return cs;
+  if (p->precision == ICR_BF16_F32ACC) return fail(ICR_ERR_UNSUPPORTED, "the Newton step needs an FP64 or FP32 plan");
+  if (iterations < 0) return fail(ICR_ERR_INVALID_ARG, "iterations must be >= 0");
+  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "at most 65535 samples per call");
+  if (batch == 0) return ICR_OK;
+  const int el = p->elem_bytes;
+  if (!w || !b || !mean || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(b, el) || !aligned(mean, el) || !aligned(w, el) || !aligned(workspace, 256) ||
+      (residual_norms && !aligned(residual_norms, 8)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned (workspace needs 256 bytes)");
+  int64_t wsb = 0;
+  (void)icr_mgvi_workspace_bytes(p, batch, &wsb);
+  const size_t nx = size_t(batch) * p->n_xi * el;
+  if (icr::overlaps(b, nx, mean, nx) || icr::overlaps(b, nx, workspace, size_t(wsb)) ||
+      icr::overlaps(mean, nx, workspace, size_t(wsb)))
+    return fail(ICR_ERR_INVALID_ARG, "b, mean and workspace overlap");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t vec = (int64_t(nx) + 255) & ~int64_t(255);
+  char* base = static_cast<char*>(workspace);
+  void* g = base;
+  void* delta = base + vec;
+  void* cg_ws = base + 2 * vec;
+  // g = M mean - b (the KL gradient over antithetic pairs), delta = M^-1 g, mean -= delta;
+  // CG's own metric workspace serves the first product
+  ICR_HIP_TRY(metric_for_cg(p, batch, w, w_batch_stride, mean, g, cg_ws, st));
+  ICR_HIP_TRY(icr::launch_sub(p, batch, g, b, p->n_xi, st));
+  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, g, delta, iterations, residual_norms, cg_ws, st,
+                             metric_for_cg));
+  ICR_HIP_TRY(icr::launch_sub(p, batch, mean, delta, p->n_xi, st));
+  return ICR_OK;
+}
+
 icr_status icr_forward_level(const icr_plan* p, int32_t level, int64_t batch, const void* s_coarse,
                              int64_t coarse_stride, const void* xi_fine, int64_t xi_stride,
                              void* s_fine, int64_t fine_stride, void* hip_stream) {

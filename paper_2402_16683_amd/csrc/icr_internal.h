@@ -154,6 +154,10 @@ hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int
                               hipStream_t st);
 hipError_t launch_level_convert(const icr_plan* p, int level, hipStream_t st);
 hipError_t launch_level0_length_derivative(const icr_plan* p, double* scratch, hipStream_t st);
+// MGVI vector operations (mgvi.hip): y = w^(1/2 or 1) * v; a -= c
+hipError_t launch_weight(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v, int64_t v_bs,
+                         void* y, int64_t y_bs, int64_t n, bool half, hipStream_t st);
+hipError_t launch_sub(const icr_plan* p, int64_t batch, void* a, const void* c, int64_t n, hipStream_t st);
 // Hyperparameter gradients (hypergrad.hip)
 int64_t hypergrad_partials(const icr_plan* p);
 hipError_t launch_hyper_grad(const icr_plan* p, int64_t batch, const void* xi, const void* s,

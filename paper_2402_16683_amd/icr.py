@@ -96,6 +96,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_cg_metric": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
         "icr_adjoint_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_hyper_grad": [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp],
+        "icr_weighted_adjoint": [vp, i64, vp, i64, i32, vp, vp, vp, vp, vp],
+        "icr_mgvi_workspace_bytes": [vp, i64, ctypes.POINTER(i64)],
+        "icr_mgvi_newton_step": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
         "icr_plan_destroy": [vp],
     }
     for name, args in sigs.items():
@@ -402,6 +405,88 @@ def icr_cg_metric(plan: Plan, w, b, iterations: int, x=None, residual_norms=Fals
     _check(load_library().icr_cg_metric(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(), x.data_ptr(),
                                         iterations, _ptr(norms), workspace.data_ptr(), _stream_handle(stream)))
     return (x, norms) if residual_norms else x
+
+
+def _weights(plan, w):
+    if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
+        raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
+    return 0 if w.dim() == 1 else w.shape[-1]
+
+
+def icr_weighted_adjoint(plan: Plan, w, y, add=None, half=True, out=None, workspace=None, stream=None):
+    """out = L^T (w^(1/2 if half else 1) * y) + add (add may be None)."""
+    _check_tensor(y, plan, "y")
+    batch = _batch_of(y, plan.info["n_out"])
+    w_stride = _weights(plan, w)
+    if add is not None:
+        _check_tensor(add, plan, "add")
+    if out is None:
+        out = _empty(y.shape[:-1] + (plan.info["n_xi"],), plan)
+    _check_tensor(out, plan, "out")
+    if workspace is None:
+        workspace = workspace_for(plan, batch, metric=True)
+    _check(load_library().icr_weighted_adjoint(plan.handle, batch, w.data_ptr(), w_stride, 1 if half else 0,
+                                               y.data_ptr(), _ptr(add), out.data_ptr(), workspace.data_ptr(),
+                                               _stream_handle(stream)))
+    return out
+
+
+def icr_mgvi_workspace_bytes(plan: Plan, batch: int) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().icr_mgvi_workspace_bytes(plan.handle, batch, ctypes.byref(out)))
+    return out.value
+
+
+def icr_mgvi_newton_step(plan: Plan, w, b, mean, iterations: int, residual_norms=False, workspace=None,
+                         stream=None):
+    """mean <- mean - M^-1 (M mean - b) in place (CG with `iterations` steps); returns mean
+    (and the CG residual norms when asked)."""
+    import torch
+    _check_tensor(b, plan, "b")
+    _check_tensor(mean, plan, "mean")
+    batch = _batch_of(mean, plan.info["n_xi"])
+    w_stride = _weights(plan, w)
+    if workspace is None:
+        workspace = torch.empty(icr_mgvi_workspace_bytes(plan, batch), dtype=torch.uint8, device="cuda")
+    norms = torch.empty((batch, iterations + 1), dtype=torch.float64, device="cuda") if residual_norms else None
+    _check(load_library().icr_mgvi_newton_step(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(),
+                                               mean.data_ptr(), iterations, _ptr(norms), workspace.data_ptr(),
+                                               _stream_handle(stream)))
+    return (mean, norms) if residual_norms else mean
+
+
+def mgvi(plan: Plan, w, d, n_pairs: int = 3, n_iterations: int = 3, sample_iterations: int = 100,
+         newton_iterations: int = 35, seed: int = 0, mean=None, stream=None):
+    """MGVI with antithetic samples: per iteration draw n_pairs sample displacements
+    delta = M^-1 (eta + L^T (sqrt(w) eta')) (CG) around the current mean, then one
+    Newton-CG step of the mean. Random numbers come from numpy's PCG64 with `seed` and
+    are uploaded; every arithmetic step runs in the library. Returns (mean, deltas);
+    the samples are mean + deltas and mean - deltas."""
+    import numpy as _np
+    import torch
+    n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
+    rng = _np.random.default_rng(seed)
+    b = icr_weighted_adjoint(plan, w, d.reshape(1, n_out), half=False, stream=stream)
+    mean = torch.zeros((1, n_xi), dtype=plan.dtype, device="cuda") if mean is None else mean.reshape(1, n_xi)
+    deltas = None
+    for _ in range(n_iterations):
+        eta = torch.from_numpy(rng.standard_normal((n_pairs, n_xi))).to("cuda").to(plan.dtype)
+        eta_d = torch.from_numpy(rng.standard_normal((n_pairs, n_out))).to("cuda").to(plan.dtype)
+        deltas = mgvi_step(plan, w, b, mean, eta, eta_d, sample_iterations, newton_iterations, stream=stream)
+    return mean[0], deltas
+
+
+def mgvi_step(plan: Plan, w, b, mean, eta, eta_d, sample_iterations: int, newton_iterations: int,
+              workspaces=None, stream=None):
+    """The device work of one MGVI iteration for given standard-normal draws eta
+    (pairs, n_xi) and eta_d (pairs, n_out): the sample displacements (returned) and the
+    Newton-CG step of `mean` (updated in place); b = L^T W d. workspaces: optional
+    (weighted-adjoint, CG, Newton) workspaces to reuse."""
+    ws_a, ws_cg, ws_n = workspaces if workspaces is not None else (None, None, None)
+    r = icr_weighted_adjoint(plan, w, eta_d, add=eta, half=True, workspace=ws_a, stream=stream)
+    deltas = icr_cg_metric(plan, w, r, sample_iterations, workspace=ws_cg, stream=stream)
+    icr_mgvi_newton_step(plan, w, b, mean, newton_iterations, workspace=ws_n, stream=stream)
+    return deltas
 
 
 def icr_plan_destroy(plan: Plan):

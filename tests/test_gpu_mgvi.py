@@ -1,0 +1,124 @@
+"""MGVI on the device: the weighted adjoint (sample right-hand side and data term),
+the Newton-CG step of the expansion point and the antithetic driver, against the
+oracle (same inputs, identical matrices where iterates are compared) and against
+dense linear algebra on a tiny grid."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import icr_oracle as O
+from tests import icr_cases as C
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    C.from_workload("icr2d_chart_24to1284", depth=2, batch=2, precision="f64", name="2d_chart_f64"),
+    C.from_workload("icr2d_chart_24to1284", depth=2, batch=2, name="2d_chart_f32"),
+    C.from_workload("icr3d_m52_10to388", depth=3, batch=2, name="3d_m52_10to52_f32"),
+]
+
+
+def _weights(info, seed, batch=None):
+    n = info["n_out"]
+    if batch is None:
+        return (W.bernoulli_mask(n, 0.7, seed=seed) / 0.1 ** 2)
+    return np.stack([W.bernoulli_mask(n, 0.7, seed=seed + k) / 0.1 ** 2 for k in range(batch)])
+
+
+@pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
+@pytest.mark.parametrize("half", [True, False], ids=["sqrt_w", "w"])
+def test_weighted_adjoint_matches_the_oracle(c, half):
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan = C.gpu_plan(c)
+    info = plan.info
+    nb = c["batch"]
+    model = C.oracle_model(c)
+    y = W.standard_normal(info["n_out"], seed=60, batch=nb)
+    add = W.standard_normal(info["n_xi"], seed=61, batch=nb) if half else None
+    w = _weights(info, 62, batch=nb)   # one weight vector per sample
+    w_d = torch.from_numpy(w).cuda().to(plan.acc_dtype)
+    out = B.icr_weighted_adjoint(plan, w_d, C.to_device(y, plan),
+                                 add=None if add is None else C.to_device(add, plan), half=half)
+    torch.cuda.synchronize()
+    ys = C.stored_values(y, c["precision"])
+    ws = w.astype(np.float64) if c["precision"] == "f64" else w.astype(np.float32).astype(np.float64)
+    adds = None if add is None else C.stored_values(add, c["precision"])
+    ref = np.stack([O.weighted_adjoint(model, ws[k], 0.5 if half else 1.0, ys[k], None if adds is None else adds[k])
+                    for k in range(nb)])
+    rms, mx = C.rel_errors(C.to_numpy(out), ref)
+    print(f"[errors] {c['name']} weighted adjoint (p = {0.5 if half else 1}): rel-RMS {rms:.2e} rel-max {mx:.2e}")
+    tol_rms, tol_max = C.TOL[c["precision"]]
+    assert rms <= tol_rms and mx <= tol_max
+
+
+def test_newton_step_iterates_match_the_oracle_on_identical_matrices():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = CASES[0]
+    plan = C.gpu_plan(c)
+    model = C.oracle_model(c)
+    C.upload_oracle_matrices(plan, model)
+    info = plan.info
+    w = _weights(info, 63)
+    w_d = torch.from_numpy(w).cuda()
+    b = W.standard_normal(info["n_xi"], seed=64)
+    mean0 = W.standard_normal(info["n_xi"], seed=65)
+    for k in (1, 3, 5):
+        mean = torch.from_numpy(mean0.copy()).cuda()[None]
+        B.icr_mgvi_newton_step(plan, w_d, torch.from_numpy(b).cuda()[None], mean, k)
+        ref = O.mgvi_newton_step(model, w, b, mean0, k)
+        np.testing.assert_allclose(mean[0].cpu().numpy(), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+
+
+def test_driver_reaches_the_posterior_on_a_tiny_grid():
+    """One MGVI iteration (antithetic samples + one Newton-CG step) lands on the dense
+    posterior mean M^-1 L^T W d, and every drawn delta solves M delta = r."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = C.case(2, (6, 5), 1, (1 / 6, 1 / 5), "matern32", 0.3, precision="f64", name="tiny")
+    plan = C.gpu_plan(c)
+    model = C.oracle_model(c)
+    info = plan.info
+    lmat = model.dense()
+    w = _weights(info, 66)
+    d = W.standard_normal(info["n_out"], seed=67)
+    mmat = lmat.T @ (w[:, None] * lmat) + np.eye(info["n_xi"])
+    w_d = torch.from_numpy(w).cuda()
+    mean, deltas = B.mgvi(plan, w_d, torch.from_numpy(d).cuda(), n_pairs=3, n_iterations=1,
+                          sample_iterations=200, newton_iterations=200, seed=5)
+    np.testing.assert_allclose(mean.cpu().numpy(), np.linalg.solve(mmat, lmat.T @ (w * d)), rtol=1e-7, atol=1e-9)
+    # the deltas: M delta = eta + L^T (sqrt(w) eta') with the driver's own draws
+    rng = np.random.default_rng(5)
+    eta = rng.standard_normal((3, info["n_xi"]))
+    eta_d = rng.standard_normal((3, info["n_out"]))
+    r = eta + (np.sqrt(w) * eta_d) @ lmat
+    np.testing.assert_allclose(deltas.cpu().numpy() @ mmat.T, r, rtol=1e-7, atol=1e-8)
+
+
+def test_newton_step_fp32_converges_and_refuses_bf16():
+    """FP32 on a well-conditioned metric (noise sigma 1: at sigma 0.1 FP32 CG stagnates,
+    as plain FP32 CG on this metric does)."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = CASES[1]
+    plan = C.gpu_plan(c)
+    model = C.oracle_model(c)
+    info = plan.info
+    w = _weights(info, 68) * 0.1 ** 2
+    b = W.standard_normal(info["n_xi"], seed=69)
+    w_d = torch.from_numpy(w).cuda().float()
+    mean = torch.zeros((1, info["n_xi"]), device="cuda")
+    _, norms = B.icr_mgvi_newton_step(plan, w_d, torch.from_numpy(b).cuda().float()[None], mean, 60,
+                                      residual_norms=True)
+    ref = O.mgvi_newton_step(model, w, b, np.zeros(info["n_xi"]), 400)
+    rms, _ = C.rel_errors(mean[0].cpu().numpy(), ref)
+    nr = norms[0].cpu().numpy()
+    print(f"[errors] 2d_chart_f32 Newton step after 60 CG steps: rel-RMS {rms:.2e}, |r|/|r0| {nr[-1] / nr[0]:.2e}")
+    assert rms < 1e-4
+    bf = C.gpu_plan(dict(c, precision="bf16"))
+    with pytest.raises(B.ICRError) as exc:
+        B.icr_mgvi_newton_step(bf, w_d, torch.zeros((1, info["n_xi"]), device="cuda").bfloat16(),
+                               torch.zeros((1, info["n_xi"]), device="cuda").bfloat16(), 3)
+    assert exc.value.status == 5
