@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests in the served-mode stream (0: skip the served measurement)")
     ap.add_argument("--serve-priors", type=int, default=24)
+    ap.add_argument("--cf-reps", type=int, default=11,
+                    help="repetitions per size of the correlated-field M_p benchmark (0: skip it)")
     ap.add_argument("--hypergrad-steps", type=int, default=20,
                     help="timed hyperparameter-gradient evaluations (0: skip that measurement)")
     ap.add_argument("--cg-iters", type=int, default=None,
@@ -320,6 +322,37 @@ def mgvi_bench(B, plan, wl: dict, pairs: int, quiet: bool) -> dict:
     return out
 
 
+def correlated_field_bench(sizes, reps: int, quiet: bool) -> list:
+    """The paper's benchmark operator on the correlated-field model: building M_p at a
+    random position (the Poisson rate) and applying it to random input, per 2-D size
+    (median of `reps` timed repetitions with HIP events)."""
+    import torch
+    from paper_2402_16683_amd.cf import CorrelatedField
+    rows = []
+    for n in sizes:
+        cf = CorrelatedField(n)
+        p = torch.from_numpy(0.5 * W.standard_normal_f32(n * n, seed=71)).cuda().reshape(n, n)
+        v = torch.from_numpy(W.standard_normal_f32(n * n, seed=72)).cuda().reshape(n, n)
+        lam = torch.empty_like(p)
+        out = torch.empty_like(p)
+        cf.rate(p, lam)
+        cf.metric_apply(lam, v, out)
+        torch.cuda.synchronize()
+        times = {"build": [], "apply": []}
+        for _ in range(reps):
+            for key, fn in (("build", lambda: cf.rate(p, lam)), ("apply", lambda: cf.metric_apply(lam, v, out))):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                times[key].append(e0.elapsed_time(e1))
+        b_ms, a_ms = statistics.median(times["build"]), statistics.median(times["apply"])
+        rows.append({"n": n, "pixels": n * n, "ms_build": b_ms, "ms_apply": a_ms, "ms_build_and_apply": b_ms + a_ms})
+        log(f"correlated field {n}^2: build M_p {b_ms * 1e3:.1f} us, apply {a_ms * 1e3:.1f} us", quiet)
+    return rows
+
+
 def hyper_grad_bench(B, wl: dict, prec: str, steps: int, quiet: bool) -> dict:
     """Hyperparameter gradients on the workload: a plan built with the length
     derivatives, then per step icr_forward + icr_adjoint + icr_hyper_grad (the full
@@ -556,6 +589,9 @@ def main():
     if cg_iters > 0 and not args.copy_probe and prec != "bf16":
         out["cg"] = cg_solve(B, plan, wl, cg_iters, args.quiet)
         out["mgvi"] = mgvi_bench(B, plan, wl, 3, args.quiet)
+    if args.cf_reps > 0 and not args.copy_probe:
+        out["correlated_field_metric"] = correlated_field_bench([64, 128, 256, 512, 1024, 2048, 4096], args.cf_reps,
+                                                                args.quiet)
     if args.hypergrad_steps > 0 and not args.copy_probe:
         out["hyper_grad"] = hyper_grad_bench(B, wl, prec, args.hypergrad_steps, args.quiet)
     if args.serve_requests > 0 and not args.copy_probe:

@@ -1,0 +1,252 @@
+// Correlated-field model on an n x n periodic grid and the Fisher metric of a Poisson
+// likelihood (NIFTy.re, section "Gaussian Processes": s = FT(sqrt(P) xi); section
+// "Performance of NIFTy.re compared to NIFTy": M_p = J^T N^-1 J + 1).
+//
+// The field is real, so FT is the 2-D Hartley transform, normalised to be its own
+// inverse: T x = (Re - Im)(FFT2 x) / n. With lambda = exp(m + T(A xi)) the Jacobian is
+// J = diag(lambda) T diag(A) and N^-1 = diag(1 / lambda), so
+//   M_p v = v + A T(lambda(p) T(A v)).
+// A transform is four passes over the grid, each a hand-written kernel:
+//   1. row FFTs of the (pre-multiplied) real input, radix-2 in LDS, one workgroup a row;
+//   2. a tiled transpose;
+//   3. row FFTs again (the column transforms of pass 1's result);
+//   4. a tiled transpose back that forms (Re - Im) / n and applies the post-operation
+//      (x lambda, exp(m + .), or v + A .), so the elementwise work rides on the passes.
+// FP32 throughout; twiddles from sincospif on the reduced angle.
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "icr_cf.h"
+#include "icr_internal.h"
+
+struct icr_cf_plan {
+  int n = 0;
+  int logn = 0;
+  double mean = 0.0;
+  float* amp = nullptr;  // device [n][n] amplitude spectrum
+};
+
+namespace icr {
+namespace {
+
+constexpr int kTile = 32;
+
+template <bool kRealIn>
+__global__ void __launch_bounds__(512) cf_row_fft(const float* __restrict__ xr, const float* __restrict__ pre,
+                                                  const float2* __restrict__ xc, float2* __restrict__ out, int n,
+                                                  int logn) {
+  extern __shared__ float2 buf[];
+  const int64_t row = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = static_cast<int>(__brev(static_cast<unsigned>(i)) >> (32 - logn));  // bit-reversed slot
+    float2 v;
+    if (kRealIn) {
+      float a = xr[row * n + i];
+      if (pre) a *= pre[row * n + i];
+      v = make_float2(a, 0.0f);
+    } else {
+      v = xc[row * n + i];
+    }
+    buf[r] = v;
+  }
+  __syncthreads();
+  for (int s = 0; s < logn; ++s) {  // decimation in time: butterflies of span 2^(s+1)
+    const int half = 1 << s;
+    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
+      const int pos = j & (half - 1);
+      const int i0 = ((j >> s) << (s + 1)) + pos;
+      const int i1 = i0 + half;
+      float sn, cs;
+      sincospif(-static_cast<float>(pos) / static_cast<float>(half), &sn, &cs);  // exp(-2 pi i pos / 2^(s+1))
+      const float2 a = buf[i0], b = buf[i1];
+      const float tr = b.x * cs - b.y * sn, ti = b.x * sn + b.y * cs;
+      buf[i0] = make_float2(a.x + tr, a.y + ti);
+      buf[i1] = make_float2(a.x - tr, a.y - ti);
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[row * n + i] = buf[i];
+}
+
+__global__ void __launch_bounds__(kTile * 8) cf_transpose(const float2* __restrict__ in, float2* __restrict__ out,
+                                                          int n) {
+  __shared__ float2 tile[kTile][kTile + 1];
+  const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int k = 0; k < kTile; k += 8) tile[ty + k][tx] = in[int64_t(by + ty + k) * n + bx + tx];
+  __syncthreads();
+  for (int k = 0; k < kTile; k += 8) out[int64_t(bx + ty + k) * n + by + tx] = tile[tx][ty + k];
+}
+
+enum Post { kPostNone = 0, kPostMul = 1, kPostExp = 2, kPostMetric = 3 };
+
+// y = post((Re - Im)(Yt^T) / n) with Yt the transposed 2-D FFT.
+template <int kPost>
+__global__ void __launch_bounds__(kTile * 8) cf_finish(const float2* __restrict__ yt, float* __restrict__ out,
+                                                       const float* __restrict__ v1, const float* __restrict__ v2,
+                                                       float mean, float inv_n, int n) {
+  __shared__ float tile[kTile][kTile + 1];
+  const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int k = 0; k < kTile; k += 8) {
+    const float2 c = yt[int64_t(by + ty + k) * n + bx + tx];
+    tile[ty + k][tx] = (c.x - c.y) * inv_n;
+  }
+  __syncthreads();
+  for (int k = 0; k < kTile; k += 8) {
+    const int64_t idx = int64_t(bx + ty + k) * n + by + tx;
+    const float t = tile[tx][ty + k];
+    float r;
+    if (kPost == kPostMul) r = t * v1[idx];
+    else if (kPost == kPostExp) r = expf(mean + t);
+    else if (kPost == kPostMetric) r = v1[idx] + v2[idx] * t;
+    else r = t;
+    out[idx] = r;
+  }
+}
+
+__global__ void cf_amplitude_kernel(float* __restrict__ amp, int n, double a, double a0, double length, double slope) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * n) return;
+  const int i = static_cast<int>(t / n), j = static_cast<int>(t % n);
+  const double ki = i < n - i ? i : n - i, kj = j < n - j ? j : n - j;
+  const double k2 = (ki * ki + kj * kj) * length * length;
+  amp[t] = t == 0 ? static_cast<float>(a0) : static_cast<float>(a * pow(1.0 + k2, -slope / 4.0));
+}
+
+// out = post(T(pre * x)); work: two complex n x n buffers.
+hipError_t transform(const icr_cf_plan* p, const float* x, const float* pre, float* out, int post, const float* v1,
+                     const float* v2, float2* work, hipStream_t st) {
+  const int n = p->n;
+  float2* c1 = work;
+  float2* c2 = work + int64_t(n) * n;
+  const unsigned rows = static_cast<unsigned>(n);
+  const unsigned threads = static_cast<unsigned>(n / 2 < 512 ? n / 2 : 512);
+  const size_t lds = sizeof(float2) * n;
+  cf_row_fft<true><<<rows, threads, lds, st>>>(x, pre, nullptr, c1, n, p->logn);
+  const dim3 tgrid(n / kTile, n / kTile), tblock(kTile, 8);
+  cf_transpose<<<tgrid, tblock, 0, st>>>(c1, c2, n);
+  cf_row_fft<false><<<rows, threads, lds, st>>>(nullptr, nullptr, c2, c1, n, p->logn);
+  const float inv_n = 1.0f / static_cast<float>(n);
+  const float mean = static_cast<float>(p->mean);
+  switch (post) {
+    case kPostMul: cf_finish<kPostMul><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
+    case kPostExp: cf_finish<kPostExp><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
+    case kPostMetric: cf_finish<kPostMetric><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
+    default: cf_finish<kPostNone><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
+  }
+  return hipGetLastError();
+}
+
+icr_status cf_fail(icr_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+bool cf_aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % 4) == 0; }
+
+}  // namespace
+}  // namespace icr
+
+extern "C" {
+
+icr_status icr_cf_create(int32_t n, double amplitude, double zero_mode, double length, double slope,
+                         double offset_mean, void* hip_stream, icr_cf_plan** out_plan) {
+  icr::clear_error();
+  if (!out_plan) return icr::cf_fail(ICR_ERR_INVALID_ARG, "out_plan is NULL");
+  *out_plan = nullptr;
+  if (n < 32 || n > 4096 || (n & (n - 1)) != 0)
+    return icr::cf_fail(ICR_ERR_INVALID_ARG, "n must be a power of two in [32, 4096]");
+  if (!(amplitude > 0.0) || !(zero_mode >= 0.0) || !(length >= 0.0) || !std::isfinite(slope) ||
+      !std::isfinite(offset_mean) || !std::isfinite(amplitude) || !std::isfinite(zero_mode) || !std::isfinite(length))
+    return icr::cf_fail(ICR_ERR_INVALID_ARG, "amplitude > 0, zero_mode >= 0, length >= 0, finite slope and mean");
+  icr_cf_plan* p = new (std::nothrow) icr_cf_plan;
+  if (!p) return icr::cf_fail(ICR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->n = n;
+  while ((1 << p->logn) < n) ++p->logn;
+  p->mean = offset_mean;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipMalloc(&p->amp, sizeof(float) * size_t(n) * n);
+  if (e == hipSuccess) {
+    const int64_t total = int64_t(n) * n;
+    icr::cf_amplitude_kernel<<<static_cast<unsigned>((total + 255) / 256), 256, 0, st>>>(p->amp, n, amplitude,
+                                                                                        zero_mode, length, slope);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  if (e != hipSuccess) {
+    if (p->amp) (void)hipFree(p->amp);
+    delete p;
+    return icr::cf_fail(e == hipErrorOutOfMemory ? ICR_ERR_OUT_OF_MEMORY : ICR_ERR_HIP,
+                        std::string("correlated-field plan: ") + hipGetErrorString(e));
+  }
+  *out_plan = p;
+  return ICR_OK;
+}
+
+icr_status icr_cf_workspace_bytes(const icr_cf_plan* p, int64_t* bytes) {
+  icr::clear_error();
+  if (!p || !bytes) return icr::cf_fail(ICR_ERR_INVALID_ARG, "plan or bytes is NULL");
+  *bytes = int64_t(p->n) * p->n * (2 * int64_t(sizeof(float2)) + int64_t(sizeof(float)));
+  return ICR_OK;
+}
+
+icr_status icr_cf_copy_amplitude(const icr_cf_plan* p, float* amp) {
+  icr::clear_error();
+  if (!p || !amp) return icr::cf_fail(ICR_ERR_INVALID_ARG, "plan or amp is NULL");
+  const hipError_t e = hipMemcpy(amp, p->amp, sizeof(float) * size_t(p->n) * p->n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  return ICR_OK;
+}
+
+icr_status icr_cf_transform(const icr_cf_plan* p, const float* x, float* y, void* workspace, void* hip_stream) {
+  icr::clear_error();
+  if (!p || !x || !y || !workspace) return icr::cf_fail(ICR_ERR_INVALID_ARG, "NULL argument");
+  if (!icr::cf_aligned(x) || !icr::cf_aligned(y) || (reinterpret_cast<uintptr_t>(workspace) % 8) != 0)
+    return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
+  const hipError_t e = icr::transform(p, x, nullptr, y, icr::kPostNone, nullptr, nullptr,
+                                      static_cast<float2*>(workspace), static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("transform: ") + hipGetErrorString(e));
+  return ICR_OK;
+}
+
+icr_status icr_cf_rate(const icr_cf_plan* p, const float* position, float* lambda, void* workspace,
+                       void* hip_stream) {
+  icr::clear_error();
+  if (!p || !position || !lambda || !workspace) return icr::cf_fail(ICR_ERR_INVALID_ARG, "NULL argument");
+  if (!icr::cf_aligned(position) || !icr::cf_aligned(lambda) || (reinterpret_cast<uintptr_t>(workspace) % 8) != 0)
+    return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
+  const hipError_t e = icr::transform(p, position, p->amp, lambda, icr::kPostExp, nullptr, nullptr,
+                                      static_cast<float2*>(workspace), static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("rate: ") + hipGetErrorString(e));
+  return ICR_OK;
+}
+
+icr_status icr_cf_metric_apply(const icr_cf_plan* p, const float* lambda, const float* v, float* out,
+                               void* workspace, void* hip_stream) {
+  icr::clear_error();
+  if (!p || !lambda || !v || !out || !workspace) return icr::cf_fail(ICR_ERR_INVALID_ARG, "NULL argument");
+  if (!icr::cf_aligned(lambda) || !icr::cf_aligned(v) || !icr::cf_aligned(out) ||
+      (reinterpret_cast<uintptr_t>(workspace) % 8) != 0)
+    return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
+  if (v == out) return icr::cf_fail(ICR_ERR_INVALID_ARG, "v and out must differ");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  float2* work = static_cast<float2*>(workspace);
+  float* u = reinterpret_cast<float*>(work + 2 * int64_t(p->n) * p->n);
+  // u = lambda * T(A v); out = v + A * T(u)
+  hipError_t e = icr::transform(p, v, p->amp, u, icr::kPostMul, lambda, nullptr, work, st);
+  if (e == hipSuccess) e = icr::transform(p, u, nullptr, out, icr::kPostMetric, v, p->amp, work, st);
+  if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("metric: ") + hipGetErrorString(e));
+  return ICR_OK;
+}
+
+icr_status icr_cf_destroy(icr_cf_plan* p) {
+  icr::clear_error();
+  if (!p) return ICR_OK;
+  if (p->amp) (void)hipFree(p->amp);
+  delete p;
+  return ICR_OK;
+}
+
+}  // extern "C"
