@@ -7,7 +7,8 @@
 // J = diag(lambda) T diag(A) and N^-1 = diag(1 / lambda), so
 //   M_p v = v + A T(lambda(p) T(A v)).
 // A transform is four passes over the grid, each a hand-written kernel:
-//   1. row FFTs of the (pre-multiplied) real input, radix-2 in LDS, one workgroup a row;
+//   1. row FFTs of the (pre-multiplied) real input, Stockham radix 4 in LDS, one
+//      workgroup a row;
 //   2. a tiled transpose;
 //   3. row FFTs again (the column transforms of pass 1's result);
 //   4. a tiled transpose back that forms (Re - Im) / n and applies the post-operation
@@ -32,14 +33,26 @@ namespace {
 
 constexpr int kTile = 32;
 
+constexpr int kFftThreads = 512;
+constexpr int kFftIt = 2;  // radix-4 butterflies per thread and stage: n / 4 <= kFftIt * kFftThreads
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One row per workgroup, in LDS, Stockham autosort (natural order in and out): radix-4
+// stages, then one radix-2 stage when log2(n) is odd. A stage of span ns reads the r-th
+// quarter at j + r n/4, twiddles it by exp(-2 pi i r (j mod ns) / (4 ns)), takes the
+// 4-point DFT and writes it to (j / ns) 4 ns + (j mod ns) + r ns; all reads of a stage
+// finish (barrier) before its writes.
 template <bool kRealIn>
-__global__ void __launch_bounds__(512) cf_row_fft(const float* __restrict__ xr, const float* __restrict__ pre,
-                                                  const float2* __restrict__ xc, float2* __restrict__ out, int n,
-                                                  int logn) {
+__global__ void __launch_bounds__(kFftThreads) cf_row_fft(const float* __restrict__ xr, const float* __restrict__ pre,
+                                                          const float2* __restrict__ xc, float2* __restrict__ out,
+                                                          int n, int logn) {
   extern __shared__ float2 buf[];
   const int64_t row = blockIdx.x;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = static_cast<int>(__brev(static_cast<unsigned>(i)) >> (32 - logn));  // bit-reversed slot
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < n; i += nt) {
     float2 v;
     if (kRealIn) {
       float a = xr[row * n + i];
@@ -48,25 +61,70 @@ __global__ void __launch_bounds__(512) cf_row_fft(const float* __restrict__ xr, 
     } else {
       v = xc[row * n + i];
     }
-    buf[r] = v;
+    buf[i] = v;
   }
   __syncthreads();
-  for (int s = 0; s < logn; ++s) {  // decimation in time: butterflies of span 2^(s+1)
-    const int half = 1 << s;
-    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
-      const int pos = j & (half - 1);
-      const int i0 = ((j >> s) << (s + 1)) + pos;
-      const int i1 = i0 + half;
-      float sn, cs;
-      sincospif(-static_cast<float>(pos) / static_cast<float>(half), &sn, &cs);  // exp(-2 pi i pos / 2^(s+1))
-      const float2 a = buf[i0], b = buf[i1];
-      const float tr = b.x * cs - b.y * sn, ti = b.x * sn + b.y * cs;
-      buf[i0] = make_float2(a.x + tr, a.y + ti);
-      buf[i1] = make_float2(a.x - tr, a.y - ti);
+  const int q4 = n >> 2;
+  int ns = 1, lns = 0;
+  for (; lns + 2 <= logn; ns <<= 2, lns += 2) {  // while 4 ns <= n
+    float2 v[kFftIt][4];
+#pragma unroll
+    for (int it = 0; it < kFftIt; ++it) {
+      const int j = tid + it * nt;
+      if (j < q4) {
+        const int k = j & (ns - 1);
+        float sn, cs;
+        sincospif(-2.0f * static_cast<float>(k) / static_cast<float>(4 * ns), &sn, &cs);
+        const float2 w1 = make_float2(cs, sn), w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+        const float2 a = buf[j], b = cmul(buf[j + q4], w1), c = cmul(buf[j + 2 * q4], w2),
+                     d = cmul(buf[j + 3 * q4], w3);
+        const float2 t0 = make_float2(a.x + c.x, a.y + c.y), t1 = make_float2(a.x - c.x, a.y - c.y);
+        const float2 t2 = make_float2(b.x + d.x, b.y + d.y), t3 = make_float2(b.x - d.x, b.y - d.y);
+        v[it][0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+        v[it][1] = make_float2(t1.x + t3.y, t1.y - t3.x);  // t1 - i t3
+        v[it][2] = make_float2(t0.x - t2.x, t0.y - t2.y);
+        v[it][3] = make_float2(t1.x - t3.y, t1.y + t3.x);  // t1 + i t3
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kFftIt; ++it) {
+      const int j = tid + it * nt;
+      if (j < q4) {
+        const int base = ((j >> lns) << (lns + 2)) + (j & (ns - 1));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[base + r * ns] = v[it][r];
+      }
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) out[row * n + i] = buf[i];
+  if (ns < n) {  // the last stage is radix 2 (ns = n / 2)
+    const int q2 = n >> 1;
+    float2 v[2 * kFftIt][2];
+#pragma unroll
+    for (int it = 0; it < 2 * kFftIt; ++it) {
+      const int j = tid + it * nt;
+      if (j < q2) {
+        float sn, cs;
+        sincospif(-static_cast<float>(j & (ns - 1)) / static_cast<float>(ns), &sn, &cs);
+        const float2 a = buf[j], b = cmul(buf[j + q2], make_float2(cs, sn));
+        v[it][0] = make_float2(a.x + b.x, a.y + b.y);
+        v[it][1] = make_float2(a.x - b.x, a.y - b.y);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 2 * kFftIt; ++it) {
+      const int j = tid + it * nt;
+      if (j < q2) {
+        const int base = ((j >> lns) << (lns + 1)) + (j & (ns - 1));
+        buf[base] = v[it][0];
+        buf[base + ns] = v[it][1];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) out[row * n + i] = buf[i];
 }
 
 __global__ void __launch_bounds__(kTile * 8) cf_transpose(const float2* __restrict__ in, float2* __restrict__ out,
@@ -122,7 +180,8 @@ hipError_t transform(const icr_cf_plan* p, const float* x, const float* pre, flo
   float2* c1 = work;
   float2* c2 = work + int64_t(n) * n;
   const unsigned rows = static_cast<unsigned>(n);
-  const unsigned threads = static_cast<unsigned>(n / 2 < 512 ? n / 2 : 512);
+  // n / 4 radix-4 butterflies per stage over at most kFftIt per thread (n <= 4096)
+  const unsigned threads = static_cast<unsigned>(n / 4 < kFftThreads ? (n / 4 < 64 ? 64 : n / 4) : kFftThreads);
   const size_t lds = sizeof(float2) * n;
   cf_row_fft<true><<<rows, threads, lds, st>>>(x, pre, nullptr, c1, n, p->logn);
   const dim3 tgrid(n / kTile, n / kTile), tblock(kTile, 8);
