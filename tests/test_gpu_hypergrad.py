@@ -30,6 +30,11 @@ CASES = [
     C.from_workload("icr3d_m52_10to388", depth=2, precision="f64", name="3d_m52_10to28_f64"),
     C.from_workload("icr2d_chart_24to1284", depth=2, name="2d_chart_24to84_f32"),
     C.from_workload("icr3d_chart_10to388", depth=2, name="3d_chart_10to28_f32"),
+    # batches through the fast 3-D contraction (partial sums per sample), BF16 on shells
+    C.from_workload("icr3d_m52_10to388", depth=3, batch=3, name="3d_m52_10to52_b3_f32"),
+    C.from_workload("icr3d_chart_10to388", depth=3, batch=2, precision="bf16", name="3d_chart_10to52_b2_bf16"),
+    C.case(3, (6, 7, 5), 2, (1 / 6, 1 / 7, 1 / 5), "matern52", 0.2, chart="logradial_cyl3d",
+           chart_params=(0.2, 1.5, 1.2, 0.7), batch=2, name="3d_chart_ragged_f32"),
     C.from_workload("icr3d_m52_10to388", name="3d_m52_full_f32"),
 ]
 
