@@ -524,36 +524,36 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
       }
     } else {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      float A[8], Bv[8], Ys[8];
+      for (int p = 0; p < 2; ++p) {
+        float A[8], Bv[8], Ys[8];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {  // z: (bz, by, bx) -> (sz, by, bx)
-        A[h] = yv[p][h] + yv[p][4 + h];
-        A[4 + h] = yv[p][4 + h] - yv[p][h];
-      }
-#pragma unroll
-      for (int sz = 0; sz < 2; ++sz)  // y
-#pragma unroll
-        for (int bx = 0; bx < 2; ++bx) {
-          Bv[sz * 4 + bx] = A[sz * 4 + bx] + A[sz * 4 + 2 + bx];
-          Bv[sz * 4 + 2 + bx] = A[sz * 4 + 2 + bx] - A[sz * 4 + bx];
+        for (int h = 0; h < 4; ++h) {  // z: (bz, by, bx) -> (sz, by, bx)
+          A[h] = yv[p][h] + yv[p][4 + h];
+          A[4 + h] = yv[p][4 + h] - yv[p][h];
         }
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {  // x
-        Ys[2 * h] = Bv[2 * h] + Bv[2 * h + 1];
-        Ys[2 * h + 1] = Bv[2 * h + 1] - Bv[2 * h];
-      }
+        for (int sz = 0; sz < 2; ++sz)  // y
 #pragma unroll
-      for (int jj = 0; jj < 9; ++jj) {
-        const int sy = jj / 3 == 2, sx = jj % 3 == 2;
-        const float ue = m.k.c[jj] * Ys[(sy << 1) | sx];
-        const float um = m.k.c[9 + jj] * Ys[(sy << 1) | sx];
-        const float uo = m.k.c[18 + jj] * Ys[4 | (sy << 1) | sx];
-        G[p][jj] = A0[p][jj] + (ue - uo);   // window slot z-1 of this block: coarse zb-1
-        A0[p][jj] = A1[p][jj] + um;          // slot 0: coarse zb
-        A1[p][jj] = ue + uo;                 // slot z+1: coarse zb+1
+          for (int bx = 0; bx < 2; ++bx) {
+            Bv[sz * 4 + bx] = A[sz * 4 + bx] + A[sz * 4 + 2 + bx];
+            Bv[sz * 4 + 2 + bx] = A[sz * 4 + 2 + bx] - A[sz * 4 + bx];
+          }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {  // x
+          Ys[2 * h] = Bv[2 * h] + Bv[2 * h + 1];
+          Ys[2 * h + 1] = Bv[2 * h + 1] - Bv[2 * h];
+        }
+#pragma unroll
+        for (int jj = 0; jj < 9; ++jj) {
+          const int sy = jj / 3 == 2, sx = jj % 3 == 2;
+          const float ue = m.k.c[jj] * Ys[(sy << 1) | sx];
+          const float um = m.k.c[9 + jj] * Ys[(sy << 1) | sx];
+          const float uo = m.k.c[18 + jj] * Ys[4 | (sy << 1) | sx];
+          G[p][jj] = A0[p][jj] + (ue - uo);   // window slot z-1 of this block: coarse zb-1
+          A0[p][jj] = A1[p][jj] + um;          // slot 0: coarse zb
+          A1[p][jj] = ue + uo;                 // slot z+1: coarse zb+1
+        }
       }
-    }
     }
     if (zb >= z0 + 1) {  // coarse plane zb - 1 is complete in G (uniform branch)
       const int zc = zb - 1;
