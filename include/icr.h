@@ -68,8 +68,10 @@ typedef enum icr_kernel {
 typedef enum icr_chart {
   ICR_CHART_REGULAR = 0,      /* pixels on a regular grid: one R, sqrtD per level */
   ICR_CHART_LOGRADIAL_2D = 1, /* index point (u, v) sits at (r cos t, r sin t) with
-                                 r = p0 exp(p1 u), t = p2 v (chart_params p0..p2);
-                                 one R, sqrtD per interior coarse pixel */
+                                 r = p0 exp(p1 u), t = p2 v (chart_params p0..p2), ndim 2.
+                                 Distances depend on u1, u2 and v1 - v2 only, so the plan
+                                 keeps one R, sqrtD per interior coarse index along the
+                                 first axis (radial shell), built at pixel (u, 1) */
   ICR_CHART_LOGRADIAL_CYL_3D = 2
                               /* index point (u, v, w) sits at (r cos t, r sin t, p3 w)
                                  with r = p0 exp(p1 u), t = p2 v (chart_params p0..p3),
@@ -125,8 +127,7 @@ typedef struct icr_plan_info {
   int64_t metric_workspace_elems; /* workspace per sample for icr_metric_apply: n_xi */
   int64_t device_bytes;        /* device memory held by the plan */
   int64_t level_sets[ICR_MAX_DEPTH]; /* matrix sets of refinement l -> l+1: 1 on a regular
-                                        grid, prod(n_l - 2) under the 2-D chart, n_l,0 - 2
-                                        (radial shells) under the cylinder chart */
+                                        grid, n_l,0 - 2 (radial shells) under either chart */
   int64_t hypergrad_workspace_elems; /* doubles of workspace per sample for icr_hyper_grad
                                         (0 unless built with ICR_FLAG_HYPERGRAD) */
 } icr_plan_info;
@@ -154,8 +155,7 @@ icr_status icr_plan_get_info(const icr_plan* plan, icr_plan_info* info);
  *   level0:  l00 receives the lower Cholesky factor of K_00, N0 x N0 row-major
  *            with N0 = prod(shape0).
  *   level l: r receives R_l (2^d x 3^d row-major) and sqrtd sqrtD_l (2^d x 2^d);
- *            level_sets[l] pairs (icr_plan_info), set index outermost: under the
- *            2-D chart one per interior coarse pixel in C order, under the cylinder
+ *            level_sets[l] pairs (icr_plan_info), set index outermost: under either
  *            chart one per radial shell u = 1 .. n_l,0 - 2. Either pointer may be NULL.
  */
 icr_status icr_plan_copy_level0(const icr_plan* plan, double* l00);

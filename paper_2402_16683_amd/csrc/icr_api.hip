@@ -224,7 +224,7 @@ icr_status refresh_host_copies(icr_plan* p, int level) {
   m.shell_asym = 1.0;
   if (p->precision == ICR_F64) return ICR_OK;
   const auto ok = [](double asym) { return std::isfinite(asym) && asym <= icr::kSectorTolerance; };
-  if (p->shell) {
+  if (icr::shell_tables(p)) {
     icr_status r = shell_asymmetry(m.shell_chk, m.nsets, &m.shell_asym);
     if (r != ICR_OK) return r;
     m.shell_ok = ok(m.shell_asym);
@@ -291,7 +291,9 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   p->depth = cfg->depth;
   p->precision = cfg->precision;
   p->charted = cfg->chart != ICR_CHART_REGULAR;
-  p->shell = cfg->chart == ICR_CHART_LOGRADIAL_CYL_3D;
+  // both charts are invariant along their angular (and height) axes: one matrix set per
+  // interior coarse index along the first (radial) axis describes a level exactly
+  p->shell = cfg->chart == ICR_CHART_LOGRADIAL_CYL_3D || cfg->chart == ICR_CHART_LOGRADIAL_2D;
   p->hypergrad = (cfg->flags & ICR_FLAG_HYPERGRAD) ? 1 : 0;
   p->elem_bytes = elem_bytes_of(cfg->precision);
   const int d = p->ndim;
@@ -345,7 +347,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][2] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nw * ab);
     off_lev[l][3] = bytes; bytes = align_up(bytes + size_t(nsets) * nc * nc * ab);
     off_lev[l][4] = bytes; bytes = align_up(bytes + size_t(3) * nw * 8);
-    const int64_t shell_sets = p->shell ? nsets : 0;
+    const int64_t shell_sets = icr::shell_tables(p) ? nsets : 0;
     off_lev[l][5] = bytes; bytes = align_up(bytes + size_t(shell_sets) * icr::kShellStride * 4);
     off_lev[l][6] = bytes; bytes = align_up(bytes + size_t(shell_sets) * 2 * 8);
     const int64_t dsets = p->hypergrad ? nsets : 0;
@@ -354,7 +356,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][9] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * ab);
     off_lev[l][10] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * ab);
     off_lev[l][11] = bytes; bytes = align_up(bytes + (p->hypergrad && !p->charted ? size_t(3) * nw * 8 : 0));
-    const int64_t dshell = p->hypergrad && p->shell ? nsets : 0;
+    const int64_t dshell = p->hypergrad && icr::shell_tables(p) ? nsets : 0;
     off_lev[l][12] = bytes; bytes = align_up(bytes + size_t(dshell) * icr::kShellStride * 4);
     off_lev[l][13] = bytes; bytes = align_up(bytes + size_t(dshell) * 2 * 8);
   }
@@ -379,7 +381,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     p->lev[l].r_c = base + off_lev[l][2];
     p->lev[l].s_c = base + off_lev[l][3];
     p->lev[l].sector64 = reinterpret_cast<double*>(base + off_lev[l][4]);
-    if (p->shell) {
+    if (icr::shell_tables(p)) {
       p->lev[l].shell_tab = reinterpret_cast<float*>(base + off_lev[l][5]);
       p->lev[l].shell_chk = reinterpret_cast<double*>(base + off_lev[l][6]);
     }
@@ -389,7 +391,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
       p->lev[l].dr_c = base + off_lev[l][9];
       p->lev[l].ds_c = base + off_lev[l][10];
       if (!p->charted) p->lev[l].dsector64 = reinterpret_cast<double*>(base + off_lev[l][11]);
-      if (p->shell) {
+      if (icr::shell_tables(p)) {
         p->lev[l].dshell_tab = reinterpret_cast<float*>(base + off_lev[l][12]);
         p->lev[l].dshell_chk = reinterpret_cast<double*>(base + off_lev[l][13]);
       }
@@ -426,7 +428,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     BUILD_TRY(icr::launch_build_level(p, l, counts + 1 + l, status, st));
     BUILD_TRY(icr::launch_level_convert(p, l, st));
     if (!p->charted) BUILD_TRY(icr::launch_sector(p, l, st));
-    if (p->shell) BUILD_TRY(icr::launch_shell_sector(p, l, st));
+    if (icr::shell_tables(p)) BUILD_TRY(icr::launch_shell_sector(p, l, st));
   }
   int32_t host_status[kMaxLevels + 1];
   BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
@@ -528,7 +530,7 @@ icr_status icr_plan_set_refinement(icr_plan* p, int32_t level, const double* r, 
   ICR_HIP_TRY(hipMemcpyAsync(m.s64, sqrtd, size_t(m.nsets) * nc * nc * 8, hipMemcpyHostToDevice, st));
   ICR_HIP_TRY(icr::launch_level_convert(p, level, st));
   if (!p->charted) ICR_HIP_TRY(icr::launch_sector(p, level, st));
-  if (p->shell) ICR_HIP_TRY(icr::launch_shell_sector(p, level, st));
+  if (icr::shell_tables(p)) ICR_HIP_TRY(icr::launch_shell_sector(p, level, st));
   ICR_HIP_TRY(hipStreamSynchronize(st));
   return refresh_host_copies(p, level);
 }

@@ -117,6 +117,7 @@ struct icr_plan {
   int precision = 0;
   int charted = 0;   // matrices per pixel or per shell instead of one set per level
   int shell = 0;     // charted with one set per interior coarse index along the first axis
+                     // (both log-radial charts: their distances do not depend on the angle)
   int device = 0;
   int shapes[icr::kMaxLevels][3];  // level shapes, axes beyond ndim are 1 (stored leading)
   int64_t offsets[icr::kMaxLevels + 1];
@@ -134,6 +135,12 @@ struct icr_plan {
   void* pool = nullptr;      // the one device allocation the plan owns
   int64_t pool_bytes = 0;
 };
+
+namespace icr {
+// 3-D shell levels keep a per-plane table in the sector form of the two symmetric axes
+// for the fast kernels; 2-D shell levels run the generic kernels on the plain sets.
+inline bool shell_tables(const icr_plan* p) { return p->shell && p->ndim == 3; }
+}  // namespace icr
 
 namespace icr {
 

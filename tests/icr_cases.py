@@ -63,8 +63,13 @@ def chart_positions(c, pts: np.ndarray) -> np.ndarray:
 
 
 def is_shell(model) -> bool:
-    """Cylinder-chart models: the device keeps one matrix set per radial shell."""
-    return model.cfg.chart == "logradial_cyl3d"
+    """Charted models: the device keeps one matrix set per radial shell (first axis)."""
+    return model.cfg.chart in ("logradial2d", "logradial_cyl3d")
+
+
+def shell_sets(mat: np.ndarray, ndim: int) -> np.ndarray:
+    """The per-pixel stack's sets at pixel (u, 1, ...) of every shell: (n_u, ...)."""
+    return mat[(slice(None),) + (0,) * (ndim - 1)]
 
 
 def rel_errors(got: np.ndarray, ref: np.ndarray):
@@ -100,19 +105,20 @@ def stored_values(a: np.ndarray, precision: str) -> np.ndarray:
 def upload_oracle_matrices(plan, model):
     """Give the device plan the oracle's FP64 matrices (sweep-only comparisons).
 
-    For a cylinder-chart model the device holds one set per radial shell: it gets the
-    oracle's set at pixel (u, 1, 1) of each shell, and the model's per-pixel sets are
-    replaced by those shell sets broadcast along the other axes, so that both sides
-    apply identical matrices."""
+    For a charted model the device holds one set per radial shell: it gets the oracle's
+    set at pixel (u, 1, ...) of each shell, and the model's per-pixel sets are replaced by
+    those shell sets broadcast along the other axes, so that both sides apply identical
+    matrices."""
     from paper_2402_16683_amd import icr as B
     B.icr_plan_set_level0(plan, model.l00)
     d = model.cfg.ndim
     for l in range(model.cfg.depth):
         if is_shell(model):
-            r_sh = model.r_mats[l][:, 0, 0]
-            s_sh = model.sqrt_ds[l][:, 0, 0]
-            model.r_mats[l] = np.ascontiguousarray(np.broadcast_to(r_sh[:, None, None], model.r_mats[l].shape))
-            model.sqrt_ds[l] = np.ascontiguousarray(np.broadcast_to(s_sh[:, None, None], model.sqrt_ds[l].shape))
+            r_sh = shell_sets(model.r_mats[l], d)
+            s_sh = shell_sets(model.sqrt_ds[l], d)
+            grow = (slice(None),) + (None,) * (d - 1)
+            model.r_mats[l] = np.ascontiguousarray(np.broadcast_to(r_sh[grow], model.r_mats[l].shape))
+            model.sqrt_ds[l] = np.ascontiguousarray(np.broadcast_to(s_sh[grow], model.sqrt_ds[l].shape))
             r, s = r_sh, s_sh
         else:
             r = np.reshape(model.r_mats[l], (-1, 2 ** d, 3 ** d))

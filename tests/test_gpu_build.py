@@ -37,7 +37,7 @@ CASES = [
 def _window_geometry(c, model, level):
     """Physical window / child positions of every set the device keeps for a level
     (oracle geometry) and the oracle's matrices of the same sets. The cylinder chart
-    keeps one set per radial shell u, built at pixel (u, 1, 1)."""
+    keeps one set per radial shell u, built at pixel (u, 1, ...)."""
     d = c["ndim"]
     spac = O.level_spacings(c["delta0"], c["depth"])[level]
     org = O.level_origins(c["delta0"], c["depth"])[level]
@@ -49,7 +49,7 @@ def _window_geometry(c, model, level):
     if C.is_shell(model):
         idx = np.ones((n_int[0], d))
         idx[:, 0] = np.arange(1, n_int[0] + 1)
-        r_ora, s_ora = model.r_mats[level][:, 0, 0], model.sqrt_ds[level][:, 0, 0]
+        r_ora, s_ora = C.shell_sets(model.r_mats[level], d), C.shell_sets(model.sqrt_ds[level], d)
     else:
         idx = O.grid_indices(n_int) + 1
         r_ora, s_ora = model.r_mats[level], model.sqrt_ds[level]
