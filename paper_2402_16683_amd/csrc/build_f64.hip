@@ -500,6 +500,19 @@ __global__ void shell_sector_kernel(const double* __restrict__ r64, const double
   chk[2 * set + 1] = on;
 }
 
+// Shell-charted 2-D levels: the FP32 row table of the fast 2-D kernels, per set R (36,
+// [b][w]) then sqrtD lower by rows (10).
+__global__ void shell2_table_kernel(const double* __restrict__ r64, const double* __restrict__ s64,
+                                    int64_t nsets, float* __restrict__ tab) {
+  const int64_t set = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (set >= nsets) return;
+  float* out = tab + set * kShellStride;
+  for (int e = 0; e < 36; ++e) out[e] = static_cast<float>(r64[set * 36 + e]);
+  for (int c = 0; c < 4; ++c)
+    for (int cp = 0; cp <= c; ++cp) out[36 + c * (c + 1) / 2 + cp] = static_cast<float>(s64[set * 16 + c * 4 + cp]);
+  for (int e = 46; e < kShellStride; ++e) out[e] = 0.0f;
+}
+
 KernelSpec kernel_spec(const icr_plan* p) {
   return KernelSpec{p->cfg.kernel, p->cfg.scale * p->cfg.scale, p->cfg.length};
 }
@@ -636,6 +649,10 @@ hipError_t launch_shell_sector(const icr_plan* p, int level, hipStream_t st) {
   const LevelMats& m = p->lev[level];
   const unsigned threads = 64;
   const unsigned blocks = static_cast<unsigned>((m.nsets + threads - 1) / threads);
+  if (p->ndim == 2) {  // dense rows; no symmetry needed
+    shell2_table_kernel<<<blocks, threads, 0, st>>>(m.r64, m.s64, m.nsets, m.shell_tab);
+    return hipGetLastError();
+  }
   shell_sector_kernel<<<blocks, threads, 0, st>>>(m.r64, m.s64, m.nsets, m.shell_tab, m.shell_chk);
   if (m.dr64 && m.dshell_tab)
     shell_sector_kernel<<<blocks, threads, 0, st>>>(m.dr64, m.ds64, m.nsets, m.dshell_tab, m.dshell_chk);

@@ -224,6 +224,10 @@ icr_status refresh_host_copies(icr_plan* p, int level) {
   m.shell_asym = 1.0;
   if (p->precision == ICR_F64) return ICR_OK;
   const auto ok = [](double asym) { return std::isfinite(asym) && asym <= icr::kSectorTolerance; };
+  if (icr::shell_tables(p) && p->ndim == 2) {  // dense rows: always usable
+    m.shell_ok = true;
+    return ICR_OK;
+  }
   if (icr::shell_tables(p)) {
     icr_status r = shell_asymmetry(m.shell_chk, m.nsets, &m.shell_asym);
     if (r != ICR_OK) return r;
@@ -349,14 +353,14 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     off_lev[l][4] = bytes; bytes = align_up(bytes + size_t(3) * nw * 8);
     const int64_t shell_sets = icr::shell_tables(p) ? nsets : 0;
     off_lev[l][5] = bytes; bytes = align_up(bytes + size_t(shell_sets) * icr::kShellStride * 4);
-    off_lev[l][6] = bytes; bytes = align_up(bytes + size_t(shell_sets) * 2 * 8);
+    off_lev[l][6] = bytes; bytes = align_up(bytes + size_t(shell_sets) * 2 * 8);  // symmetry check (3-D)
     const int64_t dsets = p->hypergrad ? nsets : 0;
     off_lev[l][7] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * 8);
     off_lev[l][8] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * 8);
     off_lev[l][9] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nw * ab);
     off_lev[l][10] = bytes; bytes = align_up(bytes + size_t(dsets) * nc * nc * ab);
     off_lev[l][11] = bytes; bytes = align_up(bytes + (p->hypergrad && !p->charted ? size_t(3) * nw * 8 : 0));
-    const int64_t dshell = p->hypergrad && icr::shell_tables(p) ? nsets : 0;
+    const int64_t dshell = p->hypergrad && icr::shell_tables(p) && d == 3 ? nsets : 0;
     off_lev[l][12] = bytes; bytes = align_up(bytes + size_t(dshell) * icr::kShellStride * 4);
     off_lev[l][13] = bytes; bytes = align_up(bytes + size_t(dshell) * 2 * 8);
   }
@@ -391,7 +395,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
       p->lev[l].dr_c = base + off_lev[l][9];
       p->lev[l].ds_c = base + off_lev[l][10];
       if (!p->charted) p->lev[l].dsector64 = reinterpret_cast<double*>(base + off_lev[l][11]);
-      if (icr::shell_tables(p)) {
+      if (icr::shell_tables(p) && d == 3) {
         p->lev[l].dshell_tab = reinterpret_cast<float*>(base + off_lev[l][12]);
         p->lev[l].dshell_chk = reinterpret_cast<double*>(base + off_lev[l][13]);
       }

@@ -137,9 +137,9 @@ struct icr_plan {
 };
 
 namespace icr {
-// 3-D shell levels keep a per-plane table in the sector form of the two symmetric axes
-// for the fast kernels; 2-D shell levels run the generic kernels on the plain sets.
-inline bool shell_tables(const icr_plan* p) { return p->shell && p->ndim == 3; }
+// Shell levels keep an FP32 table with one row per set for the fast kernels: in 3-D the
+// sector form of the two symmetric axes, in 2-D the dense R and sqrtD.
+inline bool shell_tables(const icr_plan* p) { return p->shell && p->ndim >= 2; }
 }  // namespace icr
 
 namespace icr {

@@ -1,5 +1,6 @@
 // 2-D refinement level, forward and adjoint, with the dense 4 x 9 R and lower 4 x 4
-// sqrtD of a stationary level, FP32 arithmetic with FP32 or bfloat16 storage.
+// sqrtD of a stationary level, or of each coarse row of a shell-charted level (one set
+// per radial index, the marching axis), FP32 arithmetic with FP32 or bfloat16 storage.
 //
 // Forward: a lane owns two neighbouring interior coarse pixels along x (x = 2P+1, 2P+2)
 // and marches along y; the four coarse columns 2P .. 2P+3 of the rows y-1, y, y+1 slide
@@ -31,6 +32,27 @@ struct Mat2 {
   float s[10];  // lower sqrtD by rows: s[c (c + 1) / 2 + c']
 };
 
+// The matrices of a block row: a stationary level passes its set by value, a shell
+// level a table with one row per coarse row (R, then sqrtD lower by rows, see
+// shell2_table_kernel), read through the constant address space: every lane of a
+// wavefront marches through the same rows, so the compiler uses scalar loads.
+struct Stat2 {
+  Mat2 m;
+};
+struct Shell2 {
+  const float* tab;
+  int nsets;
+};
+typedef const float __attribute__((address_space(4))) const_float2d;
+template <typename M>
+__device__ __forceinline__ const const_float2d* row_of(const M& m, int set) {
+  return (const const_float2d*)(m.tab + static_cast<int64_t>(min(max(set, 0), m.nsets - 1)) * kShellStride);
+}
+template <typename M>
+constexpr bool kShell2 = false;
+template <>
+constexpr bool kShell2<Shell2> = true;
+
 struct Adj2Geom {
   int ny, nx;   // coarse shape
   int pairs;    // (nx - 2) / 2 block pairs per row
@@ -46,13 +68,15 @@ constexpr int kWavesPerGroup = 4;
 
 __host__ __device__ __forceinline__ int sd2(int c, int cp) { return c * (c + 1) / 2 + cp; }
 
-template <typename TS, bool kAdd>
-__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom g, RefineAdjArgs a, Mat2 m) {
+template <typename TS, bool kAdd, typename M>
+__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom g, RefineAdjArgs a, M mats) {
   fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.y, a.y_bs, a.xi_bar, a.xi_bar_bs, a.s_bar,
              a.s_bar_bs);
   if (kAdd) fetch_args(a.add, a.add_bs);
   const int lane = threadIdx.x % kLanes;
-  const int wave = blockIdx.x * kWavesPerGroup + threadIdx.x / kLanes;
+  // the wavefront index is uniform across its lanes; saying so lets every row-derived
+  // address (and a shell level's matrix rows) go through scalar registers
+  const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
   if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
   const int strip = wave % g.strips, chunk = wave / g.strips;
   const int P = strip * kOwnedPairs + lane - 1;  // blocks x = 2P+1, 2P+2
@@ -91,6 +115,19 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
 
   auto process = [&](int yb, const Row& rw) {
     const bool ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
+    float R[36], S[10];  // this block row's matrices
+    if constexpr (kShell2<M>) {
+      const auto row = row_of(mats, yb - 1);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = mats.m.s[e];
+    }
     float yv[2][4];  // [block of the pair][by * 2 + bx]
 #pragma unroll
     for (int by = 0; by < 2; ++by) {
@@ -108,7 +145,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
         for (int cp = 0; cp < 4; ++cp) {
           float v = 0.0f;
 #pragma unroll
-          for (int c = cp; c < 4; ++c) v = fmaf(m.s[sd2(c, cp)], yv[p][c], v);
+          for (int c = cp; c < 4; ++c) v = fmaf(S[sd2(c, cp)], yv[p][c], v);
           xo[p][cp] = v;
         }
 #pragma unroll
@@ -130,7 +167,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
       for (int w = 0; w < 9; ++w) {
         float v = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v = fmaf(m.r[c * 9 + w], yv[p][c], v);
+        for (int c = 0; c < 4; ++c) v = fmaf(R[c * 9 + w], yv[p][c], v);
         u[w] = v;
       }
 #pragma unroll
@@ -187,13 +224,15 @@ struct Fwd2Geom {
   int waves;    // wavefronts per sample
 };
 
-template <typename TS, bool kW>
-__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom g, RefineFwdArgs a, Mat2 m) {
+template <typename TS, bool kW, typename M>
+__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom g, RefineFwdArgs a, M mats) {
   fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.s_in, a.s_in_bs, a.xi, a.xi_bs, a.s_out,
              a.s_out_bs);
   if (kW) fetch_args(a.w, a.w_bs);
   const int lane = threadIdx.x % kLanes;
-  const int wave = blockIdx.x * kWavesPerGroup + threadIdx.x / kLanes;
+  // the wavefront index is uniform across its lanes; saying so lets every row-derived
+  // address (and a shell level's matrix rows) go through scalar registers
+  const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
   if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
   const int strip = wave % g.strips, chunk = wave / g.strips;
   const int P = strip * kLanes + lane;
@@ -230,6 +269,19 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
   float rm[4], r0[4];  // coarse rows y-1 and y
   auto compute_step = [&](int y, const Step& st) {
     float o[2][4];
+    float R[36], S[10];  // this coarse row's matrices
+    if constexpr (kShell2<M>) {
+      const auto row = row_of(mats, y - 1);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = mats.m.s[e];
+    }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       float win[9];  // window of block 2P+1+p: columns 2P+p .. 2P+p+2 of rows y-1, y, y+1
@@ -249,9 +301,9 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
       for (int c = 0; c < 4; ++c) {
         float v = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v = fmaf(m.r[c * 9 + k], win[k], v);
+        for (int k = 0; k < 9; ++k) v = fmaf(R[c * 9 + k], win[k], v);
 #pragma unroll
-        for (int cp = 0; cp <= c; ++cp) v = fmaf(m.s[sd2(c, cp)], xv[cp], v);
+        for (int cp = 0; cp <= c; ++cp) v = fmaf(S[sd2(c, cp)], xv[cp], v);
         o[p][c] = v;
       }
     }
@@ -310,9 +362,8 @@ int pick_ychunk(int rows, int strips, int64_t batch) {
   return static_cast<int>((rows + chunks - 1) / chunks);
 }
 
-template <typename TS>
-hipError_t fwd2_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
-  const Mat2 m = mat2_of(p, level);
+template <typename TS, typename M>
+hipError_t fwd2_launch(const icr_plan* p, int level, const M& m, const RefineFwdArgs& a, hipStream_t st) {
   Fwd2Geom g;
   g.ny = p->shapes[level][1];
   g.nx = p->shapes[level][2];
@@ -332,17 +383,16 @@ hipError_t fwd2_launch(const icr_plan* p, int level, const RefineFwdArgs& a, hip
     c.s_out = static_cast<TS*>(a.s_out) + b0 * a.s_out_bs;
     if (a.w) c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
     const dim3 grid(groups, static_cast<unsigned>(c.batch));
-    if (a.w) refine2_fwd<TS, true><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
-    else refine2_fwd<TS, false><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    if (a.w) refine2_fwd<TS, true, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    else refine2_fwd<TS, false, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <typename TS>
-hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
-  const Mat2 m = mat2_of(p, level);
+template <typename TS, typename M>
+hipError_t adj2_launch(const icr_plan* p, int level, const M& m, const RefineAdjArgs& a, hipStream_t st) {
   Adj2Geom g;
   g.ny = p->shapes[level][1];
   g.nx = p->shapes[level][2];
@@ -362,18 +412,31 @@ hipError_t adj2_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hip
     c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
     if (a.add) c.add = static_cast<const TS*>(a.add) + b0 * a.add_bs;
     const dim3 grid(groups, static_cast<unsigned>(c.batch));
-    if (a.add) refine2_adj<TS, true><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
-    else refine2_adj<TS, false><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    if (a.add) refine2_adj<TS, true, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    else refine2_adj<TS, false, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// Stationary 2-D levels in FP32 arithmetic with an even coarse row length, vector-aligned
-// fine rows and batch strides; everything else takes the generic kernels.
+template <typename TS>
+hipError_t fwd2_any(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
+  if (p->shell) return fwd2_launch<TS>(p, level, Shell2{p->lev[level].shell_tab, static_cast<int>(p->lev[level].nsets)}, a, st);
+  return fwd2_launch<TS>(p, level, Stat2{mat2_of(p, level)}, a, st);
+}
+template <typename TS>
+hipError_t adj2_any(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st) {
+  if (p->shell) return adj2_launch<TS>(p, level, Shell2{p->lev[level].shell_tab, static_cast<int>(p->lev[level].nsets)}, a, st);
+  return adj2_launch<TS>(p, level, Stat2{mat2_of(p, level)}, a, st);
+}
+
+// Stationary or shell-charted 2-D levels in FP32 arithmetic with an even coarse row
+// length, vector-aligned fine rows and batch strides; everything else takes the generic
+// kernels.
 bool eligible2(const icr_plan* p, int level) {
-  if (p->ndim != 2 || p->charted || p->precision == ICR_F64) return false;
+  if (p->ndim != 2 || p->precision == ICR_F64) return false;
+  if (p->charted && !(p->shell && p->lev[level].shell_tab)) return false;
   const int nx = p->shapes[level][2];
   if (nx % 2 != 0 || nx < 4) return false;
   const int64_t nf = int64_t(p->shapes[level + 1][1]) * p->shapes[level + 1][2];
@@ -388,7 +451,7 @@ bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipSt
   if (!aligned2(a.xi, 4 * el) || !aligned2(a.s_out, 4 * el) || !aligned2(a.s_in, 2 * el)) return false;
   if (a.xi_bs % 4 || a.s_out_bs % 4 || a.s_in_bs % 2) return false;
   if (a.w && (!aligned2(a.w, 16) || a.w_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? fwd2_launch<float>(p, level, a, st) : fwd2_launch<bf16_t>(p, level, a, st);
+  *err = p->precision == ICR_F32 ? fwd2_any<float>(p, level, a, st) : fwd2_any<bf16_t>(p, level, a, st);
   return true;
 }
 
@@ -397,7 +460,7 @@ bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipSt
   const int vec = 4 * p->elem_bytes;
   if (!aligned2(a.y, vec) || !aligned2(a.xi_bar, vec) || (a.add && !aligned2(a.add, vec))) return false;
   if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? adj2_launch<float>(p, level, a, st) : adj2_launch<bf16_t>(p, level, a, st);
+  *err = p->precision == ICR_F32 ? adj2_any<float>(p, level, a, st) : adj2_any<bf16_t>(p, level, a, st);
   return true;
 }
 
