@@ -304,28 +304,29 @@ __global__ void build_k00_kernel(KernelSpec ks, ChartSpec cs, int n0a, int n0b, 
 }
 
 // Derivative of the level-0 factor along dK_00 (dL = L Phi(L^-1 dK L^-T), as for sqrtD),
-// in three passes over n x n FP64 matrices. 1: one thread per column j overwrites dK
-// with X = L^-1 dK by forward substitution down its own column (no sharing between
-// threads). 2: one thread per column j writes Y = L^-1 X^T, reading row j of X.
-// 3: one thread per element (i, j <= i) of dL = L Phi(Y).
-__global__ void dl00_solve_kernel(const double* __restrict__ low, double* __restrict__ a, int64_t n) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// in three passes over n x n FP64 matrices. 1: X = L^-1 dK by forward substitution,
+// column j by one wavefront that keeps the column in LDS (the lanes split each row's dot
+// product, a butterfly sums it); dK is overwritten by X. 2: Y = L^-1 X^T the same way,
+// the right-hand side of column j being row j of X. 3: one thread per element (i, j <= i)
+// of dL = L Phi(Y).
+template <bool kTransposedRhs>
+__global__ void __launch_bounds__(64) dl00_solve_kernel(const double* __restrict__ low,
+                                                        const double* __restrict__ rhs, double* __restrict__ out,
+                                                        int64_t n) {
+  extern __shared__ double col[];
+  const int64_t j = blockIdx.x;
+  const int lane = threadIdx.x;
   for (int64_t i = 0; i < n; ++i) {
-    double v = a[i * n + j];
-    for (int64_t k = 0; k < i; ++k) v -= low[i * n + k] * a[k * n + j];
-    a[i * n + j] = v / low[i * n + i];
+    double v = 0.0;
+    for (int64_t k = lane; k < i; k += 64) v += low[i * n + k] * col[k];
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane == 0) {
+      const double b = kTransposedRhs ? rhs[j * n + i] : rhs[i * n + j];
+      col[i] = (b - v) / low[i * n + i];
+    }
+    __syncthreads();  // one wavefront: makes col[i] visible to every lane
   }
-}
-__global__ void dl00_solve_t_kernel(const double* __restrict__ low, const double* __restrict__ x,
-                                    double* __restrict__ y, int64_t n) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int64_t i = 0; i < n; ++i) {
-    double v = x[j * n + i];
-    for (int64_t k = 0; k < i; ++k) v -= low[i * n + k] * y[k * n + j];
-    y[i * n + j] = v / low[i * n + i];
-  }
+  for (int64_t i = lane; i < n; i += 64) out[i * n + j] = col[i];
 }
 __global__ void dl00_product_kernel(const double* __restrict__ low, const double* __restrict__ y,
                                     double* __restrict__ dl, int64_t n) {
@@ -340,45 +341,76 @@ __global__ void dl00_product_kernel(const double* __restrict__ low, const double
   dl[i * n + j] = v;  // zero above the diagonal (empty sum)
 }
 
-// Right-looking Cholesky of the n x n matrix a (row-major, in place, lower), one
-// workgroup. A pivot at or below tau makes its column zero and is counted.
-__global__ void __launch_bounds__(1024) cholesky_level0_kernel(double* __restrict__ a, int64_t n,
-                                                               double tau, int clamp,
-                                                               int32_t* __restrict__ count,
-                                                               int32_t* __restrict__ status) {
+// Blocked right-looking Cholesky of the n x n matrix a (row-major, in place, lower) in
+// panels of kPanel columns. A pivot at or below tau makes its column zero and is
+// counted; a zero column leaves the rest of the matrix unchanged. The blocked order only
+// regroups the same updates: each panel is factored column by column by one workgroup
+// (rows j0 .. n-1), then one workgroup per 32 x 32 tile of the trailing lower triangle
+// subtracts the panel's contribution.
+constexpr int kPanel = 32;
+
+__global__ void __launch_bounds__(1024) chol_panel_kernel(double* __restrict__ a, int64_t n, int64_t j0, double tau,
+                                                          int clamp, int32_t* __restrict__ count,
+                                                          int32_t* __restrict__ status) {
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
+  const int64_t j1 = j0 + kPanel < n ? j0 + kPanel : n;
   int clamped = 0;
-  for (int64_t j = 0; j < n; ++j) {
-    __syncthreads();  // the previous trailing update is complete
+  for (int64_t j = j0; j < j1; ++j) {
+    __syncthreads();  // the previous column's updates are complete
     const double piv = a[j * n + j];
     __syncthreads();  // every thread holds the pivot before column j is written
     if (!(piv > tau)) {  // uniform across the workgroup
       ++clamped;
       for (int64_t i = j + tid; i < n; i += nthreads) a[i * n + j] = 0.0;
-      continue;  // a zero column leaves the trailing matrix unchanged
+      continue;
     }
     const double root = sqrt(piv);
     const double inv = 1.0 / root;
     for (int64_t i = j + 1 + tid; i < n; i += nthreads) a[i * n + j] *= inv;
     if (tid == 0) a[j * n + j] = root;
     __syncthreads();
-    // trailing update of the lower triangle: a[i][k] -= a[i][j] a[k][j], j < k <= i
-    const int tx = tid & 31, ty = tid >> 5, ny = nthreads >> 5;
-    for (int64_t i = j + 1 + ty; i < n; i += ny) {
-      const double lij = a[i * n + j];
-      for (int64_t k = j + 1 + tx; k <= i; k += 32) a[i * n + k] -= lij * a[k * n + j];
+    // the panel's remaining columns: a[i][k] -= a[i][j] a[k][j], j < k < j1, k <= i
+    const int64_t cols = j1 - j - 1;
+    for (int64_t e = tid; e < (n - j - 1) * cols; e += nthreads) {
+      const int64_t i = j + 1 + e / cols, k = j + 1 + e % cols;
+      if (k <= i) a[i * n + k] -= a[i * n + j] * a[k * n + j];
     }
   }
-  __syncthreads();
-  for (int64_t t = tid; t < n * n; t += nthreads) {
-    const int64_t i = t / n, k = t % n;
-    if (k > i) a[t] = 0.0;
-  }
   if (tid == 0) {
-    *count = clamped;
-    if (clamped > 0 && !clamp) atomicOr(status, 2);
+    *count += clamped;  // panels run one after another on the stream
+    if (clamped > 0 && !clamp) *status |= 2;
   }
+}
+
+// Trailing update after the panel j0 .. j0+kPanel-1: a[i][k] -= sum_p a[i][p] a[k][p] for
+// j1 <= k <= i < n; one workgroup per 32 x 32 tile (tiles above the diagonal leave).
+__global__ void __launch_bounds__(256) chol_update_kernel(double* __restrict__ a, int64_t n, int64_t j0) {
+  const int64_t j1 = j0 + kPanel;
+  const int ti = blockIdx.y, tk = blockIdx.x;
+  if (tk > ti) return;
+  __shared__ double pi_[32][kPanel + 1], pk_[32][kPanel + 1];
+  const int64_t i0 = j1 + int64_t(ti) * 32, k0 = j1 + int64_t(tk) * 32;
+  for (int e = threadIdx.x; e < 32 * kPanel; e += blockDim.x) {
+    const int r = e / kPanel, c = e % kPanel;
+    pi_[r][c] = i0 + r < n ? a[(i0 + r) * n + j0 + c] : 0.0;
+    pk_[r][c] = k0 + r < n ? a[(k0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int r = e / 32, c = e % 32;
+    const int64_t i = i0 + r, k = k0 + c;
+    if (i >= n || k > i) continue;
+    double v = 0.0;
+    for (int p = 0; p < kPanel; ++p) v += pi_[r][p] * pk_[c][p];
+    a[i * n + k] -= v;
+  }
+}
+
+__global__ void chol_zero_upper_kernel(double* __restrict__ a, int64_t n) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  if (t % n > t / n) a[t] = 0.0;
 }
 
 template <typename TA>
@@ -557,9 +589,9 @@ hipError_t launch_level0_length_derivative(const icr_plan* p, double* scratch, h
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned cols = static_cast<unsigned>((n + 63) / 64);
-  dl00_solve_kernel<<<cols, 64, 0, st>>>(p->l00_64, a, n);
-  dl00_solve_t_kernel<<<cols, 64, 0, st>>>(p->l00_64, a, y, n);
+  const size_t lds = sizeof(double) * size_t(n);  // one column per wavefront (n <= 4096: 32 KB)
+  dl00_solve_kernel<false><<<static_cast<unsigned>(n), 64, lds, st>>>(p->l00_64, a, a, n);
+  dl00_solve_kernel<true><<<static_cast<unsigned>(n), 64, lds, st>>>(p->l00_64, a, y, n);
   dl00_product_kernel<<<grid, 256, 0, st>>>(p->l00_64, y, p->dl00_64, n);
   return hipGetLastError();
 }
@@ -567,7 +599,18 @@ hipError_t launch_level0_length_derivative(const icr_plan* p, double* scratch, h
 hipError_t launch_cholesky_level0(const icr_plan* p, double* a, int32_t* counts, int32_t* status,
                                   hipStream_t st) {
   const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
-  cholesky_level0_kernel<<<1, 1024, 0, st>>>(a, p->n0, tau_of(p), clamp, counts, status);
+  const int64_t n = p->n0;
+  for (int64_t j0 = 0; j0 < n; j0 += kPanel) {
+    chol_panel_kernel<<<1, 1024, 0, st>>>(a, n, j0, tau_of(p), clamp, counts, status);
+    const int64_t m = n - j0 - kPanel;  // trailing size
+    if (m > 0) {
+      const unsigned tiles = static_cast<unsigned>((m + 31) / 32);
+      chol_update_kernel<<<dim3(tiles, tiles), 256, 0, st>>>(a, n, j0);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  chol_zero_upper_kernel<<<static_cast<unsigned>((n * n + 255) / 256), 256, 0, st>>>(a, n);
   return hipGetLastError();
 }
 
