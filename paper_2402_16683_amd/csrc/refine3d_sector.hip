@@ -395,6 +395,9 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   constexpr int kAdjThreads = kTP * kTR;
   static_assert(64 % kTP == 0, "tile rows of lanes must not straddle wavefronts");
   __shared__ float ldy[2][8][kAdjThreads];   // double-buffered by coarse-plane parity
+  // shell levels: the coefficient rows of block planes zb .. zb+3 in a ring (slot zb & 3);
+  // read from LDS, the rows do not compete for the scalar registers
+  __shared__ float coef_ring[kIsShell<M> ? 4 : 1][kShellStride];
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.xtiles, g.zchunk, g.nfy, g.nfx, g.xy_tiles, g.nwg, a.y, a.y_bs, a.xi_bar,
              a.xi_bar_bs, a.s_bar, a.s_bar_bs);
   if (kAdd) fetch_args(a.add, a.add_bs);
@@ -448,9 +451,11 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   auto process = [&](int zb, const Plane& pl) {
     const bool ok = blocks_ok && zb >= 1 && zb <= g.nz - 2;
     float S[36];
-    const const_float* cz = nullptr;  // shell: this block plane's row (clamped, uniform)
+    const float* cz = nullptr;  // shell: this block plane's row in the LDS ring
+    float pre = 0.0f;           // shell: a value of the row for block plane zb + 2
     if constexpr (kIsShell<M>) {
-      cz = shell_row(m, min(max(zb - 1, 0), m.nsets - 1));
+      if (t < kShellStride) pre = m.tab[static_cast<int64_t>(min(max(zb + 1, 0), m.nsets - 1)) * kShellStride + t];
+      cz = coef_ring[zb & 3];
 #pragma unroll
       for (int e = 0; e < 36; ++e) S[e] = cz[54 + e];
     } else {
@@ -495,9 +500,6 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
     // sectors (Q), channels (C^T) and the z stage of P^T
     float G[2][9];
     if constexpr (kIsShell<M>) {
-      // the plane's sqrtD and C rows are scalar values: keep their loads in two groups so
-      // that both never need registers at the same time
-      __builtin_amdgcn_sched_barrier(0);
       // y and x sectors per z child, then per channel (ty, tx) the three window planes
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
@@ -585,6 +587,10 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
         ldy[buf][4 + c][t] = H[c][0] - H[c][2];  // to row yb - 1
       }
       __syncthreads();
+      // every wave is past its reads of block plane zb - 2's slot: refill it with zb + 2's
+      if constexpr (kIsShell<M>) {
+        if (t < kShellStride) coef_ring[(zb + 2) & 3][t] = pre;
+      }
       if (owner) {  // owner rows have both neighbour rows inside the tile
         float sv[4];
 #pragma unroll
@@ -601,6 +607,14 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   // Block planes z0-1 .. z1 (coarse plane zb - 1 is finished while plane zb is read),
   // three planes in flight: a ring of three buffers, unrolled so no buffer is copied
   // (measured faster than deeper rings or an indexed ring array).
+  if constexpr (kIsShell<M>) {  // rows of block planes z0-1 .. z0+2; later ones refill in process
+    for (int e = t; e < 4 * kShellStride; e += kAdjThreads) {
+      const int plane = z0 - 1 + e / kShellStride;
+      coef_ring[plane & 3][e % kShellStride] =
+          m.tab[static_cast<int64_t>(min(max(plane - 1, 0), m.nsets - 1)) * kShellStride + e % kShellStride];
+    }
+    __syncthreads();
+  }
   Plane pa, pb, pc;
   load_plane_y(z0 - 1, pa);
   load_plane_y(z0, pb);
