@@ -39,6 +39,12 @@ CASES = [
     C.case(1, (7,), 4, (0.1,), "sqexp", 0.4, batch=4, name="1d_se_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=3, name="2d_chart_24to164_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=2, precision="f64", name="2d_chart_24to84_f64"),
+    # 2-D chart, one set per radial shell: the 2-D fast kernels read a row per coarse row;
+    # an odd row length at level 0 sends that level to the generic kernels
+    C.case(2, (9, 12), 3, (1 / 9, 1 / 12), "matern32", 0.08, chart="logradial2d", batch=2, precision="bf16",
+           name="2d_chart_ragged_b2_bf16"),
+    C.case(2, (12, 9), 3, (1 / 12, 1 / 9), "matern52", 0.1, chart="logradial2d", batch=2,
+           name="2d_chart_oddx_b2_f32"),
     C.from_workload("icr3d_chart_10to388", depth=3, name="3d_chart_10to52_f32"),
     C.from_workload("icr3d_chart_10to388", depth=3, precision="bf16", name="3d_chart_10to52_bf16"),
     C.from_workload("icr3d_chart_10to388", depth=2, precision="f64", name="3d_chart_10to28_f64"),
