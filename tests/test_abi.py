@@ -5,6 +5,7 @@ argument errors are reported before any device work."""
 import ctypes
 import os
 import subprocess
+import sys
 
 import pytest
 
@@ -93,3 +94,23 @@ def test_hot_calls_reject_a_null_plan_and_negative_batch():
     assert lib.icr_plan_destroy(None) == 0 and B.icr_last_error() == ""
     info = B.IcrPlanInfo()
     assert lib.icr_plan_get_info(None, ctypes.byref(info)) == 1
+
+
+def test_a_missing_library_fails_loudly():
+    """No CPU fallback: without libicr.so the binding raises instead of computing."""
+    code = ("from paper_2402_16683_amd import icr\n"
+            "try:\n"
+            "    icr.load_library('/nonexistent/libicr.so')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert r.returncode == 0 and "raised" in r.stdout and "missing" in r.stdout
+
+
+def test_hot_calls_refuse_host_tensors():
+    import torch
+    plan = B.Plan.__new__(B.Plan)  # no device plan is needed to reach the argument check
+    plan.handle, plan.cfg = None, B.make_config(1, (12,), 1, (0.1,), precision="f32")
+    plan.info = {"n_xi": 32, "n_out": 20}
+    with pytest.raises(ValueError):
+        B.icr_forward(plan, torch.zeros(32))
