@@ -32,7 +32,7 @@ typedef struct icr_cf_plan icr_cf_plan;  /* opaque; owns the device amplitude sp
  * slope and offset_mean m finite. Synchronous. */
 icr_status icr_cf_create(int32_t n, double amplitude, double zero_mode, double length, double slope,
                          double offset_mean, void* hip_stream, icr_cf_plan** out_plan);
-/* Device workspace for the calls below: 20 n^2 bytes (two complex grids and one real). */
+/* Device workspace for the calls below: 12 n^2 bytes (three real grids). */
 icr_status icr_cf_workspace_bytes(const icr_cf_plan* plan, int64_t* bytes);
 /* Copy A (FP32, n x n) to host memory. Synchronous. */
 icr_status icr_cf_copy_amplitude(const icr_cf_plan* plan, float* amp);

@@ -6,13 +6,16 @@
 // inverse: T x = (Re - Im)(FFT2 x) / n. With lambda = exp(m + T(A xi)) the Jacobian is
 // J = diag(lambda) T diag(A) and N^-1 = diag(1 / lambda), so
 //   M_p v = v + A T(lambda(p) T(A v)).
-// A transform is four passes over the grid, each a hand-written kernel:
-//   1. row FFTs of the (pre-multiplied) real input, Stockham radix 4 in LDS, one
-//      workgroup a row;
+// A transform is four passes over the grid, each a hand-written kernel, on real data
+// (the separable Hartley transform S = H_rows H_cols and the identity cas(a + b) =
+// (cas a cas b + cas(-a) cas b + cas a cas(-b) - cas(-a) cas(-b)) / 2 give T from S):
+//   1. 1-D Hartley transforms of the (pre-multiplied) rows, two rows per workgroup as one
+//      complex Stockham FFT (radix 4) in LDS;
 //   2. a tiled transpose;
-//   3. row FFTs again (the column transforms of pass 1's result);
-//   4. a tiled transpose back that forms (Re - Im) / n and applies the post-operation
-//      (x lambda, exp(m + .), or v + A .), so the elementwise work rides on the passes.
+//   3. the same on the rows of the transpose (the column transforms), paired as (l, -l)
+//      so each workgroup forms T for both from S[., l] and S[., -l];
+//   4. a tiled transpose back with the post-operation (x lambda, exp(m + .), or v + A .),
+//      so the elementwise work rides on the passes.
 // FP32 throughout; twiddles from sincospif on the reduced angle.
 #include <cmath>
 #include <new>
@@ -40,30 +43,13 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// One row per workgroup, in LDS, Stockham autosort (natural order in and out): radix-4
-// stages, then one radix-2 stage when log2(n) is odd. A stage of span ns reads the r-th
-// quarter at j + r n/4, twiddles it by exp(-2 pi i r (j mod ns) / (4 ns)), takes the
+// In-place FFT of n complex values in LDS, Stockham autosort (natural order in and out):
+// radix-4 stages, then one radix-2 stage when log2(n) is odd. A stage of span ns reads the
+// r-th quarter at j + r n/4, twiddles it by exp(-2 pi i r (j mod ns) / (4 ns)), takes the
 // 4-point DFT and writes it to (j / ns) 4 ns + (j mod ns) + r ns; all reads of a stage
-// finish (barrier) before its writes.
-template <bool kRealIn>
-__global__ void __launch_bounds__(kFftThreads) cf_row_fft(const float* __restrict__ xr, const float* __restrict__ pre,
-                                                          const float2* __restrict__ xc, float2* __restrict__ out,
-                                                          int n, int logn) {
-  extern __shared__ float2 buf[];
-  const int64_t row = blockIdx.x;
+// finish (barrier) before its writes. Called by the whole workgroup; ends with a barrier.
+__device__ void lds_fft(float2* buf, int n, int logn) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < n; i += nt) {
-    float2 v;
-    if (kRealIn) {
-      float a = xr[row * n + i];
-      if (pre) a *= pre[row * n + i];
-      v = make_float2(a, 0.0f);
-    } else {
-      v = xc[row * n + i];
-    }
-    buf[i] = v;
-  }
-  __syncthreads();
   const int q4 = n >> 2;
   int ns = 1, lns = 0;
   for (; lns + 2 <= logn; ns <<= 2, lns += 2) {  // while 4 ns <= n
@@ -124,12 +110,93 @@ __global__ void __launch_bounds__(kFftThreads) cf_row_fft(const float* __restric
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += nt) out[row * n + i] = buf[i];
 }
 
-__global__ void __launch_bounds__(kTile * 8) cf_transpose(const float2* __restrict__ in, float2* __restrict__ out,
+constexpr int kDhtPer = 8;  // k values per thread in the post-processing (n / threads <= 8)
+
+// 1-D Hartley transforms (unnormalised, (Re - Im) of the DFT) of two real rows a, b at
+// once: the FFT of z = row_a + i row_b gives, with u = Z[-k], H_a[k] = (Z.x + u.x - Z.y +
+// u.y) / 2 and H_b[k] = (Z.y + u.y + Z.x - u.x) / 2. Pass 1 (kCombine false) takes the
+// row pairs (2w, 2w+1) of the pre-multiplied input and writes both transforms. Pass 3
+// (kCombine true) takes the rows (w, n-w) (w = 0: rows 0 and n/2) of the transposed
+// first-pass result, i.e. the column transforms S[., l] and S[., -l] of the separable
+// transform, and writes the 2-D Hartley transform from them,
+//   T[k][l] = (S[k][l] + S[-k][l] + S[k][-l] - S[-k][-l]) / 2   (cas(a + b) identity),
+// scaled by 1/n, still transposed (out row l holds T[.][l]).
+template <bool kCombine>
+__global__ void __launch_bounds__(kFftThreads) cf_dht_rows(const float* __restrict__ in, const float* __restrict__ pre,
+                                                           float* __restrict__ out, int n, int logn, float scale) {
+  extern __shared__ float2 buf[];
+  const int w = blockIdx.x;
+  const int ra = kCombine ? w : 2 * w;
+  const int rb = kCombine ? (w == 0 ? n / 2 : n - w) : 2 * w + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const float* xa = in + int64_t(ra) * n;
+  const float* xb = in + int64_t(rb) * n;
+  for (int i = tid; i < n; i += nt) {
+    float a = xa[i], b = xb[i];
+    if (pre) {
+      a *= pre[int64_t(ra) * n + i];
+      b *= pre[int64_t(rb) * n + i];
+    }
+    buf[i] = make_float2(a, b);
+  }
+  __syncthreads();
+  lds_fft(buf, n, logn);
+  float ha[kDhtPer], hb[kDhtPer];
+#pragma unroll
+  for (int it = 0; it < kDhtPer; ++it) {
+    const int k = tid + it * nt;
+    if (k < n) {
+      const float2 z = buf[k], u = buf[(n - k) & (n - 1)];
+      ha[it] = 0.5f * (z.x + u.x - z.y + u.y);
+      hb[it] = 0.5f * (z.y + u.y + z.x - u.x);
+    }
+  }
+  float* oa = out + int64_t(ra) * n;
+  float* ob = out + int64_t(rb) * n;
+  if (!kCombine) {
+#pragma unroll
+    for (int it = 0; it < kDhtPer; ++it) {
+      const int k = tid + it * nt;
+      if (k < n) {
+        oa[k] = ha[it];
+        ob[k] = hb[it];
+      }
+    }
+    return;
+  }
+  __syncthreads();  // every thread has read the spectrum: reuse the LDS for H_a, H_b
+  float* hs = reinterpret_cast<float*>(buf);
+#pragma unroll
+  for (int it = 0; it < kDhtPer; ++it) {
+    const int k = tid + it * nt;
+    if (k < n) {
+      hs[k] = ha[it];
+      hs[n + k] = hb[it];
+    }
+  }
+  __syncthreads();
+  const float half = 0.5f * scale;
+#pragma unroll
+  for (int it = 0; it < kDhtPer; ++it) {
+    const int k = tid + it * nt;
+    if (k < n) {
+      const int nk = (n - k) & (n - 1);
+      if (w == 0) {  // rows 0 and n/2 are their own reflections
+        oa[k] = ha[it] * scale;
+        ob[k] = hb[it] * scale;
+      } else {
+        oa[k] = half * (ha[it] + hs[nk] + hb[it] - hs[n + nk]);
+        ob[k] = half * (hb[it] + hs[n + nk] + ha[it] - hs[nk]);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kTile * 8) cf_transpose(const float* __restrict__ in, float* __restrict__ out,
                                                           int n) {
-  __shared__ float2 tile[kTile][kTile + 1];
+  __shared__ float tile[kTile][kTile + 1];
   const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
   const int tx = threadIdx.x, ty = threadIdx.y;
   for (int k = 0; k < kTile; k += 8) tile[ty + k][tx] = in[int64_t(by + ty + k) * n + bx + tx];
@@ -139,18 +206,16 @@ __global__ void __launch_bounds__(kTile * 8) cf_transpose(const float2* __restri
 
 enum Post { kPostNone = 0, kPostMul = 1, kPostExp = 2, kPostMetric = 3 };
 
-// y = post((Re - Im)(Yt^T) / n) with Yt the transposed 2-D FFT.
+// out = post(Tt^T): the transpose back of pass 3's result with the operator's elementwise
+// step (x lambda, exp(m + .), or v + A .).
 template <int kPost>
-__global__ void __launch_bounds__(kTile * 8) cf_finish(const float2* __restrict__ yt, float* __restrict__ out,
+__global__ void __launch_bounds__(kTile * 8) cf_finish(const float* __restrict__ tt, float* __restrict__ out,
                                                        const float* __restrict__ v1, const float* __restrict__ v2,
-                                                       float mean, float inv_n, int n) {
+                                                       float mean, int n) {
   __shared__ float tile[kTile][kTile + 1];
   const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
   const int tx = threadIdx.x, ty = threadIdx.y;
-  for (int k = 0; k < kTile; k += 8) {
-    const float2 c = yt[int64_t(by + ty + k) * n + bx + tx];
-    tile[ty + k][tx] = (c.x - c.y) * inv_n;
-  }
+  for (int k = 0; k < kTile; k += 8) tile[ty + k][tx] = tt[int64_t(by + ty + k) * n + bx + tx];
   __syncthreads();
   for (int k = 0; k < kTile; k += 8) {
     const int64_t idx = int64_t(bx + ty + k) * n + by + tx;
@@ -173,27 +238,26 @@ __global__ void cf_amplitude_kernel(float* __restrict__ amp, int n, double a, do
   amp[t] = t == 0 ? static_cast<float>(a0) : static_cast<float>(a * pow(1.0 + k2, -slope / 4.0));
 }
 
-// out = post(T(pre * x)); work: two complex n x n buffers.
+// out = post(T(pre * x)); work: two real n x n buffers.
 hipError_t transform(const icr_cf_plan* p, const float* x, const float* pre, float* out, int post, const float* v1,
-                     const float* v2, float2* work, hipStream_t st) {
+                     const float* v2, float* work, hipStream_t st) {
   const int n = p->n;
-  float2* c1 = work;
-  float2* c2 = work + int64_t(n) * n;
-  const unsigned rows = static_cast<unsigned>(n);
+  float* r1 = work;
+  float* r2 = work + int64_t(n) * n;
+  const unsigned pairs = static_cast<unsigned>(n / 2);
   // n / 4 radix-4 butterflies per stage over at most kFftIt per thread (n <= 4096)
   const unsigned threads = static_cast<unsigned>(n / 4 < kFftThreads ? (n / 4 < 64 ? 64 : n / 4) : kFftThreads);
   const size_t lds = sizeof(float2) * n;
-  cf_row_fft<true><<<rows, threads, lds, st>>>(x, pre, nullptr, c1, n, p->logn);
   const dim3 tgrid(n / kTile, n / kTile), tblock(kTile, 8);
-  cf_transpose<<<tgrid, tblock, 0, st>>>(c1, c2, n);
-  cf_row_fft<false><<<rows, threads, lds, st>>>(nullptr, nullptr, c2, c1, n, p->logn);
-  const float inv_n = 1.0f / static_cast<float>(n);
+  cf_dht_rows<false><<<pairs, threads, lds, st>>>(x, pre, r1, n, p->logn, 1.0f);
+  cf_transpose<<<tgrid, tblock, 0, st>>>(r1, r2, n);
+  cf_dht_rows<true><<<pairs, threads, lds, st>>>(r2, nullptr, r1, n, p->logn, 1.0f / static_cast<float>(n));
   const float mean = static_cast<float>(p->mean);
   switch (post) {
-    case kPostMul: cf_finish<kPostMul><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
-    case kPostExp: cf_finish<kPostExp><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
-    case kPostMetric: cf_finish<kPostMetric><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
-    default: cf_finish<kPostNone><<<tgrid, tblock, 0, st>>>(c1, out, v1, v2, mean, inv_n, n); break;
+    case kPostMul: cf_finish<kPostMul><<<tgrid, tblock, 0, st>>>(r1, out, v1, v2, mean, n); break;
+    case kPostExp: cf_finish<kPostExp><<<tgrid, tblock, 0, st>>>(r1, out, v1, v2, mean, n); break;
+    case kPostMetric: cf_finish<kPostMetric><<<tgrid, tblock, 0, st>>>(r1, out, v1, v2, mean, n); break;
+    default: cf_finish<kPostNone><<<tgrid, tblock, 0, st>>>(r1, out, v1, v2, mean, n); break;
   }
   return hipGetLastError();
 }
@@ -247,7 +311,7 @@ icr_status icr_cf_create(int32_t n, double amplitude, double zero_mode, double l
 icr_status icr_cf_workspace_bytes(const icr_cf_plan* p, int64_t* bytes) {
   icr::clear_error();
   if (!p || !bytes) return icr::cf_fail(ICR_ERR_INVALID_ARG, "plan or bytes is NULL");
-  *bytes = int64_t(p->n) * p->n * (2 * int64_t(sizeof(float2)) + int64_t(sizeof(float)));
+  *bytes = int64_t(p->n) * p->n * 3 * int64_t(sizeof(float));
   return ICR_OK;
 }
 
@@ -265,7 +329,7 @@ icr_status icr_cf_transform(const icr_cf_plan* p, const float* x, float* y, void
   if (!icr::cf_aligned(x) || !icr::cf_aligned(y) || (reinterpret_cast<uintptr_t>(workspace) % 8) != 0)
     return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
   const hipError_t e = icr::transform(p, x, nullptr, y, icr::kPostNone, nullptr, nullptr,
-                                      static_cast<float2*>(workspace), static_cast<hipStream_t>(hip_stream));
+                                      static_cast<float*>(workspace), static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("transform: ") + hipGetErrorString(e));
   return ICR_OK;
 }
@@ -277,7 +341,7 @@ icr_status icr_cf_rate(const icr_cf_plan* p, const float* position, float* lambd
   if (!icr::cf_aligned(position) || !icr::cf_aligned(lambda) || (reinterpret_cast<uintptr_t>(workspace) % 8) != 0)
     return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
   const hipError_t e = icr::transform(p, position, p->amp, lambda, icr::kPostExp, nullptr, nullptr,
-                                      static_cast<float2*>(workspace), static_cast<hipStream_t>(hip_stream));
+                                      static_cast<float*>(workspace), static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return icr::cf_fail(ICR_ERR_HIP, std::string("rate: ") + hipGetErrorString(e));
   return ICR_OK;
 }
@@ -291,8 +355,8 @@ icr_status icr_cf_metric_apply(const icr_cf_plan* p, const float* lambda, const 
     return icr::cf_fail(ICR_ERR_INVALID_ARG, "buffer not aligned");
   if (v == out) return icr::cf_fail(ICR_ERR_INVALID_ARG, "v and out must differ");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  float2* work = static_cast<float2*>(workspace);
-  float* u = reinterpret_cast<float*>(work + 2 * int64_t(p->n) * p->n);
+  float* work = static_cast<float*>(workspace);
+  float* u = work + 2 * int64_t(p->n) * p->n;
   // u = lambda * T(A v); out = v + A * T(u)
   hipError_t e = icr::transform(p, v, p->amp, u, icr::kPostMul, lambda, nullptr, work, st);
   if (e == hipSuccess) e = icr::transform(p, u, nullptr, out, icr::kPostMetric, v, p->amp, work, st);
