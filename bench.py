@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests in the served-mode stream (0: skip the served measurement)")
     ap.add_argument("--serve-priors", type=int, default=24)
+    ap.add_argument("--bf16-steps", type=int, default=20,
+                    help="timed steps of the same workload in BF16 storage (0: skip; f32 workloads only)")
     ap.add_argument("--cf-reps", type=int, default=11,
                     help="repetitions per size of the correlated-field M_p benchmark (0: skip it)")
     ap.add_argument("--hypergrad-steps", type=int, default=20,
@@ -279,6 +281,61 @@ def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
            "data": "truth xi* seed 2, noise sigma 0.1 seed 3, 70% observed (Bernoulli seed 4)"}
     log(f"cg: {iters} iterations in {ms:.2f} ms ({out['us_per_metric_product']:.1f} us per metric product), "
         f"|r|/|r0| = {out['residual_reduction']:.2e}", quiet)
+    return out
+
+
+def bf16_leg(B, wl: dict, steps: int, quiet: bool) -> dict:
+    """The same step in BF16 storage (FP32 arithmetic): time per step and the last level's
+    forward and adjoint launches (HIP events), with their algorithmic bandwidth."""
+    import torch
+    cfg = B.make_config(wl["ndim"], wl["shape0"], wl["depth"], wl["delta0"], kernel=wl["kernel"],
+                        scale=wl["scale"], length=wl["length"], chart=wl["chart"],
+                        chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966)),
+                        precision="bf16")
+    plan = B.icr_build_matrices(cfg)
+    info = plan.info
+    batch, L = wl["batch"], info["depth"]
+    n_xi, n_out, offs = info["n_xi"], info["n_out"], info["level_offsets"]
+    xi_h = torch.from_numpy(W.standard_normal_f32(n_xi, seed=0, batch=batch))
+    y_h = torch.from_numpy(W.standard_normal_f32(n_out, seed=1, batch=batch))
+    sets = [dict(xi=xi_h.to("cuda").to(plan.dtype), y=y_h.to("cuda").to(plan.dtype),
+                 s=torch.empty((batch, n_out), dtype=plan.dtype, device="cuda"),
+                 xib=torch.empty((batch, n_xi), dtype=plan.dtype, device="cuda"),
+                 wsf=B.workspace_for(plan, batch), wsa=B.workspace_for(plan, batch)) for _ in range(2)]
+
+    def step(k):
+        b = sets[k % 2]
+        B.icr_forward(plan, b["xi"], b["s"], b["wsf"])
+        B.icr_adjoint(plan, b["y"], b["xib"], b["wsa"])
+
+    def fwd_last(k):
+        b = sets[k % 2]
+        B.icr_forward_level(plan, L - 1, b["wsf"][:, offs[L - 1]:offs[L]], b["xi"][:, offs[L]:], b["s"])
+
+    def adj_last(k):
+        b = sets[k % 2]
+        B.icr_adjoint_level(plan, L - 1, b["y"], b["xib"][:, offs[L]:], b["wsa"][:, offs[L - 1]:offs[L]])
+
+    out = {}
+    for name, fn, n in (("ms_per_step", step, steps), ("fwd_last_ms", fwd_last, steps), ("adj_last_ms", adj_last, steps)):
+        for k in range(3):
+            fn(k)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for k in range(n):
+            evs[k][0].record()
+            fn(k)
+            evs[k][1].record()
+        torch.cuda.synchronize()
+        out[name] = statistics.mean(a.elapsed_time(b) for a, b in evs)
+    step_bytes = 2 * batch * (n_xi + n_out) * 2
+    launch_bytes = batch * (2 * n_out + (offs[L] - offs[L - 1])) * 2
+    out["fine_px_per_s"] = batch * n_out / (out["ms_per_step"] * 1e-3)
+    out["step_hbm_frac"] = step_bytes / (out["ms_per_step"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    out["adj_last_frac"] = launch_bytes / (out["adj_last_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    out["fwd_last_frac"] = launch_bytes / (out["fwd_last_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    log(f"bf16: {out['ms_per_step']:.3f} ms per step (event-timed), last level forward "
+        f"{out['fwd_last_ms'] * 1e3:.1f} us, adjoint {out['adj_last_ms'] * 1e3:.1f} us", quiet)
     return out
 
 
@@ -589,6 +646,8 @@ def main():
     if cg_iters > 0 and not args.copy_probe and prec != "bf16":
         out["cg"] = cg_solve(B, plan, wl, cg_iters, args.quiet)
         out["mgvi"] = mgvi_bench(B, plan, wl, 3, args.quiet)
+    if args.bf16_steps > 0 and prec == "f32" and not args.copy_probe:
+        out["bf16_storage"] = bf16_leg(B, wl, args.bf16_steps, args.quiet)
     if args.cf_reps > 0 and not args.copy_probe:
         out["correlated_field_metric"] = correlated_field_bench([64, 128, 256, 512, 1024, 2048, 4096], args.cf_reps,
                                                                 args.quiet)
