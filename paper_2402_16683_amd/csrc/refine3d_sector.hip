@@ -204,24 +204,39 @@ struct Fwd3Geom {
 // both are reduced over the workgroup by a fixed tree.
 template <typename TS, bool kW, typename M, bool kDot = false>
 __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdArgs a, M m) {
-  // plane-major order (no XCD renumbering): the forward's only shared data is the
-  // small coarse level, and this order measured faster on the 388^3 level
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.rows, g.zchunk, g.nfy, g.nfx, g.xy_blocks, a.s_in, a.s_in_bs, a.xi,
              a.xi_bs, a.s_out, a.s_out_bs);
   if (kW) fetch_args(a.w, a.w_bs);
   if (kDot) fetch_args(a.dot, a.dot_bs, a.partial, a.partial_bs, a.partial_sig);
   if constexpr (kIsShell<M>) fetch_args(m.tab);
   const int tile = static_cast<int>(blockIdx.x);
+  // Within each chunk of planes the 8 XCDs (workgroups go to them round-robin) each take
+  // a contiguous band of xy blocks, so the coarse rows that neighbouring blocks share are
+  // read into one L2; all XCDs still work on the same chunk, keeping DRAM accesses close.
+  const int chunk = tile / g.xy_blocks;
+  int xy;
+  {
+    const int r = tile - chunk * g.xy_blocks;
+    const int xcd = tile & (kXcds - 1);
+    const int shift = (chunk * g.xy_blocks) & (kXcds - 1);  // xcd of the chunk's block r is (shift + r) mod 8
+    int start = 0;
+    for (int x = 0; x < xcd; ++x) {
+      const int r0 = (x - shift) & (kXcds - 1);
+      start += r0 < g.xy_blocks ? (g.xy_blocks - r0 + kXcds - 1) / kXcds : 0;
+    }
+    const int r0 = (xcd - shift) & (kXcds - 1);
+    xy = start + (r - r0) / kXcds;
+  }
   // no early exit: threads past the last pair work on the last pair and store nothing,
   // so every kernel argument can be fetched in one round at the start (an exit branch
   // made the pointer loads wait for the geometry loads)
-  const int tid_raw = (tile % g.xy_blocks) * 256 + threadIdx.x;
+  const int tid_raw = xy * 256 + threadIdx.x;
   const bool valid = tid_raw < g.rows * g.pairs;
   const int tid = valid ? tid_raw : g.rows * g.pairs - 1;
   const int yi = tid / g.pairs;
   const int q = tid - yi * g.pairs;
   const int y = yi + 1;
-  const int zb = 1 + (tile / g.xy_blocks) * g.zchunk;
+  const int zb = 1 + chunk * g.zchunk;
   const int ze = min(zb + g.zchunk, g.nz - 1);
   const int64_t b = blockIdx.y;
   const TS* sc = static_cast<const TS*>(a.s_in) + b * a.s_in_bs;
