@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
           const float4 av = rw.v[by];
           v.x += av.x; v.y += av.y; v.z += av.z; v.w += av.w;
         }
-        Io<TS>::st4(xb + fine_off(yb, by), v);
+        st4_stream<TS>(xb + fine_off(yb, by), v);  // nontemporal: measured 79 vs 87 us (plain) at 1540^2 x 16
       }
     }
     // window contributions, then the y march: row yb-1 is complete after this block row
