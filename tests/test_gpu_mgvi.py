@@ -122,3 +122,29 @@ def test_newton_step_fp32_converges_and_refuses_bf16():
         B.icr_mgvi_newton_step(bf, w_d, torch.zeros((1, info["n_xi"]), device="cuda").bfloat16(),
                                torch.zeros((1, info["n_xi"]), device="cuda").bfloat16(), 3)
     assert exc.value.status == 5
+
+
+def test_weighted_adjoint_with_shared_weights_equals_per_sample_weights():
+    """w with batch stride 0 (one weight vector for every sample) against the same vector
+    repeated per sample, and a two-sample Newton step against two one-sample steps."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    c = CASES[1]
+    plan = C.gpu_plan(c)
+    info = plan.info
+    w = torch.from_numpy(_weights(info, 70)).cuda().float()
+    y = C.to_device(W.standard_normal(info["n_out"], seed=71, batch=3), plan)
+    shared = B.icr_weighted_adjoint(plan, w, y, half=True)
+    per = B.icr_weighted_adjoint(plan, w.repeat(3, 1).contiguous(), y, half=True)
+    torch.cuda.synchronize()
+    assert torch.equal(shared, per)
+    b = C.to_device(W.standard_normal(info["n_xi"], seed=72, batch=2), plan)
+    m2 = C.to_device(W.standard_normal(info["n_xi"], seed=73, batch=2), plan)
+    ones = [m2[k:k + 1].clone() for k in range(2)]
+    wl = w * 0.01   # a well-conditioned metric for FP32
+    B.icr_mgvi_newton_step(plan, wl, b, m2, 20)
+    for k in range(2):
+        B.icr_mgvi_newton_step(plan, wl, b[k:k + 1].contiguous(), ones[k], 20)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert torch.equal(m2[k], ones[k][0])
