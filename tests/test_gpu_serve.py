@@ -7,6 +7,8 @@ the same order whatever the batch, so the comparison is bitwise. Graph replays a
 checked over two rounds with eager work and synchronisation in between.
 """
 
+import math
+
 import numpy as np
 import pytest
 
@@ -20,6 +22,10 @@ POOL = [
     C.case(3, (8, 8, 8), 3, (0.06, 0.06, 0.06), "matern52", 0.2, name="s3"),
     C.case(3, (7, 9, 8), 2, (0.05, 0.06, 0.07), "matern32", 0.3, name="s4"),
     C.case(2, (9, 10), 3, (0.04, 0.05), "matern32", 0.1, precision="bf16", name="s5"),
+    # charted priors (one matrix set per radial shell) served like the stationary ones
+    C.case(2, (10, 12), 3, (0.1, 1 / 12), "matern32", 0.1, chart="logradial2d", name="s6"),
+    C.case(3, (6, 6, 6), 2, (1 / 6,) * 3, "matern32", 0.2, chart="logradial_cyl3d",
+           chart_params=(0.1, math.log(10.0), math.pi / 2, 1.0), name="s7"),
 ]
 
 
