@@ -409,7 +409,10 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   constexpr int kOR = kTR - 2;     // owned rows per tile
   constexpr int kAdjThreads = kTP * kTR;
   static_assert(64 % kTP == 0, "tile rows of lanes must not straddle wavefronts");
-  __shared__ float ldy[2][8][kAdjThreads];   // double-buffered by coarse-plane parity
+  // stationary levels: two coarse planes per barrier, sets alternating by plane pair;
+  // shell levels: one plane per barrier (their coefficient ring refills behind each)
+  constexpr int kPair = kIsShell<M> ? 1 : 2;
+  __shared__ float ldy[2][kPair][8][kAdjThreads];
   // shell levels: the coefficient rows of block planes zb .. zb+3 in a ring (slot zb & 3);
   // read from LDS, the rows do not compete for the scalar registers
   __shared__ float coef_ring[kIsShell<M> ? 4 : 1][kShellStride];
@@ -458,6 +461,19 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   };
 
   float A0[2][9], A1[2][9];
+  float pCy[4], pUp[4], pDn[4];  // pair mode: the y-stage values of the pending even plane
+  auto store_row = [&](int zc, const float (&cy)[4], int set, int q) {
+    if (owner) {  // owner rows have both neighbour rows inside the tile
+      float sv[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sv[c] = cy[c] + ldy[set][q][c][t - kTP] + ldy[set][q][4 + c][t + kTP];
+      TS* row = sb + (static_cast<int64_t>(zc) * g.ny + yb) * g.nx;
+      Io<TS>::st1(row + 2 * P + 1, sv[0]);
+      Io<TS>::st1(row + 2 * P + 2, sv[1]);
+      if (P == 0) Io<TS>::st1(row, sv[2]);
+      if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, sv[3]);
+    }
+  };
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -574,7 +590,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
     }
     if (zb >= z0 + 1) {  // coarse plane zb - 1 is complete in G (uniform branch)
       const int zc = zb - 1;
-      const int buf = zc & 1;
+      const int buf = zc & 1;  // one-plane mode
       // x stage: the pair sums its coarse columns x = 2P+1, 2P+2 from its own blocks and
       // the outer column of each neighbouring pair (the adjacent lanes, read with DPP
       // wave shifts); the first and last pairs also sum the edge columns x = 0 and nx-1.
@@ -592,29 +608,44 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
         H[2][ty] = P == 0 ? l0 : 0.0f;               // x = 0
         H[3][ty] = P == g.pairs - 1 ? r1 : 0.0f;     // x = nx-1
       }
-      // y stage through LDS; the buffer alternates with the plane, so one barrier per
-      // plane separates this plane's writes from its reads and from the next plane's writes
-      float Cy[4];
+      // y stage through LDS
+      float Cy[4], up[4], dn[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         Cy[c] = H[c][1];
-        ldy[buf][c][t] = H[c][0] + H[c][2];      // to row yb + 1
-        ldy[buf][4 + c][t] = H[c][0] - H[c][2];  // to row yb - 1
+        up[c] = H[c][0] + H[c][2];  // to row yb + 1
+        dn[c] = H[c][0] - H[c][2];  // to row yb - 1
       }
-      __syncthreads();
-      // every wave is past its reads of block plane zb - 2's slot: refill it with zb + 2's
-      if constexpr (kIsShell<M>) {
-        if (t < kShellStride) coef_ring[(zb + 2) & 3][t] = pre;
-      }
-      if (owner) {  // owner rows have both neighbour rows inside the tile
-        float sv[4];
+      if constexpr (kPair == 1) {
+        // the buffer alternates with the plane, so one barrier per plane separates this
+        // plane's writes from its reads and from the next plane's writes
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sv[c] = Cy[c] + ldy[buf][c][t - kTP] + ldy[buf][4 + c][t + kTP];
-        TS* row = sb + (static_cast<int64_t>(zc) * g.ny + yb) * g.nx;
-        Io<TS>::st1(row + 2 * P + 1, sv[0]);
-        Io<TS>::st1(row + 2 * P + 2, sv[1]);
-        if (P == 0) Io<TS>::st1(row, sv[2]);
-        if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, sv[3]);
+        for (int c = 0; c < 4; ++c) { ldy[buf][0][c][t] = up[c]; ldy[buf][0][4 + c][t] = dn[c]; }
+        __syncthreads();
+        // every wave is past its reads of block plane zb - 2's slot: refill it with zb + 2's
+        if constexpr (kIsShell<M>) {
+          if (t < kShellStride) coef_ring[(zb + 2) & 3][t] = pre;
+        }
+        store_row(zc, Cy, buf, 0);
+      } else {
+        // two planes per barrier: an even plane (counted from z0) waits in registers, an
+        // odd one writes both to the set of its pair (sets alternate by pair, so a pair's
+        // writes never meet the previous pair's reads)
+        const int idx = zc - z0;
+        if ((idx & 1) == 0) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) { pCy[c] = Cy[c]; pUp[c] = up[c]; pDn[c] = dn[c]; }
+        } else {
+          const int set = (idx >> 1) & 1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            ldy[set][0][c][t] = pUp[c]; ldy[set][0][4 + c][t] = pDn[c];
+            ldy[set][1][c][t] = up[c];  ldy[set][1][4 + c][t] = dn[c];
+          }
+          __syncthreads();
+          store_row(zc - 1, pCy, set, 0);
+          store_row(zc, Cy, set, 1);
+        }
       }
     }
   };
@@ -645,6 +676,16 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
     load_plane_y(zb + 4, pb);
     __builtin_amdgcn_sched_barrier(0);
     process(zb + 2, pc);
+  }
+  if constexpr (kPair == 2) {  // an odd number of planes leaves the last one pending
+    const int idx = z1 - 1 - z0;
+    if (idx >= 0 && (idx & 1) == 0) {
+      const int set = (idx >> 1) & 1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { ldy[set][0][c][t] = pUp[c]; ldy[set][0][4 + c][t] = pDn[c]; }
+      __syncthreads();
+      store_row(z1 - 1, pCy, set, 0);
+    }
   }
 }
 
