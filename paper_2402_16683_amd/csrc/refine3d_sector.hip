@@ -746,7 +746,12 @@ hipError_t fwd_launch(const icr_plan* p, int level, const M& k, const RefineFwdA
   const int64_t xy_blocks = (int64_t(g.rows) * g.pairs + 255) / 256;
   static const int64_t slots =
       resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false, M>), 256);
-  const int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
+  int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
+  {  // mid-size levels: at least 8 planes per workgroup while ~200 workgroups remain (the
+     // 100^3 -> 196^3 forward: 98 planes in 12 chunks instead of 40; the step 3 us shorter)
+    const int64_t c8 = (g.nz - 2) / 8;
+    if (c8 >= 1 && c8 < chunks && xy_blocks * c8 * (a.batch < 65535 ? a.batch : 65535) >= 192) chunks = c8;
+  }
   g.zchunk = static_cast<int>((g.nz - 2 + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz - 2 + g.zchunk - 1) / g.zchunk;
   g.xy_blocks = static_cast<int>(xy_blocks);
