@@ -10,8 +10,11 @@ than the 256 MB Infinity Cache. Prints one JSON line:
 
   value        fine pixels per second, batch * n_L^d / (time of one step)
   roofline     the dominant kernel (the last level's forward or adjoint) timed alone
-               with HIP events in the same launch configuration: algorithmic bytes
-               per launch / average duration, against the 8 TB/s HBM peak
+               in the same launch configuration, HIP events around a run of launches on
+               the stream they go to: algorithmic bytes per launch (the fine level's
+               input read and output write, 2 batch n_L^d elements; the coarse level's
+               read or write is implementation traffic, reported beside it) / average
+               duration, against the 8 TB/s HBM peak
   cpu_baseline the FP64 oracle on the host, one sample of the same workload,
                forward + adjoint, one thread
 """
@@ -64,6 +67,8 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="replay the step from a captured HIP graph (measured slower than launching "
                          "every kernel from the host on this stack, so off by default)")
+    ap.add_argument("--legs", default="icr2d_se_16to1540_b16,icr2d_chart_24to1284,icr1d_m32_12to260",
+                    help="other workloads measured compactly in the same line (empty: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -246,7 +251,7 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     return out
 
 
-def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
+def cg_solve(B, plan, wl: dict, iters: int, quiet: bool, solves: int = 5) -> dict:
     """MGVI-style metric solve on the workload: d = mask * L xi* + 0.1 noise with a
     Bernoulli(0.7) mask, w = mask / 0.1^2, b = L^T (w * d); `iters` CG steps of
     (L^T W L + 1) x = b on the device (each step one metric product), timed over
@@ -265,7 +270,7 @@ def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
     x = torch.empty_like(b)
     x, norms = B.icr_cg_metric(plan, w, b, iters, x=x, residual_norms=True, workspace=ws)
     torch.cuda.synchronize()
-    n_solves = 5
+    n_solves = solves
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_solves)]
     for e0, e1 in evs:
         e0.record()
@@ -281,6 +286,88 @@ def cg_solve(B, plan, wl: dict, iters: int, quiet: bool) -> dict:
            "data": "truth xi* seed 2, noise sigma 0.1 seed 3, 70% observed (Bernoulli seed 4)"}
     log(f"cg: {iters} iterations in {ms:.2f} ms ({out['us_per_metric_product']:.1f} us per metric product), "
         f"|r|/|r0| = {out['residual_reduction']:.2e}", quiet)
+    return out
+
+
+def time_runs(fn, n: int) -> float:
+    """Mean ms per call of fn(k), k = 0 .. n-1, from one pair of HIP events around the
+    whole run on the current stream (the calls launch there)."""
+    import torch
+    for k in range(3):
+        fn(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(n):
+        fn(k)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def workload_leg(B, key: str, steps: int, quiet: bool, prec=None, cg_iters: int = 0) -> dict:
+    """A compact measurement of another workload: the step (icr_forward + icr_adjoint over
+    its batch, two rotating buffer sets), the last level's forward and adjoint launches
+    with their algorithmic bandwidth, and for charted workloads CG and one MGVI iteration."""
+    import torch
+    wl = dict(W.WORKLOADS[key])
+    prec = prec or wl["precision"]
+    cfg = B.make_config(wl["ndim"], wl["shape0"], wl["depth"], wl["delta0"], kernel=wl["kernel"],
+                        scale=wl["scale"], length=wl["length"], chart=wl["chart"],
+                        chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966)),
+                        precision=prec)
+    t0 = time.perf_counter()
+    plan = B.icr_build_matrices(cfg)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info
+    batch, L, el = wl["batch"], info["depth"], info["elem_bytes"]
+    n_xi, n_out, offs = info["n_xi"], info["n_out"], info["level_offsets"]
+    xi_h = torch.from_numpy(W.standard_normal_f32(n_xi, seed=0, batch=batch))
+    y_h = torch.from_numpy(W.standard_normal_f32(n_out, seed=1, batch=batch))
+    sets = [dict(xi=xi_h.to("cuda").to(plan.dtype), y=y_h.to("cuda").to(plan.dtype),
+                 s=torch.empty((batch, n_out), dtype=plan.dtype, device="cuda"),
+                 xib=torch.empty((batch, n_xi), dtype=plan.dtype, device="cuda"),
+                 wsf=B.workspace_for(plan, batch), wsa=B.workspace_for(plan, batch)) for _ in range(2)]
+
+    def step(k):
+        b = sets[k % 2]
+        B.icr_forward(plan, b["xi"], b["s"], b["wsf"])
+        B.icr_adjoint(plan, b["y"], b["xib"], b["wsa"])
+
+    def fwd_last(k):
+        b = sets[k % 2]
+        B.icr_forward_level(plan, L - 1, b["wsf"][:, offs[L - 1]:offs[L]], b["xi"][:, offs[L]:], b["s"])
+
+    def adj_last(k):
+        b = sets[k % 2]
+        B.icr_adjoint_level(plan, L - 1, b["y"], b["xib"][:, offs[L]:], b["wsa"][:, offs[L - 1]:offs[L]])
+
+    ms = time_runs(step, steps)
+    out = {"workload": key, "precision": prec, "batch": batch, "final_shape": list(info["level_shapes"][-1]),
+           "build_ms": build_ms, "ms_per_step": ms, "us_per_step": ms * 1e3,
+           "fine_px_per_s": batch * n_out / (ms * 1e-3),
+           "step_hbm_frac": 2 * batch * (n_xi + n_out) * el / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    if L > 0 and batch * n_out >= 1 << 20:
+        alg = 2 * batch * n_out * el
+        out["fwd_last_ms"] = time_runs(fwd_last, steps)
+        out["adj_last_ms"] = time_runs(adj_last, steps)
+        out["fwd_last_frac"] = alg / (out["fwd_last_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        out["adj_last_frac"] = alg / (out["adj_last_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    log(f"{key} {prec}: {ms * 1e3:.1f} us per step (batch {batch})", quiet)
+    if cg_iters > 0:
+        out["cg"] = cg_solve(B, plan, wl, cg_iters, quiet)
+        out["mgvi"] = mgvi_bench(B, plan, wl, 3, quiet)
+        if prec == "f32":
+            # the same CG on an FP64 plan, for the residual reduction FP32 reaches against it
+            cfg64 = B.make_config(wl["ndim"], wl["shape0"], wl["depth"], wl["delta0"], kernel=wl["kernel"],
+                                  scale=wl["scale"], length=wl["length"], chart=wl["chart"],
+                                  chart_params=wl.get("chart_params", (0.1, 2.302585092994046, 1.5707963267948966)),
+                                  precision="f64")
+            plan64 = B.icr_build_matrices(cfg64)
+            out["cg_f64"] = cg_solve(B, plan64, wl, cg_iters, quiet, solves=1)
+            B.icr_plan_destroy(plan64)
+    del sets
+    B.icr_plan_destroy(plan)
     return out
 
 
@@ -363,19 +450,34 @@ def mgvi_bench(B, plan, wl: dict, pairs: int, quiet: bool) -> dict:
            torch.empty(B.icr_mgvi_workspace_bytes(plan, 1), dtype=torch.uint8, device="cuda"))
     B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(2):
-        B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 2
+    mean0 = mean.clone()
+
+    def iteration_ms(absdelta=None, done=None):
+        mean.copy_(mean0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss, absdelta=absdelta,
+                        iterations_done=done)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 2
+
+    ms = iteration_ms()
     products = pairs * 100 + 35 + 1   # metric products on single samples (the samples' CG runs batched)
+    # the paper's example stops the samples' CG by the energy change: absdelta = 1e-4 size / 10,
+    # at most 100 steps
+    absdelta = 1e-4 * n_xi / 10.0
+    done = torch.zeros(pairs, dtype=torch.int32, device="cuda")
+    ms_sl = iteration_ms(absdelta, done)
     out = {"antithetic_pairs": pairs, "sample_cg_iterations": 100, "newton_cg_iterations": 35,
            "ms_per_iteration": ms, "sample_metric_products_per_iteration": products,
            "us_per_sample_metric_product": ms * 1e3 / products,
+           "energy_rule": {"absdelta": absdelta, "max_iterations": 100, "ms_per_iteration": ms_sl,
+                           "sample_cg_steps_taken": [int(v) for v in done.cpu()]},
            "data": "draws eta seed 7, eta' seed 8 (uploaded before timing); truth seed 2, noise seed 3, mask seed 4"}
-    log(f"mgvi: {ms:.1f} ms per iteration ({pairs} pairs x 100 CG steps + Newton 35 CG steps)", quiet)
+    log(f"mgvi: {ms:.1f} ms per iteration ({pairs} pairs x 100 CG steps + Newton 35 CG steps); "
+        f"energy rule {ms_sl:.1f} ms, sample steps {out['energy_rule']['sample_cg_steps_taken']}", quiet)
     return out
 
 
@@ -561,12 +663,13 @@ def main():
         B.icr_adjoint_level(plan, L - 1, b["y"], b["xib"][:, offs[L]:], b["wsa"][:, offs[L - 1]:offs[L]])
 
     n_launch = max(args.steps, 10)
-    for k in range(4):
-        fwd_last(k)
-        adj_last(k)
-    fwd_ms = time_launches(fwd_last, n_launch)
-    adj_ms = time_launches(adj_last, n_launch)
-    launch_bytes = batch * (2 * n_out + n_prev) * el   # fine read + fine write + coarse
+    fwd_ms = time_runs(fwd_last, n_launch)
+    adj_ms = time_runs(adj_last, n_launch)
+    # algorithmic bytes of one last-level launch: its fine input (xi_L, or the cotangent
+    # y_L) read once and its fine output (s_L, or xi_bar_L) written once; the coarse
+    # level's read (forward) or write (adjoint) is implementation traffic
+    launch_bytes = batch * 2 * n_out * el
+    coarse_bytes = batch * n_prev * el
     dom, dom_ms = ("refine_adj_last", adj_ms) if adj_ms >= fwd_ms else ("refine_fwd_last", fwd_ms)
     achieved = launch_bytes / (dom_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
@@ -633,7 +736,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(tag, digest),
                      "kernel": dom, "launch_ms": dom_ms, "alg_bytes_per_launch": launch_bytes,
+                     "coarse_level_bytes_per_launch": coarse_bytes,
                      "fwd_last_ms": fwd_ms, "adj_last_ms": adj_ms,
+                     "fwd_last_frac": launch_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "copy_reference_gbs": copy_gbs},
         "step": {"alg_bytes": step_bytes,
                  "hbm_frac": step_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
@@ -653,6 +758,11 @@ def main():
                                                                 args.quiet)
     if args.hypergrad_steps > 0 and not args.copy_probe:
         out["hyper_grad"] = hyper_grad_bench(B, wl, prec, args.hypergrad_steps, args.quiet)
+    if args.legs and not args.copy_probe:
+        out["workloads"] = {}
+        for key in [k for k in args.legs.split(",") if k and k != args.workload]:
+            charted = W.WORKLOADS[key]["chart"] != "regular"
+            out["workloads"][key] = workload_leg(B, key, 20, args.quiet, cg_iters=200 if charted else 0)
     if args.serve_requests > 0 and not args.copy_probe:
         out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
     if not args.no_cpu_baseline:

@@ -252,6 +252,28 @@ icr_status icr_cg_metric(const icr_plan* plan, int64_t batch, const void* w, int
                          void* workspace, void* hip_stream);
 
 /*
+ * The same CG with the energy-change stopping rule of the paper's sample-drawing CG
+ * (section "Variational Inference": the linear samples are drawn by CG with an
+ * absolute energy tolerance "absdelta" and at most 100 iterations). The CG energy is
+ * E(x) = x.Mx / 2 - b.x; with the exact line search a step lowers it by
+ * alpha (r.r) / 2. A sample stops after the first step whose decrease is below absdelta
+ * (that step is kept), when its residual is exactly zero, or after maxiter steps; each
+ * sample of the batch stops on its own and is left unchanged from then on.
+ *   absdelta        > 0, in units of E (the paper's example: 1e-4 * n_xi / 10).
+ *   maxiter         >= 0 steps at most.
+ *   iterations_done optional device int32 [batch]: the steps each sample took.
+ *   residual_norms  optional device double [batch][maxiter + 1]: |r_k|, a stopped sample's
+ *                   last value repeated to the end.
+ *   workspace       icr_cg_workspace_bytes(plan, batch) bytes, 256-byte aligned.
+ * Every kernel of all maxiter iterations is enqueued at once (no host round trip); once
+ * every sample has stopped, a flag in the workspace makes the remaining kernels return
+ * at once. FP64 and FP32 plans only; asynchronous on hip_stream; allocates nothing.
+ */
+icr_status icr_cg_metric_sl(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
+                            const void* b, void* x, double absdelta, int32_t maxiter, int32_t* iterations_done,
+                            double* residual_norms, void* workspace, void* hip_stream);
+
+/*
  * Metric Gaussian Variational Inference around this prior with a Gaussian likelihood
  * (inverse noise variance w per final pixel), section "Variational Inference". MGVI
  * draws antithetic samples mean +- delta, delta = M^-1 r with r = eta + L^T (sqrt(w)

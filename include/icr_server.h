@@ -18,7 +18,8 @@
  * Conventions: as in icr.h (status codes, icr_last_error, caller-owned device buffers).
  * The server allocates its arena once at creation; nothing is allocated per request
  * except when a new graph is captured (from the arena). A request's buffers must stay
- * valid and untouched until icr_server_query reports it done. Results are identical
+ * valid and untouched until icr_server_query reports it done (see icr_server_submit for
+ * the ordering with the caller's stream). Results are identical
  * whether a request runs alone or in a batch (each sample is computed by the same
  * kernels in the same order).
  */
@@ -67,9 +68,15 @@ icr_status icr_server_create(const icr_server_config* cfg, icr_server** out);
 icr_status icr_server_register_plan(icr_server* server, const icr_plan* plan, int32_t* plan_id);
 
 /* Queue one request (a single sample). `w` (metric only) is [n_out] in the plan's
- * arithmetic type. ICR_ERR_OUT_OF_MEMORY if a single request cannot fit the arena. */
+ * arithmetic type. ICR_ERR_OUT_OF_MEMORY if a single request cannot fit the arena.
+ * Ordering: `in` and `w` may still be in production on hip_stream (NULL = the legacy
+ * default stream): the server records an event there at submission and the request's
+ * first read waits for it, so work the caller queued on that stream before this call
+ * is complete before the request starts. `in`, `out` and `w` must stay allocated and
+ * must not be written by the caller until icr_server_query reports the request done;
+ * `out` is complete once it does. */
 icr_status icr_server_submit(icr_server* server, int32_t plan_id, int32_t op, const void* in, void* out,
-                             const void* w, int64_t* request_id);
+                             const void* w, void* hip_stream, int64_t* request_id);
 
 /* State of a request; times are host steady-clock seconds (submit, launch of its batch,
  * observed completion). */

@@ -585,6 +585,43 @@ def conjugate_gradient(apply, b: np.ndarray, iterations: int) -> np.ndarray:
     return x
 
 
+def cg_energy(mx: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:
+    """The CG energy E(x) = x.Mx / 2 - b.x, given Mx."""
+    return 0.5 * float(x @ mx) - float(b @ x)
+
+
+def conjugate_gradient_sl(apply, b: np.ndarray, absdelta: float, maxiter: int):
+    """CG from x_0 = 0 stopped by the change of its energy (section "Variational
+    Inference": the linear samples are drawn by CG with an absolute energy tolerance and
+    an iteration limit). Each step is the textbook one; after it, E(x) = x.Mx / 2 - b.x
+    is evaluated from its definition (Mx carried along by linearity) and CG stops once a
+    step lowered E by less than absdelta, keeping that step, or after maxiter steps, or
+    at a zero residual. Returns (x, steps, per-step energy decreases)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    mx = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    energy = cg_energy(mx, b, x)
+    decreases = []
+    while len(decreases) < maxiter and rr != 0.0:
+        q = apply(p)
+        alpha = rr / float(p @ q)
+        x = x + alpha * p
+        mx = mx + alpha * q
+        r = r - alpha * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        new_energy = cg_energy(mx, b, x)
+        decreases.append(energy - new_energy)
+        energy = new_energy
+        if decreases[-1] < absdelta:
+            break
+    return x, len(decreases), np.array(decreases)
+
+
 def weighted_adjoint(model: ICROracle, w: np.ndarray, power: float, y: np.ndarray, add=None) -> np.ndarray:
     """L^T (w^power * y) (+ add)."""
     out = model.adjoint(np.asarray(w, dtype=np.float64) ** power * np.asarray(y, dtype=np.float64))

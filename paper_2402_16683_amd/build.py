@@ -24,7 +24,7 @@ LIB = os.path.join(PKG, "libicr.so")
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled on purpose (see the design notes).
-HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 

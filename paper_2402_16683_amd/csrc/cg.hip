@@ -8,6 +8,14 @@
 //   beta = (r'.r') / (r.r);  p = r' + beta p.
 // Dot products accumulate in FP64 in a fixed order (per-block partial sums, then one
 // block sums the partials), so runs are bitwise reproducible.
+//
+// Early stopping by the change of the CG energy E(x) = x.Mx / 2 - b.x (the "absdelta"
+// criterion of the sample-drawing CG in the paper's VI example): a step along p with the
+// exact line search lowers E by alpha (r.r) / 2, so the decrease needs no extra dot. A
+// sample whose step lowered E by less than absdelta keeps that step and is frozen (its x,
+// r, p no longer change). Every iteration up to the maximum is enqueued at once; when the
+// last sample freezes, a device flag makes the remaining kernels (metric sweeps included)
+// return at once, so nothing waits on the host.
 #include "icr_internal.h"
 
 namespace icr {
@@ -17,10 +25,13 @@ constexpr int kDotThreads = 256;
 constexpr int kDotBlocks = 1024;  // partial sums per sample
 
 struct CgScalars {
-  double rr;     // r.r of the current residual
+  double rr;       // r.r of the current residual
   double alpha;
   double beta;
   double pq;
+  double decrease; // alpha rr / 2: the energy decrease of the current step
+  int32_t active;  // 0 once the sample has stopped
+  int32_t iters;   // steps taken
 };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -69,8 +80,10 @@ __device__ __forceinline__ void stv(T* p, const Chunk<T, V>& c) {
 // partial[b][blk] = sum over this block's share of a[b] * c[b]
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__ a, const T* __restrict__ c,
-                                                           int64_t n, double* __restrict__ partial) {
+                                                           int64_t n, double* __restrict__ partial,
+                                                           const int32_t* halt) {
   __shared__ double sh[kDotThreads];
+  if (halted(halt)) return;
   const int64_t b = blockIdx.y;
   const T* pa = a + b * n;
   const T* pc = c + b * n;
@@ -84,28 +97,45 @@ __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
-// which = 0: pq = sum, alpha = rr / pq;  which = 1: rr' = sum, beta = rr' / rr, rr = rr'
-// (also records sqrt(rr') into norms[b][iter + 1] when norms is given);
+// which = 0: pq = sum, alpha = rr / pq, decrease = alpha rr / 2;
+// which = 1: rr' = sum, beta = rr' / rr, rr = rr', one more step taken, and the sample
+// stops when its step lowered the energy by less than absdelta (absdelta > 0) or r = 0
+// (also records sqrt(rr) into norms[b][iter + 1] when norms is given, frozen samples
+// repeating their last value);
 // which = 2: rr = sum (initialisation, records norms[b][0]).
+// A stopped sample's scalars no longer change.
 __global__ void __launch_bounds__(kDotThreads) dot_finish(const double* __restrict__ partial, CgScalars* sc,
-                                                          int which, double* norms, int iter, int stride) {
+                                                          int which, double* norms, int iter, int stride,
+                                                          double absdelta, const int32_t* halt) {
   __shared__ double sh[kDotThreads];
+  if (halted(halt)) return;
   const int64_t b = blockIdx.x;
   double v = 0.0;
   for (int k = threadIdx.x; k < kDotBlocks; k += kDotThreads) v += partial[b * kDotBlocks + k];
   const double s = block_sum(v, sh);
   if (threadIdx.x != 0) return;
   CgScalars& c = sc[b];
+  if (which == 2) {
+    c.rr = s;
+    c.active = s != 0.0 ? 1 : 0;
+    c.iters = 0;
+    if (norms) norms[b * stride] = sqrt(s);
+    return;
+  }
+  if (!c.active) {
+    if (which == 1 && norms) norms[b * stride + iter + 1] = sqrt(c.rr);
+    return;
+  }
   if (which == 0) {
     c.pq = s;
     c.alpha = s != 0.0 ? c.rr / s : 0.0;
-  } else if (which == 1) {
+    c.decrease = 0.5 * c.alpha * c.rr;
+  } else {
     c.beta = c.rr != 0.0 ? s / c.rr : 0.0;
     c.rr = s;
+    c.iters += 1;
     if (norms) norms[b * stride + iter + 1] = sqrt(s);
-  } else {
-    c.rr = s;
-    if (norms) norms[b * stride] = sqrt(s);
+    if (s == 0.0 || (absdelta > 0.0 && !(c.decrease >= absdelta))) c.active = 0;
   }
 }
 
@@ -113,9 +143,11 @@ __global__ void __launch_bounds__(kDotThreads) dot_finish(const double* __restri
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                          const T* __restrict__ q, int64_t n, const CgScalars* sc,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial, const int32_t* halt) {
   __shared__ double sh[kDotThreads];
+  if (halted(halt)) return;
   const int64_t b = blockIdx.y;
+  if (!sc[b].active) return;  // uniform per workgroup (one sample per grid row)
   const T a = static_cast<T>(sc[b].alpha);
   T* px = x + b * n;
   T* pr = r + b * n;
@@ -138,11 +170,19 @@ __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* _
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
-// p = r + beta p
+// p = r + beta p. With a halt flag, workgroup (0, 0) also raises it once every sample has
+// stopped: the flag is read only by later kernels.
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const T* __restrict__ r, int64_t n,
-                                                        const CgScalars* sc) {
+                                                        const CgScalars* sc, int32_t* halt, int batch) {
+  if (halted(halt)) return;
   const int64_t b = blockIdx.y;
+  if (halt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    int any = 0;
+    for (int k = 0; k < batch; ++k) any |= sc[k].active;
+    if (!any) *halt = 1;
+  }
+  if (!sc[b].active) return;
   const T beta = static_cast<T>(sc[b].beta);
   T* pp = p + b * n;
   const T* pr = r + b * n;
@@ -155,13 +195,14 @@ __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const
   }
 }
 
-// x = 0, r = p = b, partial sums of b.b
+// x = 0, r = p = b, partial sums of b.b; clears the halt flag
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) cg_init(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                        const T* __restrict__ bvec, int64_t n,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, int32_t* halt) {
   __shared__ double sh[kDotThreads];
   const int64_t b = blockIdx.y;
+  if (halt && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) *halt = 0;
   double acc = 0.0;
   Chunk<T, V> zero;
 #pragma unroll
@@ -178,32 +219,60 @@ __global__ void __launch_bounds__(kDotThreads) cg_init(T* __restrict__ x, T* __r
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
+// norms[b][k] for k past the steps sample b took: its last residual norm
+__global__ void cg_fill_norms(const CgScalars* sc, double* norms, int stride) {
+  const int64_t b = blockIdx.x;
+  const int taken = sc[b].iters;
+  const double last = sqrt(sc[b].rr);
+  for (int k = taken + 1 + threadIdx.x; k < stride; k += blockDim.x) norms[b * stride + k] = last;
+}
+
+// iterations_done[b] = steps sample b took
+__global__ void cg_report(const CgScalars* sc, int32_t* iterations_done, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) iterations_done[b] = sc[b].iters;
+}
+
 template <typename T, int V>
 hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec, void* x,
-                  int32_t iterations, double* norms, void* mws, T* r, T* pv, T* q, double* partial,
-                  CgScalars* sc, hipStream_t st,
-                  hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*, void*,
-                                       hipStream_t)) {
+                  int32_t iterations, double absdelta, int32_t* iterations_done, double* norms, void* mws, T* r,
+                  T* pv, T* q, double* partial, CgScalars* sc, int32_t* halt_flag, hipStream_t st,
+                  MetricFn metric) {
   const int64_t n = p->n_xi;
   const dim3 grid(kDotBlocks, static_cast<unsigned>(batch));
   const int stride = iterations + 1;
+  const int nb = static_cast<int>(batch);
+  // the halt flag only with early stopping: fixed-count runs pay nothing for it
+  int32_t* halt = absdelta > 0.0 ? halt_flag : nullptr;
   T* xv = static_cast<T*>(x);
-  cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, partial);
+  cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, partial, halt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 2, norms, 0, stride);
+  dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 2, norms, 0, stride, absdelta,
+                                                                   nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int it = 0; it < iterations; ++it) {
-    if ((e = metric(p, batch, w, w_bs, pv, q, mws, st)) != hipSuccess) return e;
-    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, partial);
+    if ((e = metric(p, batch, w, w_bs, pv, q, mws, halt, st)) != hipSuccess) return e;
+    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, partial, halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 0, nullptr, it, stride);
+    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 0, nullptr, it, stride, absdelta,
+                                                                     halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, partial);
+    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, partial, halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 1, norms, it, stride);
+    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 1, norms, it, stride, absdelta,
+                                                                     halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc);
+    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, halt, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (halt && norms) {
+    // the iterations after the halt wrote nothing: repeat each sample's last norm there
+    cg_fill_norms<<<static_cast<unsigned>(batch), 64, 0, st>>>(sc, norms, stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (iterations_done) {
+    cg_report<<<static_cast<unsigned>((batch + 63) / 64), 64, 0, st>>>(sc, iterations_done, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -220,13 +289,13 @@ int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch) {
   return up(batch * p->n_xi * el)          // metric workspace
          + 3 * up(vec)                     // r, p, q
          + up(batch * kDotBlocks * 8)      // partial sums
-         + up(batch * int64_t(sizeof(CgScalars)));
+         + up(batch * int64_t(sizeof(CgScalars)))
+         + 256;                            // halt flag
 }
 
 hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
-                     void* x, int32_t iterations, double* norms, void* workspace, hipStream_t st,
-                     hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*,
-                                          void*, hipStream_t)) {
+                     void* x, int32_t iterations, double absdelta, int32_t* iterations_done, double* norms,
+                     void* workspace, hipStream_t st, MetricFn metric) {
   const int el = p->elem_bytes;
   const int64_t n = p->n_xi;
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
@@ -238,20 +307,26 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   void* q = base; base += up(batch * n * el);
   double* partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
   CgScalars* sc = reinterpret_cast<CgScalars*>(base);
+  base += up(batch * int64_t(sizeof(CgScalars)));
+  int32_t* halt = reinterpret_cast<int32_t*>(base);
   // 16-byte accesses when every sample's vector starts 16-byte aligned (the workspace
   // vectors are 256-byte aligned; x and b are the caller's)
   const int v16 = 16 / el;
   const bool vec = n % v16 == 0 && aligned16(x) && aligned16(bvec) && aligned16(workspace);
   if (p->precision == ICR_F64) {
-    return vec ? run_cg<double, 2>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<double*>(r),
-                                   static_cast<double*>(pv), static_cast<double*>(q), partial, sc, st, metric)
-               : run_cg<double, 1>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<double*>(r),
-                                   static_cast<double*>(pv), static_cast<double*>(q), partial, sc, st, metric);
+    return vec ? run_cg<double, 2>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
+                                   static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
+                                   partial, sc, halt, st, metric)
+               : run_cg<double, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
+                                   static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
+                                   partial, sc, halt, st, metric);
   }
-  return vec ? run_cg<float, 4>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<float*>(r),
-                                static_cast<float*>(pv), static_cast<float*>(q), partial, sc, st, metric)
-             : run_cg<float, 1>(p, batch, w, w_bs, bvec, x, iterations, norms, mws, static_cast<float*>(r),
-                                static_cast<float*>(pv), static_cast<float*>(q), partial, sc, st, metric);
+  return vec ? run_cg<float, 4>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
+                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), partial,
+                                sc, halt, st, metric)
+             : run_cg<float, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
+                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), partial,
+                                sc, halt, st, metric);
 }
 
 }  // namespace icr

@@ -53,6 +53,7 @@ struct FusedArgs {
   const void* add;                // xi_bar += add (metric), [batch][n_xi]
   int64_t n_xi;
   int64_t batch0;                 // first sample of this launch
+  const int32_t* halt;            // device flag: when set the launch does nothing
 };
 
 template <int D>
@@ -93,6 +94,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_fwd(FusedArgs g) {
   TA* fields = reinterpret_cast<TA*>(lds_raw);
   TA* mats = fields + g.lds_even + g.lds_odd;  // R then sqrtD of every fused level
   TA* xl = mats + g.K * (NC * NW + NC * NC);     // the excitations of levels 0 .. K
+  if (halted(g.halt)) return;
   const int t = threadIdx.x;
   const int64_t b = g.batch0 + blockIdx.x;
   const TS* xi = static_cast<const TS*>(g.xi) + b * g.n_xi;
@@ -186,6 +188,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_adj(FusedArgs g) {
   TA* fields = reinterpret_cast<TA*>(lds_raw);
   TA* mats = fields + g.lds_even + g.lds_odd;
   TA* al = mats + g.K * (NC * NW + NC * NC);  // the metric's addends of levels 0 .. K
+  if (halted(g.halt)) return;
   const int t = threadIdx.x;
   const int64_t b = g.batch0 + blockIdx.x;
   TS* xb = static_cast<TS*>(g.xi_bar) + b * g.n_xi;
@@ -396,9 +399,10 @@ int fused_levels(const icr_plan* p, bool* level0) {
 
 hipError_t launch_fused_fwd(const icr_plan* p, int K, bool level0, int64_t batch, const void* xi, void* ws,
                             int64_t ws_bs, void* out, int64_t out_bs, const void* w, int64_t w_bs,
-                            hipStream_t st) {
+                            const int32_t* halt, hipStream_t st) {
   FusedArgs g;
   plan_range(p, K, level0, &g);
+  g.halt = halt;
   g.l0 = p->l00_c;
   g.xi = xi;
   g.ws = ws;
@@ -415,9 +419,11 @@ hipError_t launch_fused_fwd(const icr_plan* p, int K, bool level0, int64_t batch
 }
 
 hipError_t launch_fused_adj(const icr_plan* p, int K, bool level0, int64_t batch, const void* y, int64_t y_bs,
-                            void* xi_bar, void* ws, int64_t ws_bs, const void* add, hipStream_t st) {
+                            void* xi_bar, void* ws, int64_t ws_bs, const void* add, const int32_t* halt,
+                            hipStream_t st) {
   FusedArgs g;
   plan_range(p, K, level0, &g);
+  g.halt = halt;
   g.l0 = p->u00_c;
   g.y = y;
   g.y_bs = y_bs;

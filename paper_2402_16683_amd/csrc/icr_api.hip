@@ -97,13 +97,14 @@ void* at(const void* base, int64_t elems, int el) {
   return static_cast<char*>(const_cast<void*>(base)) + elems * el;
 }
 
-// Adjoint sweep from the fine cotangent y (level `depth`) down to level 0.
+// Adjoint sweep from the fine cotangent y (level `depth`) down to level 0. Every kernel of
+// the sweep does nothing while the device flag `halt` is set (NULL: never).
 icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t y_bs, void* xi_bar,
-                       void* ws, int64_t ws_bs, const void* add, hipStream_t st) {
+                       void* ws, int64_t ws_bs, const void* add, hipStream_t st, const int32_t* halt = nullptr) {
   const int el = p->elem_bytes;
   const int L = p->depth;
   if (L == 0) {
-    icr::Level0Args a{y, y_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
+    icr::Level0Args a{y, y_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
     return ICR_OK;
   }
@@ -120,37 +121,40 @@ icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t 
     a.add = add ? at(add, p->offsets[l + 1], el) : nullptr;
     a.add_bs = add ? p->n_xi : 0;
     a.batch = batch;
+    a.halt = halt;
     ICR_HIP_TRY(icr::launch_refine_adj(p, l, a, st));
   }
   if (K > 0)
     ICR_HIP_TRY(icr::launch_fused_adj(p, K, fuse0, batch, K == L ? y : at(ws, p->offsets[K], el),
-                                      K == L ? y_bs : ws_bs, xi_bar, ws, ws_bs, add, st));
+                                      K == L ? y_bs : ws_bs, xi_bar, ws, ws_bs, add, halt, st));
   if (!fuse0) {
-    icr::Level0Args a{ws, ws_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch};
+    icr::Level0Args a{ws, ws_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
   }
   return ICR_OK;
 }
 
-// Forward sweep; the last level goes to `out` (stride out_bs), optionally times w.
+// Forward sweep; the last level goes to `out` (stride out_bs), optionally times w. Every
+// kernel does nothing while the device flag `halt` is set (NULL: never).
 icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* out, int64_t out_bs,
-                       void* ws, int64_t ws_bs, const void* w, int64_t w_bs, hipStream_t st) {
+                       void* ws, int64_t ws_bs, const void* w, int64_t w_bs, hipStream_t st,
+                       const int32_t* halt = nullptr) {
   const int el = p->elem_bytes;
   const int L = p->depth;
   if (L == 0) {
-    icr::Level0Args a{xi, p->n_xi, out, out_bs, w, w_bs, nullptr, 0, batch};
+    icr::Level0Args a{xi, p->n_xi, out, out_bs, w, w_bs, nullptr, 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_fwd(p, a, st));
     return ICR_OK;
   }
   bool fuse0 = false;
   const int K = icr::fused_levels(p, &fuse0);  // the smallest levels in one launch
   if (!fuse0) {
-    icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch};
+    icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_fwd(p, a0, st));
   }
   if (K > 0)
     ICR_HIP_TRY(icr::launch_fused_fwd(p, K, fuse0, batch, xi, ws, ws_bs, K == L ? out : nullptr, out_bs,
-                                      K == L ? w : nullptr, w_bs, st));
+                                      K == L ? w : nullptr, w_bs, halt, st));
   for (int l = K; l < L; ++l) {
     icr::RefineFwdArgs a;
     a.s_in = at(ws, p->offsets[l], el);
@@ -162,6 +166,7 @@ icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* o
     a.w = l == L - 1 ? w : nullptr;
     a.w_bs = w_bs;
     a.batch = batch;
+    a.halt = halt;
     ICR_HIP_TRY(icr::launch_refine_fwd(p, l, a, st));
   }
   return ICR_OK;
@@ -173,16 +178,38 @@ icr_status check_call(const icr_plan* p, int64_t batch) {
   return ICR_OK;
 }
 
-// The metric as CG applies it: v -> L^T (w * L v) + v on `batch` samples.
+// The metric as CG applies it: v -> L^T (w * L v) + v on `batch` samples; its kernels do
+// nothing while the device flag `halt` is set (NULL: never).
 hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v,
-                         void* out, void* ws, hipStream_t st) {
+                         void* out, void* ws, const int32_t* halt, hipStream_t st) {
   const int el = p->elem_bytes;
   const int64_t bs = p->n_xi;
-  if (run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), bs, ws, bs, w, w_bs, st) != ICR_OK)
+  if (run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), bs, ws, bs, w, w_bs, st, halt) != ICR_OK)
     return hipErrorLaunchFailure;
-  if (run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), bs, out, ws, bs, v, st) != ICR_OK)
+  if (run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), bs, out, ws, bs, v, st, halt) != ICR_OK)
     return hipErrorLaunchFailure;
   return hipSuccess;
+}
+
+// Argument checks shared by the CG entry points.
+icr_status check_cg_call(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride, const void* b,
+                         const void* x, int32_t iterations, const double* residual_norms, const void* workspace) {
+  if (p->precision == ICR_BF16_F32ACC) return fail(ICR_ERR_UNSUPPORTED, "CG needs an FP64 or FP32 plan");
+  if (iterations < 0) return fail(ICR_ERR_INVALID_ARG, "iterations must be >= 0");
+  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "CG takes at most 65535 right-hand sides per call");
+  if (batch == 0) return ICR_OK;
+  const int el = p->elem_bytes;
+  if (!w || !b || !x || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(b, el) || !aligned(x, el) || !aligned(w, el) || !aligned(workspace, 256) ||
+      (residual_norms && !aligned(residual_norms, 8)))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned (workspace needs 256 bytes)");
+  const size_t nx = size_t(batch) * p->n_xi * el;
+  const size_t nw = size_t(icr::cg_workspace_bytes(p, batch));
+  if (icr::overlaps(b, nx, x, nx) || icr::overlaps(b, nx, workspace, nw) || icr::overlaps(x, nx, workspace, nw))
+    return fail(ICR_ERR_INVALID_ARG, "b, x and workspace overlap");
+  return ICR_OK;
 }
 
 // Worst off-pattern / on-pattern ratio over a shell table's sets (device check array).
@@ -632,23 +659,26 @@ icr_status icr_cg_metric(const icr_plan* p, int64_t batch, const void* w, int64_
   icr::clear_error();
   icr_status cs = check_call(p, batch);
   if (cs != ICR_OK) return cs;
-  if (p->precision == ICR_BF16_F32ACC) return fail(ICR_ERR_UNSUPPORTED, "CG needs an FP64 or FP32 plan");
-  if (iterations < 0) return fail(ICR_ERR_INVALID_ARG, "iterations must be >= 0");
-  if (batch > 65535) return fail(ICR_ERR_INVALID_ARG, "CG takes at most 65535 right-hand sides per call");
-  if (batch == 0) return ICR_OK;
-  const int el = p->elem_bytes;
-  if (!w || !b || !x || !workspace) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
-  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
-    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
-  if (!aligned(b, el) || !aligned(x, el) || !aligned(w, el) || !aligned(workspace, 256) ||
-      (residual_norms && !aligned(residual_norms, 8)))
-    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned (workspace needs 256 bytes)");
-  const size_t nx = size_t(batch) * p->n_xi * el;
-  const size_t nw = size_t(icr::cg_workspace_bytes(p, batch));
-  if (icr::overlaps(b, nx, x, nx) || icr::overlaps(b, nx, workspace, nw) || icr::overlaps(x, nx, workspace, nw))
-    return fail(ICR_ERR_INVALID_ARG, "b, x and workspace overlap");
-  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, b, x, iterations, residual_norms, workspace,
-                             static_cast<hipStream_t>(hip_stream), metric_for_cg));
+  cs = check_cg_call(p, batch, w, w_batch_stride, b, x, iterations, residual_norms, workspace);
+  if (cs != ICR_OK || batch == 0) return cs;
+  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, b, x, iterations, 0.0, nullptr, residual_norms,
+                             workspace, static_cast<hipStream_t>(hip_stream), metric_for_cg));
+  return ICR_OK;
+}
+
+icr_status icr_cg_metric_sl(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                            const void* b, void* x, double absdelta, int32_t maxiter, int32_t* iterations_done,
+                            double* residual_norms, void* workspace, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK) return cs;
+  if (!(absdelta > 0.0) || !std::isfinite(absdelta)) return fail(ICR_ERR_INVALID_ARG, "absdelta must be finite and > 0");
+  cs = check_cg_call(p, batch, w, w_batch_stride, b, x, maxiter, residual_norms, workspace);
+  if (cs != ICR_OK || batch == 0) return cs;
+  if (iterations_done && !aligned(iterations_done, 4))
+    return fail(ICR_ERR_INVALID_ARG, "iterations_done not aligned");
+  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, b, x, maxiter, absdelta, iterations_done,
+                             residual_norms, workspace, static_cast<hipStream_t>(hip_stream), metric_for_cg));
   return ICR_OK;
 }
 
@@ -717,10 +747,10 @@ icr_status icr_mgvi_newton_step(const icr_plan* p, int64_t batch, const void* w,
   void* cg_ws = base + 2 * vec;
   // g = M mean - b (the KL gradient over antithetic pairs), delta = M^-1 g, mean -= delta;
   // CG's own metric workspace serves the first product
-  ICR_HIP_TRY(metric_for_cg(p, batch, w, w_batch_stride, mean, g, cg_ws, st));
+  ICR_HIP_TRY(metric_for_cg(p, batch, w, w_batch_stride, mean, g, cg_ws, nullptr, st));
   ICR_HIP_TRY(icr::launch_sub(p, batch, g, b, p->n_xi, st));
-  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, g, delta, iterations, residual_norms, cg_ws, st,
-                             metric_for_cg));
+  ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, g, delta, iterations, 0.0, nullptr, residual_norms,
+                             cg_ws, st, metric_for_cg));
   ICR_HIP_TRY(icr::launch_sub(p, batch, mean, delta, p->n_xi, st));
   return ICR_OK;
 }

@@ -180,6 +180,7 @@ struct Level0Args {
   const void* w; int64_t w_bs;    // forward only: out *= w
   const void* add; int64_t add_bs;  // adjoint only: out += add
   int64_t batch;
+  const int32_t* halt = nullptr;  // device flag: when set (non-zero) the kernel does nothing
 };
 hipError_t launch_level0_fwd(const icr_plan* p, const Level0Args& a, hipStream_t st);
 hipError_t launch_level0_adj(const icr_plan* p, const Level0Args& a, hipStream_t st);
@@ -196,6 +197,7 @@ struct RefineFwdArgs {
   const void* dot = nullptr; int64_t dot_bs = 0;
   double* partial = nullptr; int64_t partial_bs = 0;
   double* partial_sig = nullptr;       // and <dot, value sqrtD xi>, same layout
+  const int32_t* halt = nullptr;       // device flag: when set (non-zero) the kernel does nothing
 };
 struct RefineAdjArgs {
   const void* y; int64_t y_bs;          // fine cotangent, level l+1
@@ -203,6 +205,7 @@ struct RefineAdjArgs {
   void* s_bar; int64_t s_bar_bs;        // coarse cotangent, level l
   const void* add; int64_t add_bs;      // optional: xi_bar += add (storage type)
   int64_t batch;
+  const int32_t* halt = nullptr;        // device flag: when set (non-zero) the kernel does nothing
 };
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st);
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
@@ -230,15 +233,26 @@ hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineA
 int fused_levels(const icr_plan* p, bool* level0);
 hipError_t launch_fused_fwd(const icr_plan* p, int K, bool level0, int64_t batch, const void* xi, void* ws,
                             int64_t ws_bs, void* out, int64_t out_bs, const void* w, int64_t w_bs,
-                            hipStream_t st);
+                            const int32_t* halt, hipStream_t st);
 hipError_t launch_fused_adj(const icr_plan* p, int K, bool level0, int64_t batch, const void* y, int64_t y_bs,
-                            void* xi_bar, void* ws, int64_t ws_bs, const void* add, hipStream_t st);
+                            void* xi_bar, void* ws, int64_t ws_bs, const void* add, const int32_t* halt,
+                            hipStream_t st);
 
-// conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1
+// A kernel whose launch carries a halt flag returns at once while the flag is set: the
+// early-stopping CG enqueues all of its iterations and stops them on the device.
+__device__ __forceinline__ bool halted(const int32_t* halt) {
+  return halt != nullptr && *halt != 0;
+}
+
+// conjugate gradients on the metric (cg.hip); `metric` applies L^T W L + 1, its kernels
+// doing nothing while `halt` (NULL: never) is set. absdelta > 0 stops a sample once one
+// step lowers its CG energy by less than absdelta; iterations_done (optional, device
+// [batch]) receives the steps each sample took.
+using MetricFn = hipError_t (*)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*, void*,
+                                const int32_t*, hipStream_t);
 int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
 hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
-                     void* x, int32_t iterations, double* norms, void* workspace, hipStream_t st,
-                     hipError_t (*metric)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*,
-                                          void*, hipStream_t));
+                     void* x, int32_t iterations, double absdelta, int32_t* iterations_done, double* norms,
+                     void* workspace, hipStream_t st, MetricFn metric);
 
 }  // namespace icr

@@ -22,6 +22,7 @@ template <typename TS, bool kLower>
 __global__ void __launch_bounds__(256) level0_kernel(const typename Acc<TS>::type* __restrict__ mat,
                                                      int64_t n, Level0Args a) {
   using TA = typename Acc<TS>::type;
+  if (halted(a.halt)) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t b = blockIdx.y;

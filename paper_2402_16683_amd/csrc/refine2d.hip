@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
   fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.y, a.y_bs, a.xi_bar, a.xi_bar_bs, a.s_bar,
              a.s_bar_bs);
   if (kAdd) fetch_args(a.add, a.add_bs);
+  if (halted(a.halt)) return;
   const int lane = threadIdx.x % kLanes;
   // the wavefront index is uniform across its lanes; saying so lets every row-derived
   // address (and a shell level's matrix rows) go through scalar registers
@@ -229,6 +230,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
   fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.s_in, a.s_in_bs, a.xi, a.xi_bs, a.s_out,
              a.s_out_bs);
   if (kW) fetch_args(a.w, a.w_bs);
+  if (halted(a.halt)) return;
   const int lane = threadIdx.x % kLanes;
   // the wavefront index is uniform across its lanes; saying so lets every row-derived
   // address (and a shell level's matrix rows) go through scalar registers

@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(256) refine3_fwd_sector(Fwd3Geom g, RefineFwdA
   if (kW) fetch_args(a.w, a.w_bs);
   if (kDot) fetch_args(a.dot, a.dot_bs, a.partial, a.partial_bs, a.partial_sig);
   if constexpr (kIsShell<M>) fetch_args(m.tab);
+  if (halted(a.halt)) return;
   const int tile = static_cast<int>(blockIdx.x);
   // Within each chunk of planes the 8 XCDs (workgroups go to them round-robin) each take
   // a contiguous band of xy blocks, so the coarse rows that neighbouring blocks share are
@@ -418,6 +419,7 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
   __shared__ float coef_ring[kIsShell<M> ? 4 : 1][kShellStride];
   fetch_args(g.nz, g.ny, g.nx, g.pairs, g.xtiles, g.zchunk, g.nfy, g.nfx, g.xy_tiles, g.nwg, a.y, a.y_bs, a.xi_bar,
              a.xi_bar_bs, a.s_bar, a.s_bar_bs);
+  if (halted(a.halt)) return;  // uniform over the workgroup: no barrier is left waiting
   if (kAdd) fetch_args(a.add, a.add_bs);
   if constexpr (kIsShell<M>) fetch_args(m.tab, m.nsets);
   const int t = threadIdx.x;

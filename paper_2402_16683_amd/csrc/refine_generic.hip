@@ -36,6 +36,7 @@ __global__ void __launch_bounds__(256) refine_fwd_generic(Geom g, RefineFwdArgs 
   using TA = typename Acc<TS>::type;
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
+  if (halted(a.halt)) return;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
   // a stationary level's R and sqrtD are staged in LDS with one cooperative load (read
@@ -92,6 +93,7 @@ __global__ void __launch_bounds__(256) refine_adj_generic(Geom g, int64_t ncoars
   using TA = typename Acc<TS>::type;
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
+  if (halted(a.halt)) return;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t b = blockIdx.y;
   __shared__ TA lds_r[kCharted ? 1 : NC * NW], lds_s[kCharted ? 1 : NC * NC];  // as in the forward

@@ -152,6 +152,7 @@ struct Request {
   const void* in;
   void* out;
   const void* w;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
   double t_submit = 0.0, t_launch = 0.0, t_done = 0.0;
   int32_t batch_size = 0;
   bool done = false;
@@ -354,6 +355,15 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
   const int op = r0.op;
   const int k = static_cast<int>(ids.size());
   hipStream_t st = s->streams[si];
+  // the batch reads its requests' inputs only after the work their callers queued before
+  // submitting (waits issued before any capture, so a captured graph holds none of them)
+  for (int64_t id : ids) {
+    const Request& r = s->requests[id];
+    if (r.ready && hipStreamWaitEvent(st, r.ready, 0) != hipSuccess) {
+      s->error = "hipStreamWaitEvent on a request's ready event failed";
+      return false;
+    }
+  }
   Batch* b = new Batch;
   b->ids = ids;
   b->plan_id = r0.plan_id;
@@ -425,6 +435,10 @@ void retire(icr_server* s) {
       Request& r = s->requests[id];
       r.t_done = t;
       r.done = true;
+      if (r.ready) {
+        s->event_pool.push_back(r.ready);
+        r.ready = nullptr;
+      }
       ++s->completed;
     }
     if (b->graph) b->graph->busy = false;
@@ -540,7 +554,7 @@ icr_status icr_server_register_plan(icr_server* s, const icr_plan* plan, int32_t
 }
 
 icr_status icr_server_submit(icr_server* s, int32_t plan_id, int32_t op, const void* in, void* out,
-                             const void* w, int64_t* request_id) {
+                             const void* w, void* hip_stream, int64_t* request_id) {
   icr::clear_error();
   if (!s || !in || !out || !request_id) {
     icr::set_error("server, in, out or request_id is NULL");
@@ -566,6 +580,20 @@ icr_status icr_server_submit(icr_server* s, int32_t plan_id, int32_t op, const v
   r.in = in;
   r.out = out;
   r.w = w;
+  if (s->event_pool.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      icr::set_error("hipEventCreate failed");
+      return ICR_ERR_HIP;
+    }
+    s->event_pool.push_back(ev);
+  }
+  r.ready = s->event_pool.back();
+  if (hipEventRecord(r.ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+    icr::set_error("hipEventRecord on the caller's stream failed");
+    return ICR_ERR_HIP;
+  }
+  s->event_pool.pop_back();
   r.t_submit = now_s();
   const int64_t id = s->next_id++;
   s->requests[id] = r;

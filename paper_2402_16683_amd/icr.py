@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_forward_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_cg_workspace_bytes": [vp, i64, ctypes.POINTER(i64)],
         "icr_cg_metric": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
+        "icr_cg_metric_sl": [vp, i64, vp, i64, vp, vp, ctypes.c_double, i32, vp, vp, vp, vp],
         "icr_adjoint_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_hyper_grad": [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp],
         "icr_weighted_adjoint": [vp, i64, vp, i64, i32, vp, vp, vp, vp, vp],
@@ -259,13 +260,37 @@ def _batch_of(t, n):
     return t.shape[0]
 
 
-def _check_tensor(t, plan, name):
+def _check_tensor(t, plan, name, shape=None, dtype=None):
+    """Shape (when given), device, dtype and contiguity of a tensor the library reads or
+    writes. The C ABI sees only pointers, so this is where sizes are enforced."""
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
-    if t.dtype != plan.dtype:
-        raise ValueError(f"{name} must be {plan.dtype}, got {t.dtype}")
+    dtype = dtype or plan.dtype
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _lead(t):
+    """Leading shape of a batched (batch, n) or single (n,) tensor."""
+    return tuple(t.shape[:-1])
+
+
+def _check_numel(t, plan, name, need, dtype=None):
+    """A flat buffer (workspace, level stack) of at least `need` elements."""
+    if t.numel() < need:
+        raise ValueError(f"{name} needs at least {need} elements, got {t.numel()}")
+    _check_tensor(t, plan, name, dtype=dtype)
+
+
+def _check_bytes(t, name, need):
+    if t.numel() * t.element_size() < need:
+        raise ValueError(f"{name} needs at least {need} bytes, got {t.numel() * t.element_size()}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
 
 
 def _empty(shape, plan, dtype=None):
@@ -279,42 +304,43 @@ def workspace_for(plan: Plan, batch: int, metric: bool = False):
 
 
 def icr_forward(plan: Plan, xi, s=None, workspace=None, stream=None):
-    _check_tensor(xi, plan, "xi")
     batch = _batch_of(xi, plan.info["n_xi"])
+    _check_tensor(xi, plan, "xi")
     if s is None:
         s = _empty(xi.shape[:-1] + (plan.info["n_out"],), plan)
-    _check_tensor(s, plan, "s")
+    _check_tensor(s, plan, "s", shape=_lead(xi) + (plan.info["n_out"],))
     if workspace is None:
         workspace = workspace_for(plan, batch)
+    _check_numel(workspace, plan, "workspace", batch * plan.info["workspace_elems"])
     _check(load_library().icr_forward(plan.handle, batch, xi.data_ptr(), s.data_ptr(),
                                       workspace.data_ptr(), _stream_handle(stream)))
     return s
 
 
 def icr_adjoint(plan: Plan, s_bar, xi_bar=None, workspace=None, stream=None):
-    _check_tensor(s_bar, plan, "s_bar")
     batch = _batch_of(s_bar, plan.info["n_out"])
+    _check_tensor(s_bar, plan, "s_bar")
     if xi_bar is None:
         xi_bar = _empty(s_bar.shape[:-1] + (plan.info["n_xi"],), plan)
-    _check_tensor(xi_bar, plan, "xi_bar")
+    _check_tensor(xi_bar, plan, "xi_bar", shape=_lead(s_bar) + (plan.info["n_xi"],))
     if workspace is None:
         workspace = workspace_for(plan, batch)
+    _check_numel(workspace, plan, "workspace", batch * plan.info["workspace_elems"])
     _check(load_library().icr_adjoint(plan.handle, batch, s_bar.data_ptr(), xi_bar.data_ptr(),
                                       workspace.data_ptr(), _stream_handle(stream)))
     return xi_bar
 
 
 def icr_metric_apply(plan: Plan, w, v, out=None, workspace=None, stream=None):
-    _check_tensor(v, plan, "v")
     batch = _batch_of(v, plan.info["n_xi"])
-    if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
-        raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
-    w_stride = 0 if w.dim() == 1 else w.shape[-1]
+    _check_tensor(v, plan, "v")
+    w_stride = _weights(plan, w, batch)
     if out is None:
         out = _empty(v.shape, plan)
-    _check_tensor(out, plan, "out")
+    _check_tensor(out, plan, "out", shape=tuple(v.shape))
     if workspace is None:
         workspace = workspace_for(plan, batch, metric=True)
+    _check_numel(workspace, plan, "workspace", batch * plan.info["metric_workspace_elems"])
     _check(load_library().icr_metric_apply(plan.handle, batch, w.data_ptr(), w_stride, v.data_ptr(),
                                            out.data_ptr(), workspace.data_ptr(), _stream_handle(stream)))
     return out
@@ -332,16 +358,21 @@ def icr_hyper_grad(plan: Plan, xi, s, s_levels, s_bar, sbar_levels, grad=None, w
     """(dE/dsigma, dE/dlength) of E = <s_bar, L xi> per sample, float64 (batch, 2), from a
     forward (xi -> s, workspace s_levels) and an adjoint (s_bar, workspace sbar_levels)."""
     import torch
-    for t, name in ((xi, "xi"), (s, "s"), (s_bar, "s_bar"), (s_levels, "s_levels"), (sbar_levels, "sbar_levels")):
-        _check_tensor(t, plan, name)
     batch = _batch_of(xi, plan.info["n_xi"])
+    _check_tensor(xi, plan, "xi")
+    out_shape = _lead(xi) + (plan.info["n_out"],)
+    _check_tensor(s, plan, "s", shape=out_shape)
+    _check_tensor(s_bar, plan, "s_bar", shape=out_shape)
+    for t, name in ((s_levels, "s_levels"), (sbar_levels, "sbar_levels")):
+        _check_numel(t, plan, name, batch * plan.info["workspace_elems"])
     if grad is None:
         grad = torch.empty((batch, 2), dtype=torch.float64, device=xi.device)
     if workspace is None:
         workspace = torch.empty((batch, max(plan.info["hypergrad_workspace_elems"], 1)), dtype=torch.float64,
                                 device=xi.device)
-    if grad.dtype != torch.float64 or grad.numel() < 2 * batch or workspace.dtype != torch.float64:
-        raise ValueError("grad and workspace must be float64 device tensors")
+    _check_numel(grad, plan, "grad", 2 * batch, dtype=torch.float64)
+    _check_numel(workspace, plan, "workspace", batch * plan.info["hypergrad_workspace_elems"],
+                 dtype=torch.float64)
     _check(load_library().icr_hyper_grad(plan.handle, batch, xi.data_ptr(), s.data_ptr(), s_levels.data_ptr(),
                                          s_bar.data_ptr(), sbar_levels.data_ptr(), grad.data_ptr(),
                                          workspace.data_ptr(), _stream_handle(stream)))
@@ -359,9 +390,40 @@ def hyper_grad(plan: Plan, xi, s_bar, stream=None):
     return s, xi_bar, grad
 
 
+def _level_sizes(plan: Plan, level: int):
+    """(coarse, fine) element counts of refinement `level` (level -1: level 0 alone)."""
+    offs = plan.info["level_offsets"]
+    depth = plan.info["depth"]
+    if not -1 <= level < depth:
+        raise ValueError(f"level must be in -1 .. {depth - 1}")
+    fine = offs[level + 2] - offs[level + 1]
+    coarse = 0 if level < 0 else offs[level + 1] - offs[level]
+    return coarse, fine
+
+
+def _check_level_view(t, plan, name, size, batch):
+    """A (batch, size) view (rows may be strided) or a (size,) vector for batch 1."""
+    if t is None:
+        return
+    shape = (size,) if t.dim() == 1 else (batch, size)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    if not t.is_cuda or t.dtype != plan.dtype:
+        raise ValueError(f"{name} must be a device tensor of {plan.dtype}")
+    if t.stride(-1) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+
+
 def icr_forward_level(plan: Plan, level: int, s_coarse, xi_fine, s_fine, stream=None):
     """One forward level on (batch, size) views; level -1 is the level-0 factor."""
     batch = xi_fine.shape[0] if xi_fine.dim() > 1 else 1
+    n_c, n_f = _level_sizes(plan, level)
+    _check_level_view(xi_fine, plan, "xi_fine", n_f, batch)
+    _check_level_view(s_fine, plan, "s_fine", n_f, batch)
+    if level >= 0:
+        if s_coarse is None:
+            raise ValueError("s_coarse is required for a refinement level")
+        _check_level_view(s_coarse, plan, "s_coarse", n_c, batch)
     _check(load_library().icr_forward_level(plan.handle, level, batch, _ptr(s_coarse), _stride(s_coarse),
                                             _ptr(xi_fine), xi_fine.stride(0) if xi_fine.dim() > 1 else xi_fine.numel(),
                                             _ptr(s_fine), s_fine.stride(0) if s_fine.dim() > 1 else s_fine.numel(),
@@ -372,6 +434,13 @@ def icr_forward_level(plan: Plan, level: int, s_coarse, xi_fine, s_fine, stream=
 def icr_adjoint_level(plan: Plan, level: int, y_fine, xi_bar_fine, s_bar_coarse, stream=None):
     """One adjoint level on (batch, size) views; level -1 is the level-0 factor."""
     batch = y_fine.shape[0] if y_fine.dim() > 1 else 1
+    n_c, n_f = _level_sizes(plan, level)
+    _check_level_view(y_fine, plan, "y_fine", n_f, batch)
+    _check_level_view(xi_bar_fine, plan, "xi_bar_fine", n_f, batch)
+    if level >= 0:
+        if s_bar_coarse is None:
+            raise ValueError("s_bar_coarse is required for a refinement level")
+        _check_level_view(s_bar_coarse, plan, "s_bar_coarse", n_c, batch)
     st = lambda t: 0 if t is None else (t.stride(0) if t.dim() > 1 else t.numel())
     _check(load_library().icr_adjoint_level(plan.handle, level, batch, _ptr(y_fine), st(y_fine),
                                             _ptr(xi_bar_fine), st(xi_bar_fine), _ptr(s_bar_coarse),
@@ -386,45 +455,72 @@ def icr_cg_workspace_bytes(plan: Plan, batch: int) -> int:
 
 
 def icr_cg_metric(plan: Plan, w, b, iterations: int, x=None, residual_norms=False, workspace=None,
-                  stream=None):
+                  stream=None, absdelta=None, iterations_done=None):
     """Solve (L^T W L + 1) x = b by `iterations` CG steps on the device (x_0 = 0).
 
-    Returns x, or (x, norms) with norms[batch][iterations + 1] = |r_k| when asked."""
+    With absdelta (> 0) a sample stops after the first step that lowers the CG energy
+    x.Mx/2 - b.x by less than absdelta, `iterations` being the maximum
+    (icr_cg_metric_sl); iterations_done, an int32 device tensor (batch,), then receives
+    the steps each sample took. Returns x, or (x, norms) with
+    norms[batch][iterations + 1] = |r_k| when asked."""
     import torch
-    _check_tensor(b, plan, "b")
     batch = _batch_of(b, plan.info["n_xi"])
-    if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
-        raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
-    w_stride = 0 if w.dim() == 1 else w.shape[-1]
+    _check_tensor(b, plan, "b")
+    w_stride = _weights(plan, w, batch)
     if x is None:
         x = _empty(b.shape, plan)
-    _check_tensor(x, plan, "x")
+    _check_tensor(x, plan, "x", shape=tuple(b.shape))
+    if iterations < 0:
+        raise ValueError("iterations must be >= 0")
     if workspace is None:
         workspace = torch.empty(icr_cg_workspace_bytes(plan, batch), dtype=torch.uint8, device="cuda")
+    _check_bytes(workspace, "workspace", icr_cg_workspace_bytes(plan, batch))
     norms = torch.empty((batch, iterations + 1), dtype=torch.float64, device="cuda") if residual_norms else None
-    _check(load_library().icr_cg_metric(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(), x.data_ptr(),
-                                        iterations, _ptr(norms), workspace.data_ptr(), _stream_handle(stream)))
+    if absdelta is None:
+        if iterations_done is not None:
+            raise ValueError("iterations_done needs absdelta")
+        _check(load_library().icr_cg_metric(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(), x.data_ptr(),
+                                            iterations, _ptr(norms), workspace.data_ptr(), _stream_handle(stream)))
+    else:
+        if iterations_done is not None:
+            _check_tensor(iterations_done, plan, "iterations_done", shape=(batch,), dtype=torch.int32)
+        _check(load_library().icr_cg_metric_sl(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(),
+                                               x.data_ptr(), float(absdelta), iterations, _ptr(iterations_done),
+                                               _ptr(norms), workspace.data_ptr(), _stream_handle(stream)))
     return (x, norms) if residual_norms else x
 
 
-def _weights(plan, w):
+def _weights(plan, w, batch):
+    """Batch stride of the weights: (n_out,) is shared by every sample (stride 0),
+    (batch, n_out) gives each sample its own row."""
+    n_out = plan.info["n_out"]
+    if w.dim() == 1:
+        if w.numel() != n_out:
+            raise ValueError(f"w must have {n_out} elements, got {w.numel()}")
+        stride = 0
+    elif tuple(w.shape) == (batch, n_out):
+        stride = n_out
+    else:
+        raise ValueError(f"w must have shape ({n_out},) or ({batch}, {n_out}), got {tuple(w.shape)}")
     if w.dtype != plan.acc_dtype or not w.is_cuda or not w.is_contiguous():
         raise ValueError(f"w must be a contiguous device tensor of {plan.acc_dtype}")
-    return 0 if w.dim() == 1 else w.shape[-1]
+    return stride
 
 
 def icr_weighted_adjoint(plan: Plan, w, y, add=None, half=True, out=None, workspace=None, stream=None):
     """out = L^T (w^(1/2 if half else 1) * y) + add (add may be None)."""
-    _check_tensor(y, plan, "y")
     batch = _batch_of(y, plan.info["n_out"])
-    w_stride = _weights(plan, w)
+    _check_tensor(y, plan, "y")
+    w_stride = _weights(plan, w, batch)
+    xi_shape = _lead(y) + (plan.info["n_xi"],)
     if add is not None:
-        _check_tensor(add, plan, "add")
+        _check_tensor(add, plan, "add", shape=xi_shape)
     if out is None:
-        out = _empty(y.shape[:-1] + (plan.info["n_xi"],), plan)
-    _check_tensor(out, plan, "out")
+        out = _empty(xi_shape, plan)
+    _check_tensor(out, plan, "out", shape=xi_shape)
     if workspace is None:
         workspace = workspace_for(plan, batch, metric=True)
+    _check_numel(workspace, plan, "workspace", batch * plan.info["metric_workspace_elems"])
     _check(load_library().icr_weighted_adjoint(plan.handle, batch, w.data_ptr(), w_stride, 1 if half else 0,
                                                y.data_ptr(), _ptr(add), out.data_ptr(), workspace.data_ptr(),
                                                _stream_handle(stream)))
@@ -442,12 +538,15 @@ def icr_mgvi_newton_step(plan: Plan, w, b, mean, iterations: int, residual_norms
     """mean <- mean - M^-1 (M mean - b) in place (CG with `iterations` steps); returns mean
     (and the CG residual norms when asked)."""
     import torch
-    _check_tensor(b, plan, "b")
-    _check_tensor(mean, plan, "mean")
     batch = _batch_of(mean, plan.info["n_xi"])
-    w_stride = _weights(plan, w)
+    _check_tensor(mean, plan, "mean")
+    _check_tensor(b, plan, "b", shape=tuple(mean.shape))
+    w_stride = _weights(plan, w, batch)
+    if iterations < 0:
+        raise ValueError("iterations must be >= 0")
     if workspace is None:
         workspace = torch.empty(icr_mgvi_workspace_bytes(plan, batch), dtype=torch.uint8, device="cuda")
+    _check_bytes(workspace, "workspace", icr_mgvi_workspace_bytes(plan, batch))
     norms = torch.empty((batch, iterations + 1), dtype=torch.float64, device="cuda") if residual_norms else None
     _check(load_library().icr_mgvi_newton_step(plan.handle, batch, w.data_ptr(), w_stride, b.data_ptr(),
                                                mean.data_ptr(), iterations, _ptr(norms), workspace.data_ptr(),
@@ -456,12 +555,14 @@ def icr_mgvi_newton_step(plan: Plan, w, b, mean, iterations: int, residual_norms
 
 
 def mgvi(plan: Plan, w, d, n_pairs: int = 3, n_iterations: int = 3, sample_iterations: int = 100,
-         newton_iterations: int = 35, seed: int = 0, mean=None, stream=None):
+         newton_iterations: int = 35, seed: int = 0, mean=None, stream=None, absdelta=None):
     """MGVI with antithetic samples: per iteration draw n_pairs sample displacements
     delta = M^-1 (eta + L^T (sqrt(w) eta')) (CG) around the current mean, then one
-    Newton-CG step of the mean. Random numbers come from numpy's PCG64 with `seed` and
-    are uploaded; every arithmetic step runs in the library. Returns (mean, deltas);
-    the samples are mean + deltas and mean - deltas."""
+    Newton-CG step of the mean. The samples' CG runs sample_iterations steps, or with
+    absdelta stops by the energy-change rule with sample_iterations as its maximum.
+    Random numbers come from numpy's PCG64 with `seed` and are uploaded; every arithmetic
+    step runs in the library. Returns (mean, deltas); the samples are mean + deltas and
+    mean - deltas."""
     import numpy as _np
     import torch
     n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
@@ -472,19 +573,22 @@ def mgvi(plan: Plan, w, d, n_pairs: int = 3, n_iterations: int = 3, sample_itera
     for _ in range(n_iterations):
         eta = torch.from_numpy(rng.standard_normal((n_pairs, n_xi))).to("cuda").to(plan.dtype)
         eta_d = torch.from_numpy(rng.standard_normal((n_pairs, n_out))).to("cuda").to(plan.dtype)
-        deltas = mgvi_step(plan, w, b, mean, eta, eta_d, sample_iterations, newton_iterations, stream=stream)
+        deltas = mgvi_step(plan, w, b, mean, eta, eta_d, sample_iterations, newton_iterations, stream=stream,
+                           absdelta=absdelta)
     return mean[0], deltas
 
 
 def mgvi_step(plan: Plan, w, b, mean, eta, eta_d, sample_iterations: int, newton_iterations: int,
-              workspaces=None, stream=None):
+              workspaces=None, stream=None, absdelta=None, iterations_done=None):
     """The device work of one MGVI iteration for given standard-normal draws eta
     (pairs, n_xi) and eta_d (pairs, n_out): the sample displacements (returned) and the
     Newton-CG step of `mean` (updated in place); b = L^T W d. workspaces: optional
-    (weighted-adjoint, CG, Newton) workspaces to reuse."""
+    (weighted-adjoint, CG, Newton) workspaces to reuse. absdelta: stop the samples' CG
+    by the energy-change rule (sample_iterations is then the maximum)."""
     ws_a, ws_cg, ws_n = workspaces if workspaces is not None else (None, None, None)
     r = icr_weighted_adjoint(plan, w, eta_d, add=eta, half=True, workspace=ws_a, stream=stream)
-    deltas = icr_cg_metric(plan, w, r, sample_iterations, workspace=ws_cg, stream=stream)
+    deltas = icr_cg_metric(plan, w, r, sample_iterations, workspace=ws_cg, stream=stream, absdelta=absdelta,
+                           iterations_done=iterations_done)
     icr_mgvi_newton_step(plan, w, b, mean, newton_iterations, workspace=ws_n, stream=stream)
     return deltas
 

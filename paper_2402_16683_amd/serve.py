@@ -37,7 +37,7 @@ def _lib():
         sigs = {
             "icr_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "icr_server_register_plan": [vp, vp, ctypes.POINTER(i32)],
-            "icr_server_submit": [vp, i32, i32, vp, vp, vp, ctypes.POINTER(i64)],
+            "icr_server_submit": [vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(i64)],
             "icr_server_query": [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl), ctypes.POINTER(i32)],
             "icr_server_drain": [vp, dbl],
@@ -60,6 +60,7 @@ class Server:
         self.handle = ctypes.c_void_p()
         B._check(_lib().icr_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
         self.plans = []
+        self._held = {}   # request id -> tensors the request reads or writes, until it is done
 
     def register(self, plan: B.Plan) -> int:
         pid = ctypes.c_int32()
@@ -67,10 +68,15 @@ class Server:
         self.plans.append(plan)
         return pid.value
 
-    def submit(self, plan_id: int, op: str, inp, out, w=None) -> int:
+    def submit(self, plan_id: int, op: str, inp, out, w=None, stream=None) -> int:
+        """Queue one request; `inp` and `w` may still be in production on `stream` (default:
+        torch's current stream): the request waits for the work queued there before this
+        call. The tensors are kept alive here until the request is reported done."""
         rid = ctypes.c_int64()
         B._check(_lib().icr_server_submit(self.handle, plan_id, OPS[op], inp.data_ptr(), out.data_ptr(),
-                                          None if w is None else w.data_ptr(), ctypes.byref(rid)))
+                                          None if w is None else w.data_ptr(), B._stream_handle(stream),
+                                          ctypes.byref(rid)))
+        self._held[rid.value] = (inp, out, w)
         return rid.value
 
     def query(self, rid: int):
@@ -78,10 +84,13 @@ class Server:
                                 ctypes.c_int32())
         B._check(_lib().icr_server_query(self.handle, rid, ctypes.byref(done), ctypes.byref(ts), ctypes.byref(tl),
                                          ctypes.byref(td), ctypes.byref(bs)))
+        if done.value:
+            self._held.pop(rid, None)
         return bool(done.value), ts.value, tl.value, td.value, bs.value
 
     def drain(self, timeout_s: float = 0.0):
         B._check(_lib().icr_server_drain(self.handle, timeout_s))
+        self._held.clear()   # nothing is pending or in flight after a successful drain
 
     def stats(self) -> dict:
         st = ServerStats()

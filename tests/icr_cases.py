@@ -87,6 +87,13 @@ def to_numpy(t) -> np.ndarray:
     return t.detach().to(torch.float64).cpu().numpy()
 
 
+def nan_like(shape, plan):
+    """A device buffer of the plan's storage type filled with NaN: an output element a
+    kernel never writes stays NaN and fails the finiteness checks."""
+    import torch
+    return torch.full(shape, float("nan"), dtype=plan.dtype, device="cuda")
+
+
 def to_device(a: np.ndarray, plan):
     """Host FP64 array -> device tensor of the plan's storage dtype."""
     import torch

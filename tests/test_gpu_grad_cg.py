@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from oracle import icr_oracle as O
 from tests import icr_cases as C
 
 pytestmark = pytest.mark.gpu
@@ -169,3 +170,172 @@ def test_cg_batched_right_hand_sides_are_independent():
     x0 = B.icr_cg_metric(plan, torch.from_numpy(w).cuda(), C.to_device(b2[1:], plan), 40)
     torch.cuda.synchronize()
     assert torch.equal(xb[1:], x0)
+
+
+# --- the charted workload at its stated size and shape -------------------------------
+
+CHART_FULL = C.from_workload("icr2d_chart_24to1284", name="cg_chart_24to1284")
+# a charted copy with a 32 x 32 output: 11^2 -> 18^2 -> 32^2, the same chart and kernel
+CHART_32 = C.case(2, (11, 11), 2, (1 / 11, 1 / 11), "matern32", 0.05, chart="logradial2d", name="chart_32x32")
+CHART_DEEP = C.from_workload("icr2d_chart_24to1284", depth=4, name="cg_chart_24to324")
+
+
+def test_fp32_gradient_on_a_32x32_charted_copy_matches_finite_differences():
+    """Central finite differences of the charted workload's likelihood energy
+    0.5 sum mask (d - s)^2 / sigma^2 + 0.5 |xi|^2 (sigma 0.1, 30 % masked) on a copy whose
+    output is 32 x 32, along random directions, against the autograd gradient (FP32)."""
+    import torch
+    from paper_2402_16683_amd.autograd import icr_sample
+    plan = C.gpu_plan(CHART_32)
+    n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
+    assert plan.info["level_shapes"][-1] == (32, 32)
+    mask = torch.from_numpy(W.bernoulli_mask(n_out, 0.7, seed=4)).float().cuda()
+    truth = torch.from_numpy(W.standard_normal(n_xi, seed=2, batch=1)).float().cuda()
+    noise = 0.1 * torch.from_numpy(W.standard_normal(n_out, seed=3, batch=1)).float().cuda()
+    data = mask * icr_sample(plan, truth).detach() + noise
+
+    def loss(xi):
+        s = icr_sample(plan, xi)
+        r = (mask * (data - s)).double()
+        return 0.5 * (r * r).sum() / 0.01 + 0.5 * (xi.double() ** 2).sum()
+
+    xi0 = torch.from_numpy(W.standard_normal(n_xi, seed=5, batch=1)).float().cuda().requires_grad_(True)
+    loss(xi0).backward()
+    grad = xi0.grad.double()
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        d = torch.from_numpy(rng.standard_normal((1, n_xi))).float().cuda()
+        d /= d.norm()
+        h = 1e-2
+        with torch.no_grad():
+            fd = (loss(xi0 + h * d) - loss(xi0 - h * d)) / (2 * h)
+        an = (grad * d.double()).sum()
+        assert abs(float(fd - an)) <= 1e-3 * max(1.0, abs(float(an))), (float(fd), float(an))
+
+
+def _workload_problem(case, precision, sigma_n=0.1):
+    """The charted workload's data and right-hand side b = L^T W d (truth seed 2, noise
+    seed 3, 70 % observed by a Bernoulli mask of seed 4), from the oracle."""
+    plan = C.gpu_plan(case, precision)
+    model = C.oracle_model(case)
+    n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
+    mask = W.bernoulli_mask(n_out, 0.7, seed=4)
+    w = mask / sigma_n ** 2
+    data = mask * model.forward(W.standard_normal(n_xi, seed=2)) + sigma_n * W.standard_normal(n_out, seed=3)
+    b = model.adjoint(w * data)[None]
+    return plan, model, w, b
+
+
+def test_cg_iterates_on_a_deeper_chart_match_textbook_cg():
+    """As the depth-1 comparison above, on the chart refined four times (24^2 -> 324^2):
+    the first iterates to 1e-10 and the CG energy after 200 iterations to 1e-7."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan, model, w, b = _workload_problem(CHART_DEEP, "f64")
+    C.upload_oracle_matrices(plan, model)
+    energy = lambda x: 0.5 * x @ model.metric(w, x) - b[0] @ x
+    for k in (1, 4, 200):
+        x = B.icr_cg_metric(plan, torch.from_numpy(w).cuda(), C.to_device(b, plan), k)
+        torch.cuda.synchronize()
+        ref, _ = _textbook_cg(lambda v: model.metric(w, v), b[0], k)
+        got = C.to_numpy(x)[0]
+        if k <= 4:
+            rms, _ = C.rel_errors(got, ref)
+            assert rms <= 1e-10, (k, rms)
+        e_got, e_ref = energy(got), energy(ref)
+        assert abs(e_got - e_ref) <= (1e-12 if k <= 4 else 1e-7) * abs(e_ref), (k, e_got, e_ref)
+
+
+def test_fp32_cg_on_the_full_charted_workload_tracks_fp64():
+    """200 CG iterations (metric products) on the charted workload at its stated size
+    (24^2 -> 1284^2, sigma_n 0.1): the FP32 plan's residual reduction is within 10x of the
+    FP64 plan's, and so is the true residual |b - M x| / |b| of its solution evaluated by
+    the FP64 oracle. (The metric has cond ~1e4; both precisions reduce the residual
+    by ~3e-3 in 200 steps.)"""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan64, model, w, b = _workload_problem(CHART_FULL, "f64")
+    plan32 = C.gpu_plan(CHART_FULL, "f32")
+    x64, n64 = B.icr_cg_metric(plan64, torch.from_numpy(w).cuda(), C.to_device(b, plan64), 200, residual_norms=True)
+    x32, n32 = B.icr_cg_metric(plan32, torch.from_numpy(w).float().cuda(), C.to_device(b, plan32), 200,
+                               residual_norms=True)
+    torch.cuda.synchronize()
+    red64 = float(n64[0, -1] / n64[0, 0])
+    red32 = float(n32[0, -1] / n32[0, 0])
+    true32 = np.linalg.norm(b[0] - model.metric(w, C.to_numpy(x32)[0])) / np.linalg.norm(b[0])
+    print(f"[errors] charted CG 200 steps: |r|/|r0| FP64 {red64:.2e}, FP32 {red32:.2e}, FP32 true {true32:.2e}")
+    assert red64 < 1e-1
+    assert red32 <= 10 * red64 and true32 <= 10 * red64
+
+
+def test_cg_energy_rule_matches_the_oracle():
+    """icr_cg_metric_sl against the oracle's energy-change CG on identical matrices (FP64,
+    sigma_n 1 so that iterates are well-determined): two right-hand sides of different
+    size stop after different step counts, each equal to the oracle's; the solutions agree;
+    a stopped sample's residual norm is repeated to the end."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan, model, w, _ = _workload_problem(CHART, "f64", sigma_n=1.0)
+    C.upload_oracle_matrices(plan, model)
+    n_xi = plan.info["n_xi"]
+    b0 = W.standard_normal(n_xi, seed=7)
+    b = np.stack([b0, 5.0 * b0 + W.standard_normal(n_xi, seed=8)])
+    apply = lambda v: model.metric(w, v)
+    maxiter = 80
+    absdelta = 1e-4 * n_xi / 10.0            # the paper's example: 1e-4 * size / 10
+    refs = [O.conjugate_gradient_sl(apply, bk, absdelta, maxiter) for bk in b]
+    for _, steps, dec in refs:                # no decrease sits on the threshold
+        assert steps < maxiter and np.min(np.abs(dec / absdelta - 1.0)) > 1e-6
+    assert refs[0][1] != refs[1][1]
+    done = torch.zeros(2, dtype=torch.int32, device="cuda")
+    x, norms = B.icr_cg_metric(plan, torch.from_numpy(w).cuda(), C.to_device(b, plan), maxiter,
+                               residual_norms=True, absdelta=absdelta, iterations_done=done)
+    torch.cuda.synchronize()
+    got_steps = done.cpu().numpy()
+    nr = norms.cpu().numpy()
+    for k, (xr, steps, _) in enumerate(refs):
+        assert got_steps[k] == steps, (k, got_steps[k], steps)
+        rms, _ = C.rel_errors(C.to_numpy(x)[k], xr)
+        assert rms <= 1e-9, (k, rms)
+        assert np.all(nr[k, steps:] == nr[k, steps])
+
+
+def test_cg_energy_rule_halts_the_remaining_kernels():
+    """On the full charted workload (FP32) a threshold reached early stops CG on the
+    device: the result equals a fixed-count run of that many steps bit for bit, and the
+    call takes far less time than the fixed-count run to the limit (the remaining sweep
+    kernels return at once)."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan, model, w, b = _workload_problem(CHART_FULL, "f32")
+    wd = torch.from_numpy(w).float().cuda()
+    bd = C.to_device(b, plan)
+    mb = model.metric(w, C.stored_values(b[0], "f32"))
+    bs = C.stored_values(b[0], "f32")
+    first = 0.5 * (bs @ bs) ** 2 / (bs @ mb)   # the first step's energy decrease
+    absdelta = 1e-3 * first
+    ws = torch.empty(B.icr_cg_workspace_bytes(plan, 1), dtype=torch.uint8, device="cuda")
+    done = torch.zeros(1, dtype=torch.int32, device="cuda")
+    maxiter = 100
+    x_sl = B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws, absdelta=absdelta, iterations_done=done)
+    torch.cuda.synchronize()
+    steps = int(done.item())
+    assert 2 <= steps <= 60, steps
+    x_fix = B.icr_cg_metric(plan, wd, bd, steps, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(x_sl, x_fix)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    t_sl = timed(lambda: B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws, absdelta=absdelta))
+    t_fix = timed(lambda: B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws))
+    print(f"[timing] energy rule stopped after {steps} of {maxiter} steps: {t_sl:.2f} ms vs {t_fix:.2f} ms")
+    assert t_sl < 0.8 * t_fix

@@ -2,7 +2,8 @@
 FP64 oracle, level by level, on well-conditioned cases.
 
 Both sides get the same seeded inputs (the values the device stores, up-cast
-exactly for the oracle) and each builds its own matrices in FP64. Results are
+exactly for the oracle) and each builds its own matrices in FP64. Outputs and
+workspaces start as NaN, so a pixel a kernel never writes fails the comparison. Results are
 compared per level by rel-RMS and relative max error against the tolerance of
 the precision (FP32 1e-5, BF16 storage 1e-2 rel-RMS; FP64 1e-10, the agreement
 two FP64 builds of R = K_fc K_cc^-1 can reach at cond(K_cc) ~ 1e5).
@@ -38,6 +39,9 @@ CASES = [
     C.case(2, (8, 9), 4, (0.04, 0.03), "matern32", 0.2, batch=2, precision="bf16", name="2d_ragged_m32_bf16"),
     C.case(1, (7,), 4, (0.1,), "sqexp", 0.4, batch=4, name="1d_se_f32"),
     C.from_workload("icr2d_chart_24to1284", depth=3, name="2d_chart_24to164_f32"),
+    # the charted workload at its stated size, 24^2 -> 1284^2 over six levels
+    C.from_workload("icr2d_chart_24to1284", name="2d_chart_full_f32"),
+    C.from_workload("icr2d_chart_24to1284", precision="bf16", batch=2, name="2d_chart_full_b2_bf16"),
     C.from_workload("icr2d_chart_24to1284", depth=2, precision="f64", name="2d_chart_24to84_f64"),
     # 2-D chart, one set per radial shell: the 2-D fast kernels read a row per coarse row;
     # an odd row length at level 0 sends that level to the generic kernels
@@ -80,7 +84,7 @@ def test_forward_matches_oracle_per_level(c):
     xi_dev = C.to_device(xi, plan)
     ws = torch.full((B, max(info["workspace_elems"], 1)), float("nan"), dtype=plan.dtype, device="cuda")
     from paper_2402_16683_amd import icr as Bd
-    s = Bd.icr_forward(plan, xi_dev, workspace=ws)
+    s = Bd.icr_forward(plan, xi_dev, s=C.nan_like((B, info["n_out"]), plan), workspace=ws)
     torch.cuda.synchronize()
     _, ref_levels = model.forward(C.stored_values(xi, c["precision"]), return_levels=True)
     got_levels = _levels(C.to_numpy(ws), info, c["depth"]) + [C.to_numpy(s)]
@@ -105,11 +109,11 @@ def test_adjoint_matches_oracle_per_level(c):
     y = W.standard_normal(info["n_out"], seed=1, batch=B)
     ws = torch.full((B, max(info["workspace_elems"], 1)), float("nan"), dtype=plan.dtype, device="cuda")
     from paper_2402_16683_amd import icr as Bd
-    xib = Bd.icr_adjoint(plan, C.to_device(y, plan), workspace=ws)
+    xib = Bd.icr_adjoint(plan, C.to_device(y, plan), xi_bar=C.nan_like((B, info["n_xi"]), plan), workspace=ws)
     torch.cuda.synchronize()
     ref, ref_cot = model.adjoint(C.stored_values(y, c["precision"]), return_levels=True)
     got = C.to_numpy(xib)
-    assert np.all(np.isfinite(got))
+    assert np.all(np.isfinite(got)), "xi_bar has unwritten/non-finite values"
     tol_rms, tol_max = C.TOL[c["precision"]]
     offs = info["level_offsets"]
     for l in range(c["depth"] + 1):
@@ -133,9 +137,12 @@ def test_metric_matches_oracle(c):
     w = mask / 0.1 ** 2
     from paper_2402_16683_amd import icr as Bd
     w_dev = torch.from_numpy(w).to(device="cuda", dtype=plan.acc_dtype)
-    out = Bd.icr_metric_apply(plan, w_dev, C.to_device(v, plan))
+    ws = C.nan_like((B, info["metric_workspace_elems"]), plan)
+    out = Bd.icr_metric_apply(plan, w_dev, C.to_device(v, plan), out=C.nan_like((B, info["n_xi"]), plan),
+                              workspace=ws)
     torch.cuda.synchronize()
     ref = model.metric(w, C.stored_values(v, c["precision"]))
+    assert np.all(np.isfinite(C.to_numpy(out))), "metric output has unwritten/non-finite values"
     rms, mx = C.rel_errors(C.to_numpy(out), ref)
     tol_rms, tol_max = C.TOL[c["precision"]]
     assert rms <= tol_rms and mx <= tol_max, f"rel-RMS {rms:.3g}, rel-max {mx:.3g}"

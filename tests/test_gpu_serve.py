@@ -93,6 +93,39 @@ def test_results_in_the_mix_equal_results_alone(graphs):
     server.close()
 
 
+@pytest.mark.parametrize("graphs", [True, False])
+def test_served_results_match_the_oracle(graphs):
+    """Every served request (batched, several streams, graphs or not) against the FP64
+    oracle of its prior on the values the device holds, at the precision's tolerance."""
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    models = [C.oracle_model(c) for c in POOL]
+    server = Server(hbm_budget_bytes=1 << 30, max_batch=8, n_streams=4, use_graphs=graphs)
+    reqs = _requests(plans, 120, seed=11)
+    info = _serve(server, plans, reqs)
+    assert all(q[0] for q in info)
+    torch.cuda.synchronize()
+    seen = set()
+    for r in reqs:
+        c, m = POOL[r["k"]], models[r["k"]]
+        inp = C.to_numpy(r["inp"])
+        if r["op"] == "forward":
+            ref = m.forward(inp)
+        elif r["op"] == "adjoint":
+            ref = m.adjoint(inp)
+        else:
+            ref = m.metric(C.to_numpy(r["w"]), inp)
+        got = C.to_numpy(r["out"])
+        assert np.all(np.isfinite(got)), (r["k"], r["op"])
+        rms, mx = C.rel_errors(got, ref)
+        tol_rms, tol_max = C.TOL[c["precision"]]
+        assert rms <= tol_rms and mx <= tol_max, (c["name"], r["op"], rms, mx)
+        seen.add((r["k"], r["op"]))
+    assert len(seen) == 3 * len(POOL)          # every prior with every op
+    server.close()
+
+
 def test_admission_under_a_tight_budget():
     import torch
     from paper_2402_16683_amd.serve import Server

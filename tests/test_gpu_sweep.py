@@ -18,6 +18,13 @@ CASES = [
     C.case(1, (7,), 6, (0.1,), "sqexp", 0.4, batch=4, name="1d_se_deep_f32"),
     C.from_workload("icr2d_se_16to1540_b16", batch=2, name="2d_se_full_b2_f32"),
     C.from_workload("icr2d_se_16to1540_b16", batch=2, precision="bf16", name="2d_se_full_b2_bf16"),
+    # the 2-D workload at its benchmarked batch of 16: the 2-D kernels size their row marches
+    # by the batch, so the last two levels march 6 and 2 rows per wavefront (batch <= 3
+    # gives one row per wavefront at every level)
+    C.from_workload("icr2d_se_16to1540_b16", name="2d_se_full_b16_f32"),
+    C.from_workload("icr2d_se_16to1540_b16", precision="bf16", name="2d_se_full_b16_bf16"),
+    # a large batch of small grids: marches of 2 to 7 rows with a ragged last chunk
+    C.from_workload("icr2d_se_16to1540_b16", depth=4, batch=1024, name="2d_se_16to196_b1024_f32"),
     C.from_workload("icr2d_se_16to1540_b16", depth=5, precision="f64", name="2d_se_16to388_f64"),
     C.from_workload("icr3d_m52_10to388", depth=4, batch=2, name="3d_m52_10to100_b2_f32"),
     C.from_workload("icr3d_m52_10to388", depth=4, precision="bf16", name="3d_m52_10to100_bf16"),
@@ -57,7 +64,7 @@ def test_sweep_forward_with_identical_matrices(c):
     xi = W.standard_normal(info["n_xi"], seed=0, batch=c["batch"])
     ws = torch.full((c["batch"], max(info["workspace_elems"], 1)), float("nan"), dtype=plan.dtype,
                     device="cuda")
-    s = Bd.icr_forward(plan, C.to_device(xi, plan), workspace=ws)
+    s = Bd.icr_forward(plan, C.to_device(xi, plan), s=C.nan_like((c["batch"], info["n_out"]), plan), workspace=ws)
     torch.cuda.synchronize()
     _, ref = model.forward(C.stored_values(xi, c["precision"]), return_levels=True)
     got = C.level_views(C.to_numpy(ws), info["level_offsets"], c["depth"]) + [C.to_numpy(s)]
@@ -73,7 +80,8 @@ def test_sweep_adjoint_with_identical_matrices(c):
     y = W.standard_normal(info["n_out"], seed=1, batch=c["batch"])
     ws = torch.full((c["batch"], max(info["workspace_elems"], 1)), float("nan"), dtype=plan.dtype,
                     device="cuda")
-    xib = Bd.icr_adjoint(plan, C.to_device(y, plan), workspace=ws)
+    xib = Bd.icr_adjoint(plan, C.to_device(y, plan), xi_bar=C.nan_like((c["batch"], info["n_xi"]), plan),
+                         workspace=ws)
     torch.cuda.synchronize()
     ref, ref_cot = model.adjoint(C.stored_values(y, c["precision"]), return_levels=True)
     offs = info["level_offsets"]
@@ -91,8 +99,11 @@ def test_sweep_metric_with_identical_matrices(c):
     info = plan.info
     v = W.standard_normal(info["n_xi"], seed=2, batch=c["batch"])
     w = W.bernoulli_mask(info["n_out"], 0.7, seed=4) / 0.1 ** 2
-    out = Bd.icr_metric_apply(plan, torch.from_numpy(w).to("cuda", plan.acc_dtype), C.to_device(v, plan))
+    out = Bd.icr_metric_apply(plan, torch.from_numpy(w).to("cuda", plan.acc_dtype), C.to_device(v, plan),
+                              out=C.nan_like((c["batch"], info["n_xi"]), plan),
+                              workspace=C.nan_like((c["batch"], info["metric_workspace_elems"]), plan))
     torch.cuda.synchronize()
+    assert np.all(np.isfinite(C.to_numpy(out))), "metric output has unwritten/non-finite values"
     ref = model.metric(w, C.stored_values(v, c["precision"]))
     rms, mx = C.rel_errors(C.to_numpy(out), ref)
     tol_rms, tol_max = C.TOL[c["precision"]]

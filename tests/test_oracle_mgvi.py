@@ -62,3 +62,39 @@ def test_one_newton_step_reaches_the_posterior_mean():
     np.testing.assert_allclose(b, lmat.T @ (w * d), rtol=1e-10, atol=1e-10)
     mean = O.mgvi_newton_step(m, w, b, rng.standard_normal(m.n_xi), 400)
     np.testing.assert_allclose(mean, np.linalg.solve(mmat, lmat.T @ (w * d)), rtol=1e-8, atol=1e-9)
+
+
+def test_energy_stopping_rule_against_dense_energies():
+    """The energy-change rule: the energies the oracle evaluates equal x.Mx/2 - b.x with
+    the dense M; a step's decrease equals alpha (r.r) / 2 (exact line search, the form
+    the device uses); the rule stops at the first step whose decrease is below absdelta
+    and the iterate is the plain CG iterate after that many steps."""
+    m, rng, w, lmat, mmat = _setup()
+    b = rng.standard_normal(m.n_xi)
+    apply = lambda v: m.metric(w, v)
+    n = 20
+    _, steps, dec_all = O.conjugate_gradient_sl(apply, b, 0.0, n)
+    assert steps == n and np.all(dec_all > 0)          # without a threshold: the limit
+    energies = []
+    for k in range(n + 1):
+        xk = O.conjugate_gradient(apply, b, k)
+        energies.append(0.5 * xk @ mmat @ xk - b @ xk)
+    np.testing.assert_allclose(dec_all, -np.diff(energies), rtol=1e-7, atol=1e-12 * abs(energies[-1]))
+    # closed form of a step's decrease
+    x, r, p, rr = np.zeros_like(b), b.copy(), b.copy(), b @ b
+    for k in range(10):
+        q = mmat @ p
+        alpha = rr / (p @ q)
+        np.testing.assert_allclose(dec_all[k], 0.5 * alpha * rr, rtol=1e-7)
+        x, r = x + alpha * p, r - alpha * q
+        p, rr = r + (r @ r / rr) * p, r @ r
+    # thresholds between the decreases: the rule stops after the first step below it
+    for absdelta in (0.5 * dec_all[:6].min(), 0.9 * dec_all[:10].min(), 2.0 * dec_all[-1]):
+        expect = next(k for k in range(n) if dec_all[k] < absdelta) + 1
+        assert 1 < expect <= n
+        x_sl, steps, _ = O.conjugate_gradient_sl(apply, b, absdelta, n)
+        assert steps == expect
+        np.testing.assert_allclose(x_sl, O.conjugate_gradient(apply, b, steps), rtol=1e-12, atol=1e-14)
+    # a threshold above the first decrease stops after one step; the limit caps the steps
+    assert O.conjugate_gradient_sl(apply, b, 2.0 * dec_all[0], n)[1] == 1
+    assert O.conjugate_gradient_sl(apply, b, 1e-300, 5)[1] == 5
