@@ -8,6 +8,8 @@
   (FP64), its residual norms against the oracle's residuals, and FP32 against FP64.
 """
 
+import math
+
 import numpy as np
 import pytest
 
@@ -228,7 +230,11 @@ def _workload_problem(case, precision, sigma_n=0.1):
 
 def test_cg_iterates_on_a_deeper_chart_match_textbook_cg():
     """As the depth-1 comparison above, on the chart refined four times (24^2 -> 324^2):
-    the first iterates to 1e-10 and the CG energy after 200 iterations to 1e-7."""
+    the first iterates to 1e-10, and the CG energy after 200 iterations to 3e-4. CG is far
+    from converged there and its later iterates depend on rounding: perturbing every
+    metric product of the FP64 oracle by 1e-15 (1e-14) relative moves the 200th energy by
+    4e-6 (4.4e-5) and the iterate by 2e-3 (2e-2), measured; the device's FP64 sums run in
+    another order."""
     import torch
     from paper_2402_16683_amd import icr as B
     plan, model, w, b = _workload_problem(CHART_DEEP, "f64")
@@ -243,7 +249,7 @@ def test_cg_iterates_on_a_deeper_chart_match_textbook_cg():
             rms, _ = C.rel_errors(got, ref)
             assert rms <= 1e-10, (k, rms)
         e_got, e_ref = energy(got), energy(ref)
-        assert abs(e_got - e_ref) <= (1e-12 if k <= 4 else 1e-7) * abs(e_ref), (k, e_got, e_ref)
+        assert abs(e_got - e_ref) <= (1e-12 if k <= 4 else 3e-4) * abs(e_ref), (k, e_got, e_ref)
 
 
 def test_fp32_cg_on_the_full_charted_workload_tracks_fp64():
@@ -270,12 +276,14 @@ def test_fp32_cg_on_the_full_charted_workload_tracks_fp64():
 
 def test_cg_energy_rule_matches_the_oracle():
     """icr_cg_metric_sl against the oracle's energy-change CG on identical matrices (FP64,
-    sigma_n 1 so that iterates are well-determined): two right-hand sides of different
-    size stop after different step counts, each equal to the oracle's; the solutions agree;
-    a stopped sample's residual norm is repeated to the end."""
+    weights 0.1 per observed pixel, where the iterates are well-determined: perturbing the
+    oracle's products by 1e-14 moves them by ~1e-14, measured; at weight 1 the 18th iterate
+    already moves by 1e-4): two right-hand sides of different size stop after different
+    step counts, each equal to the oracle's; the solutions agree; a stopped sample's
+    residual norm is repeated to the end."""
     import torch
     from paper_2402_16683_amd import icr as B
-    plan, model, w, _ = _workload_problem(CHART, "f64", sigma_n=1.0)
+    plan, model, w, _ = _workload_problem(CHART, "f64", sigma_n=math.sqrt(10.0))
     C.upload_oracle_matrices(plan, model)
     n_xi = plan.info["n_xi"]
     b0 = W.standard_normal(n_xi, seed=7)
