@@ -210,6 +210,19 @@ icr_status icr_metric_apply(const icr_plan* plan, int64_t batch, const void* w,
                             void* workspace, void* hip_stream);
 
 /*
+ * icr_metric_apply for callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same computation with no workspace
+ * argument. Its workspace is a static device array of the library, 64 MiB on every GPU
+ * the library runs on, held until the process ends; the call allocates nothing.
+ *   w, w_batch_stride, v, out as for icr_metric_apply (v and out must not overlap).
+ * Returns ICR_ERR_INVALID_ARG, launching nothing, when batch * n_xi * elem_bytes exceeds
+ * 64 MiB. All calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different streams or threads) race and give wrong results; serialise them.
+ */
+icr_status icr_metric_apply_static(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
+                                   const void* v, void* out, void* hip_stream);
+
+/*
  * Gradient of E = <s_bar, L(theta) xi> with respect to the kernel hyperparameters
  * theta = (scale sigma, length), per sample, from the results of one icr_forward and
  * one icr_adjoint (the paper learns kernel parameters by differentiating the model,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -281,6 +282,33 @@ icr_status refresh_host_copies(icr_plan* p, int level) {
     if (r != ICR_OK) return r;
     m.dsector_ok = ok(asym);
   }
+  return ICR_OK;
+}
+
+// Device scratch of icr_metric_apply_static: a file-scope array every GPU the library runs
+// on holds until the process ends (64 MiB each). Host code never uses the array's name as
+// an address: each device's copy sits at its own device address, looked up once per device
+// with hipGetSymbolAddress and kept in scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (looked up on the first call on that device).
+icr_status scratch_ptr(void** out) {
+  int dev = 0;
+  ICR_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ICR_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    ICR_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(ICR_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return ICR_OK;
 }
 
@@ -624,6 +652,35 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   if (r != ICR_OK) return r;
   return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
                      v, st);
+}
+
+icr_status icr_metric_apply_static(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
+                                   const void* v, void* out, void* hip_stream) {
+  icr::clear_error();
+  icr_status cs = check_call(p, batch);
+  if (cs != ICR_OK || batch == 0) return cs;
+  const int el = p->elem_bytes;
+  const int ab = acc_bytes_of(p->precision);
+  const size_t need = size_t(batch) * size_t(p->n_xi) * el;
+  if (need > kStaticScratchBytes)
+    return fail(ICR_ERR_INVALID_ARG, "the metric needs " + std::to_string(need) + " bytes of workspace; the static "
+                "scratch holds " + std::to_string(kStaticScratchBytes) + " (use icr_metric_apply)");
+  if (!w || !v || !out) return fail(ICR_ERR_INVALID_ARG, "NULL buffer");
+  if (w_batch_stride != 0 && w_batch_stride < p->n_out)
+    return fail(ICR_ERR_INVALID_ARG, "w_batch_stride must be 0 or >= n_out");
+  if (!aligned(v, el) || !aligned(out, el) || !aligned(w, ab))
+    return fail(ICR_ERR_INVALID_ARG, "buffer not aligned to its element size");
+  if (icr::overlaps(v, need, out, need)) return fail(ICR_ERR_INVALID_ARG, "v and out overlap");
+  void* ws = nullptr;
+  cs = scratch_ptr(&ws);
+  if (cs != ICR_OK) return cs;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t ws_bs = p->n_xi;
+  // the same sweep as icr_metric_apply, its workspace in the scratch array: every element
+  // it reads there is written earlier in the same call, so nothing needs clearing
+  icr_status r = run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), ws_bs, ws, ws_bs, w, w_batch_stride, st);
+  if (r != ICR_OK) return r;
+  return run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), ws_bs, out, ws, ws_bs, v, st);
 }
 
 icr_status icr_hyper_grad(const icr_plan* p, int64_t batch, const void* xi, const void* s,

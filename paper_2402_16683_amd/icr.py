@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "icr_forward": [vp, i64, vp, vp, vp, vp],
         "icr_adjoint": [vp, i64, vp, vp, vp, vp],
         "icr_metric_apply": [vp, i64, vp, i64, vp, vp, vp, vp],
+        "icr_metric_apply_static": [vp, i64, vp, i64, vp, vp, vp],
         "icr_forward_level": [vp, i32, i64, vp, i64, vp, i64, vp, i64, vp],
         "icr_cg_workspace_bytes": [vp, i64, ctypes.POINTER(i64)],
         "icr_cg_metric": [vp, i64, vp, i64, vp, vp, i32, vp, vp, vp],
@@ -343,6 +344,20 @@ def icr_metric_apply(plan: Plan, w, v, out=None, workspace=None, stream=None):
     _check_numel(workspace, plan, "workspace", batch * plan.info["metric_workspace_elems"])
     _check(load_library().icr_metric_apply(plan.handle, batch, w.data_ptr(), w_stride, v.data_ptr(),
                                            out.data_ptr(), workspace.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def icr_metric_apply_static(plan: Plan, w, v, out=None, stream=None):
+    """icr_metric_apply with the library's static device scratch as its workspace (no
+    allocation in the library; at most 64 MiB of workspace: batch * n_xi elements)."""
+    batch = _batch_of(v, plan.info["n_xi"])
+    _check_tensor(v, plan, "v")
+    w_stride = _weights(plan, w, batch)
+    if out is None:
+        out = _empty(v.shape, plan)
+    _check_tensor(out, plan, "out", shape=tuple(v.shape))
+    _check(load_library().icr_metric_apply_static(plan.handle, batch, w.data_ptr(), w_stride, v.data_ptr(),
+                                                  out.data_ptr(), _stream_handle(stream)))
     return out
 
 
