@@ -179,74 +179,77 @@ def cpu_baseline_parallel(key: str, workers: int, quiet: bool) -> dict:
 
 
 def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
-    """Mixed 1-D/2-D/3-D forward/adjoint/metric requests on a pool of priors: the
-    one-launch-per-request capacity first, then Poisson streams at 0.5, 0.8 and 1.2x that
-    rate through the served form (continuous batching, hipGraphs, 8 streams, 8 GB
-    arena) and through the plain form; at 0.8x also the served form under a 256 MB arena
-    and without graphs; the served forms back to back for their saturated rates."""
+    """Mixed 1-D/2-D/3-D forward/adjoint/metric requests over a pool of priors with random
+    length scales, submitted by prior configuration: every server starts with an empty
+    plan cache and builds each prior's plan when its first request arrives (inside that
+    request's latency). First the one-launch-per-request capacity (warm cache, back to
+    back), then Poisson streams at 0.5, 0.8 and 1.2x that rate through the grouped served
+    form (requests of any prior and op share launches, 8 GB arena), the homogeneous
+    batched form (same prior and op only, hipGraphs) and the plain form; at 0.8x also the
+    grouped form under a 256 MB arena; the forms back to back for their saturated rates."""
     import torch
 
     from paper_2402_16683_amd import serve as S
     budget = 8 << 30
     priors = S.draw_priors(n_priors, seed=5)
-    t0 = time.perf_counter()
-    plans, pool = S.build_pool(priors, slots=8)
-    build_s = time.perf_counter() - t0
-    log(f"served: {n_priors} priors built in {build_s:.1f} s", quiet)
-    base = S.draw_stream(n_requests, n_priors, rate=0.0, seed=6)
-    plain = S.Server(budget, max_batch=1, n_streams=1, use_graphs=False)
-    pid = S.register_all(plain, plans)
-    S.run_stream(plain, pid, pool, S.draw_stream(min(200, n_requests), n_priors, 0.0, seed=7), pace=False)
-    _, _, wall = S.run_stream(plain, pid, pool, base, pace=False)
-    capacity = n_requests / wall
-    out = {"requests": n_requests, "priors": n_priors, "plain_capacity_req_per_s": capacity,
-           "hbm_budget_bytes": budget, "build_s": build_s}
-    servers = {"served": S.Server(budget, max_batch=16, n_streams=8, use_graphs=True), "plain": plain,
-               "served_256MB": S.Server(256 << 20, max_batch=16, n_streams=8, use_graphs=True),
-               "served_eager": S.Server(budget, max_batch=16, n_streams=8, use_graphs=False)}
-    ids = {"plain": pid}
-    for name in ("served", "served_256MB", "served_eager"):   # capture graphs before timing
-        ids[name] = S.register_all(servers[name], plans)
-        S.run_stream(servers[name], ids[name], pool, S.draw_stream(min(500, n_requests), n_priors, 0.0, seed=8),
-                     pace=False)
+    configs = [pr.config() for pr in priors]
+    _, pool = S.build_pool(priors, slots=8, plans=False)
+    kinds = {"served": dict(max_batch=16, n_streams=8, use_graphs=False, grouped=True, group_streams=2),
+             "served_homogeneous": dict(max_batch=16, n_streams=8, use_graphs=True),
+             "plain": dict(max_batch=1, n_streams=1, use_graphs=False)}
 
-    def one(name, stream):
-        srv = servers[name]
-        before = srv.stats()
-        lat, bs, wall = S.run_stream(srv, ids[name], pool, stream)
+    def fresh(name, hbm=budget):
+        return S.Server(hbm, **kinds[name])
+
+    base = S.draw_stream(n_requests, n_priors, rate=0.0, seed=6)
+    plain = fresh("plain")
+    t0 = time.perf_counter()
+    S.run_stream(plain, configs, pool, S.draw_stream(min(200, n_requests), n_priors, 0.0, seed=7), pace=False)
+    _, _, wall = S.run_stream(plain, configs, pool, S.draw_stream(4 * n_priors, n_priors, 0.0, seed=9), pace=False)
+    build_s = time.perf_counter() - t0
+    _, _, wall = S.run_stream(plain, configs, pool, base, pace=False)
+    capacity = n_requests / wall
+    st = plain.stats()
+    plain.close()
+    out = {"requests": n_requests, "priors": n_priors, "plain_capacity_req_per_s": capacity,
+           "hbm_budget_bytes": budget, "warmup_s_with_builds": build_s, "plans_built_per_server": st["plans_built"],
+           "priors_by_dim": {str(d): sum(pr.ndim == d for pr in priors) for d in (1, 2, 3)}}
+
+    def one(name, stream, rate, hbm=budget):
+        srv = fresh(name, hbm)
+        lat, bs, wall = S.run_stream(srv, configs, pool, stream)
         st = srv.stats()
+        srv.close()
         ok = ~np.isnan(lat)
         r = {"p50_ms": float(np.percentile(lat[ok], 50) * 1e3), "p99_ms": float(np.percentile(lat[ok], 99) * 1e3),
-             "fine_px_per_s": S.fine_pixels(plans, stream, ok) / wall, "requests_per_s": int(ok.sum()) / wall,
-             "mean_batch": float(bs[ok].mean()), "launches": st["batches"] - before["batches"],
-             "admissions_deferred": st["admissions_deferred"] - before["admissions_deferred"],
-             "refused": int((~ok).sum())}
-        log(f"served: {name} at {stream_rate:.0f} req/s: p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms "
-            f"{r['fine_px_per_s']:.3g} px/s, mean batch {r['mean_batch']:.2f}", quiet)
+             "fine_px_per_s": S.fine_pixels(priors, stream, ok) / wall, "requests_per_s": int(ok.sum()) / wall,
+             "mean_batch": float(bs[ok].mean()), "launch_sequences": st["batches"] + st["groups"],
+             "grouped_requests": st["grouped_requests"], "plans_built": st["plans_built"],
+             "admissions_deferred": st["admissions_deferred"], "refused": int((~ok).sum())}
+        log(f"served: {name} at {rate:.0f} req/s: p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms "
+            f"{r['fine_px_per_s']:.3g} px/s, mean batch {r['mean_batch']:.2f}, grouped {r['grouped_requests']}", quiet)
         return r
 
     out["rates"] = []
     for factor in (0.5, 0.8, 1.2):
-        stream_rate = factor * capacity
-        stream = S.draw_stream(n_requests, n_priors, rate=stream_rate, seed=6)
-        row = {"factor": factor, "arrival_rate_req_per_s": stream_rate,
-               "served": one("served", stream), "plain": one("plain", stream)}
+        rate = factor * capacity
+        stream = S.draw_stream(n_requests, n_priors, rate=rate, seed=6)
+        row = {"factor": factor, "arrival_rate_req_per_s": rate}
+        for name in ("served", "served_homogeneous", "plain"):
+            row[name] = one(name, stream, rate)
         if factor == 0.8:
-            row["served_256MB"] = one("served_256MB", stream)
-            row["served_eager"] = one("served_eager", stream)
-            out.update({"arrival_rate_req_per_s": stream_rate, "served": row["served"], "plain": row["plain"],
-                        "served_256MB": row["served_256MB"], "served_eager": row["served_eager"]})
+            row["served_256MB"] = one("served", stream, rate, hbm=256 << 20)
+            out.update({"arrival_rate_req_per_s": rate, "served": row["served"], "plain": row["plain"],
+                        "served_homogeneous": row["served_homogeneous"], "served_256MB": row["served_256MB"]})
         out["rates"].append(row)
-    # saturation: the stream back to back
-    sat = servers["served"]
-    _, bs, wall = S.run_stream(sat, ids["served"], pool, base, pace=False)
-    out["served_saturated_req_per_s"] = n_requests / wall
-    out["graph_captures"] = sat.stats()["graph_captures"]
-    _, _, wall = S.run_stream(servers["served_eager"], ids["served_eager"], pool, base, pace=False)
-    out["served_eager_saturated_req_per_s"] = n_requests / wall
-    for srv in servers.values():
+    # saturation: the stream back to back (cold caches: builds included)
+    for name in ("served", "served_homogeneous"):
+        srv = fresh(name)
+        _, bs, wall = S.run_stream(srv, configs, pool, base, pace=False)
+        out[f"{name}_saturated_req_per_s"] = n_requests / wall
+        out[f"{name}_saturated_mean_batch"] = float(bs.mean())
         srv.close()
-    del plans, pool
+    del pool
     torch.cuda.empty_cache()
     return out
 

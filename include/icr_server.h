@@ -2,26 +2,37 @@
  * icr_server.h - served ICR: continuous batching of forward / adjoint / metric requests
  * on one GPU (the serving mode of the ICR library declared in icr.h).
  *
- * Requests against registered plans are queued; a worker thread groups pending requests
- * with the same (plan, op), oldest first, into batches of a power of two up to max_batch,
- * admits a batch only when its device buffers fit in the server's fixed HBM arena
- * (first fit), and launches it on a free stream: gather the requests' inputs into a
- * contiguous batch, run the batched sweep (a hipGraph captured once per (plan, op, batch
- * size) when use_graphs is set and the batch needs at most 1/32 of the arena; larger
- * batches, whose launch overhead is small against their run time, launch eagerly),
- * scatter the outputs, record a completion event (a single request without a graph
- * runs the sweep on its own buffers, only its workspace taken from the arena). Requests
- * that arrive while others run are admitted as streams and memory free up, so batches of
- * different priors overlap on the device. max_batch = 1, n_streams = 1, use_graphs = 0 is
- * the one-launch-per-request baseline.
+ * Requests against registered plans (or against prior configurations, whose plans the
+ * server builds on first use and caches) are queued, and a worker thread launches them:
+ *  - grouped mode (cfg.grouped): requests of ANY prior (1-D, 2-D, 3-D, any level sizes,
+ *    depth, matrices and precision) and any op are grouped, oldest first, up to
+ *    max_batch: the k-th launch of a group applies the k-th step of every request's sweep
+ *    (level 0 or one refinement level, forward or adjoint) from a device table of steps,
+ *    one table copy per group. A request is admitted when its workspace fits the arena;
+ *    its own completion event follows its last step. At most group_streams groups run at
+ *    once, so requests that arrive while groups run are gathered into the next one. A
+ *    request with a refinement level of at least large_step fine pixels (bandwidth-bound,
+ *    not launch-bound) runs as below instead, with the specialised kernels.
+ *  - homogeneous batches: pending requests with the same (plan, op), oldest first, in
+ *    batches of a power of two up to max_batch, admitted when the batch's buffers fit the
+ *    arena (first fit): gather the inputs into a contiguous batch, run the batched sweep (a
+ *    hipGraph captured once per (plan, op, batch size) when use_graphs is set and the
+ *    batch needs at most 1/32 of the arena; larger batches launch eagerly), scatter the
+ *    outputs, record a completion event (a single request without a graph sweeps its own
+ *    buffers, only its workspace taken from the arena).
+ * Requests that arrive while others run are admitted as streams and memory free up, so
+ * work of different priors overlaps on the device. max_batch = 1, n_streams = 1,
+ * use_graphs = 0, grouped = 0 is the one-launch-per-request baseline.
  *
  * Conventions: as in icr.h (status codes, icr_last_error, caller-owned device buffers).
  * The server allocates its arena once at creation; nothing is allocated per request
- * except when a new graph is captured (from the arena). A request's buffers must stay
+ * except when a new graph is captured (from the arena) or a plan is built for a new
+ * prior configuration. A request's buffers must stay
  * valid and untouched until icr_server_query reports it done (see icr_server_submit for
  * the ordering with the caller's stream). Results are identical
- * whether a request runs alone or in a batch (each sample is computed by the same
- * kernels in the same order).
+ * whether a request runs alone or in a batch or group (each sample is computed by the
+ * same kernels in the same order; which path a request takes depends only on its prior
+ * and the server's configuration).
  */
 #ifndef ICR_SERVER_H
 #define ICR_SERVER_H
@@ -42,10 +53,14 @@ typedef enum icr_op {
 
 typedef struct icr_server_config {
   int64_t hbm_budget_bytes;  /* size of the arena batches and captured graphs live in */
-  int32_t max_batch;         /* 1..64 requests per launch */
-  int32_t n_streams;         /* 1..16 batches in flight at once */
-  int32_t use_graphs;        /* replay captured hipGraphs for the batched sweep */
-  int32_t reserved;          /* must be 0 */
+  int32_t max_batch;         /* 1..64 requests per launch (batch or group) */
+  int32_t n_streams;         /* 1..16 batches or groups in flight at once */
+  int32_t use_graphs;        /* replay captured hipGraphs for homogeneous batched sweeps */
+  int32_t grouped;           /* group requests of any prior and op (see above) */
+  int64_t large_step;        /* grouped mode: fine pixels of a refinement level from which a
+                                request runs on its own; 0 = 1048576 */
+  int32_t group_streams;     /* grouped mode: groups in flight at once, 1..n_streams; 0 = 1 */
+  int32_t max_plans;         /* prior configurations whose plans stay cached; 0 = 256 */
 } icr_server_config;
 
 typedef struct icr_server_statistics {
@@ -57,6 +72,10 @@ typedef struct icr_server_statistics {
   int64_t admissions_deferred; /* batches that had to wait for (or shrink to fit) memory */
   int64_t arena_bytes;
   int64_t arena_in_use;
+  int64_t groups;              /* grouped launches sequences (one per group) */
+  int64_t grouped_requests;    /* requests served in groups */
+  int64_t plans_built;         /* plans the server built for prior configurations */
+  int64_t plan_cache_hits;     /* submissions by configuration whose plan was cached or in build */
 } icr_server_statistics;
 
 typedef struct icr_server icr_server;
@@ -78,8 +97,22 @@ icr_status icr_server_register_plan(icr_server* server, const icr_plan* plan, in
 icr_status icr_server_submit(icr_server* server, int32_t plan_id, int32_t op, const void* in, void* out,
                              const void* w, void* hip_stream, int64_t* request_id);
 
+/*
+ * Queue one request against a prior configuration instead of a registered plan. The
+ * server keeps a cache of plans keyed by the whole configuration (dimension, level-0
+ * shape, depth, kernel, length scale, chart, precision, ...); on a miss a builder thread
+ * runs icr_build_matrices while the worker keeps serving other requests, and the
+ * request (and every later one for that configuration) starts once the plan is built:
+ * the build is part of its latency. The least recently used idle plans are destroyed
+ * beyond max_plans. If the build fails, icr_server_query reports the request done and
+ * returns the build's status. Other arguments as for icr_server_submit.
+ */
+icr_status icr_server_submit_prior(icr_server* server, const icr_config* cfg, int32_t op, const void* in,
+                                   void* out, const void* w, void* hip_stream, int64_t* request_id);
+
 /* State of a request; times are host steady-clock seconds (submit, launch of its batch,
- * observed completion). */
+ * observed completion). Returns the build status of a request whose prior's plan could
+ * not be built (with *done = 1). */
 icr_status icr_server_query(icr_server* server, int64_t request_id, int32_t* done, double* t_submit,
                             double* t_launch, double* t_done, int32_t* batch_size);
 

@@ -213,24 +213,27 @@ icr_status check_cg_call(const icr_plan* p, int64_t batch, const void* w, int64_
   return ICR_OK;
 }
 
-// Worst off-pattern / on-pattern ratio over a shell table's sets (device check array).
-icr_status shell_asymmetry(const double* dev_chk, int64_t nsets, double* worst) {
-  std::vector<double> chk(static_cast<size_t>(2 * nsets));
-  ICR_HIP_TRY(hipMemcpy(chk.data(), dev_chk, sizeof(double) * chk.size(), hipMemcpyDeviceToHost));
+// Host copies of a level's device results that the fast kernels need on the host:
+// staged by asynchronous copies on the build stream, used after one synchronisation.
+struct HostStage {
+  std::vector<double> chk, dchk;    // shell symmetry checks (value, derivative)
+  double sec[3 * 27], dsec[3 * 27]; // sector forms (value, derivative)
+  float hr[8 * 27], hs[8 * 8], hds[8 * 8];
+};
+
+// Worst off-pattern / on-pattern ratio over a shell table's sets (host copy of the check array).
+double shell_asymmetry(const std::vector<double>& chk, int64_t nsets) {
   double w = 0.0;
   for (int64_t s = 0; s < nsets; ++s) {
     const double off = chk[2 * s], on = chk[2 * s + 1];
     w = std::fmax(w, on > 0.0 ? off / on : 1.0);
     if (!std::isfinite(off) || !std::isfinite(on)) w = 1.0;
   }
-  *worst = w;
-  return ICR_OK;
+  return w;
 }
 
-// Sector coefficients (FP32) and the off / on-pattern ratio of a device sector array.
-icr_status sector_host(const double* dev_sector, int nw, float* coef, double* asym) {
-  double sec[3 * 27];
-  ICR_HIP_TRY(hipMemcpy(sec, dev_sector, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost));
+// Sector coefficients (FP32) and the off / on-pattern ratio of a host copy of a sector array.
+void sector_host(const double* sec, int nw, float* coef, double* asym) {
   double off = 0.0, on = 0.0;
   for (int t = 0; t < nw; ++t) {
     coef[t] = static_cast<float>(sec[t]);
@@ -238,50 +241,77 @@ icr_status sector_host(const double* dev_sector, int nw, float* coef, double* as
     on = std::fmax(on, sec[2 * nw + t]);
   }
   *asym = on > 0.0 ? off / on : 1.0;
-  return ICR_OK;
 }
 
-// Host copies of a stationary level's FP32 matrices and its sector form (the fast
-// kernels take them by value), and the symmetry checks of the sector and shell forms
-// (also of the length derivatives on plans built for hyperparameter gradients).
-// Synchronous; called at build and after set_refinement.
-icr_status refresh_host_copies(icr_plan* p, int level) {
-  icr::LevelMats& m = p->lev[level];
-  m.sector_ok = m.shell_ok = m.dsector_ok = m.dshell_ok = false;
-  m.sector_asym = 1.0;
-  m.shell_asym = 1.0;
-  if (p->precision == ICR_F64) return ICR_OK;
-  const auto ok = [](double asym) { return std::isfinite(asym) && asym <= icr::kSectorTolerance; };
-  if (icr::shell_tables(p) && p->ndim == 2) {  // dense rows: always usable
-    m.shell_ok = true;
-    return ICR_OK;
-  }
+// Enqueue on `st` the copies of a level's device results its host copies are made from
+// (nothing for FP64 plans and dense 2-D shell rows).
+icr_status stage_host_copies(const icr_plan* p, int level, HostStage* hs, hipStream_t st) {
+  const icr::LevelMats& m = p->lev[level];
+  if (p->precision == ICR_F64 || (icr::shell_tables(p) && p->ndim == 2)) return ICR_OK;
   if (icr::shell_tables(p)) {
-    icr_status r = shell_asymmetry(m.shell_chk, m.nsets, &m.shell_asym);
-    if (r != ICR_OK) return r;
-    m.shell_ok = ok(m.shell_asym);
+    hs->chk.resize(static_cast<size_t>(2 * m.nsets));
+    ICR_HIP_TRY(hipMemcpyAsync(hs->chk.data(), m.shell_chk, sizeof(double) * hs->chk.size(), hipMemcpyDeviceToHost, st));
     if (m.dshell_tab) {
-      double asym = 1.0;
-      r = shell_asymmetry(m.dshell_chk, m.nsets, &asym);
-      if (r != ICR_OK) return r;
-      m.dshell_ok = ok(asym);
+      hs->dchk.resize(static_cast<size_t>(2 * m.nsets));
+      ICR_HIP_TRY(hipMemcpyAsync(hs->dchk.data(), m.dshell_chk, sizeof(double) * hs->dchk.size(),
+                                 hipMemcpyDeviceToHost, st));
     }
     return ICR_OK;
   }
   if (p->charted) return ICR_OK;
   const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
-  ICR_HIP_TRY(hipMemcpy(m.h_r, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost));
-  ICR_HIP_TRY(hipMemcpy(m.h_s, m.s_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
-  icr_status r = sector_host(m.sector64, nw, m.h_sector, &m.sector_asym);
-  if (r != ICR_OK) return r;
+  ICR_HIP_TRY(hipMemcpyAsync(hs->hr, m.r_c, sizeof(float) * nc * nw, hipMemcpyDeviceToHost, st));
+  ICR_HIP_TRY(hipMemcpyAsync(hs->hs, m.s_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost, st));
+  ICR_HIP_TRY(hipMemcpyAsync(hs->sec, m.sector64, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost, st));
+  if (m.dsector64) {
+    ICR_HIP_TRY(hipMemcpyAsync(hs->hds, m.ds_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost, st));
+    ICR_HIP_TRY(hipMemcpyAsync(hs->dsec, m.dsector64, sizeof(double) * 3 * nw, hipMemcpyDeviceToHost, st));
+  }
+  return ICR_OK;
+}
+
+// Host copies of a stationary level's FP32 matrices and its sector form (the fast
+// kernels take them by value), and the symmetry checks of the sector and shell forms
+// (also of the length derivatives on plans built for hyperparameter gradients), from a
+// completed stage_host_copies.
+void apply_host_copies(icr_plan* p, int level, const HostStage& hs) {
+  icr::LevelMats& m = p->lev[level];
+  m.sector_ok = m.shell_ok = m.dsector_ok = m.dshell_ok = false;
+  m.sector_asym = 1.0;
+  m.shell_asym = 1.0;
+  if (p->precision == ICR_F64) return;
+  const auto ok = [](double asym) { return std::isfinite(asym) && asym <= icr::kSectorTolerance; };
+  if (icr::shell_tables(p) && p->ndim == 2) {  // dense rows: always usable
+    m.shell_ok = true;
+    return;
+  }
+  if (icr::shell_tables(p)) {
+    m.shell_asym = shell_asymmetry(hs.chk, m.nsets);
+    m.shell_ok = ok(m.shell_asym);
+    if (m.dshell_tab) m.dshell_ok = ok(shell_asymmetry(hs.dchk, m.nsets));
+    return;
+  }
+  if (p->charted) return;
+  const int nc = 1 << p->ndim, nw = icr::pow3(p->ndim);
+  std::memcpy(m.h_r, hs.hr, sizeof(float) * nc * nw);
+  std::memcpy(m.h_s, hs.hs, sizeof(float) * nc * nc);
+  sector_host(hs.sec, nw, m.h_sector, &m.sector_asym);
   m.sector_ok = ok(m.sector_asym);
   if (m.dsector64) {
-    ICR_HIP_TRY(hipMemcpy(m.h_ds, m.ds_c, sizeof(float) * nc * nc, hipMemcpyDeviceToHost));
+    std::memcpy(m.h_ds, hs.hds, sizeof(float) * nc * nc);
     double asym = 1.0;
-    r = sector_host(m.dsector64, nw, m.h_dsector, &asym);
-    if (r != ICR_OK) return r;
+    sector_host(hs.dsec, nw, m.h_dsector, &asym);
     m.dsector_ok = ok(asym);
   }
+}
+
+// The same for one level, synchronously on `st` (after icr_plan_set_refinement).
+icr_status refresh_host_copies(icr_plan* p, int level, hipStream_t st) {
+  HostStage hs;
+  icr_status r = stage_host_copies(p, level, &hs, st);
+  if (r != ICR_OK) return r;
+  ICR_HIP_TRY(hipStreamSynchronize(st));
+  apply_host_copies(p, level, hs);
   return ICR_OK;
 }
 
@@ -342,6 +372,9 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   const icr_status cs = check_config(cfg);
   if (cs != ICR_OK) return cs;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // launch checks below read the thread's last error: start from a clean one, so an
+  // earlier unchecked call of this thread cannot fail the build
+  (void)hipGetLastError();
 
   icr_plan* p = new (std::nothrow) icr_plan;
   if (!p) return fail(ICR_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
@@ -489,8 +522,20 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
     if (!p->charted) BUILD_TRY(icr::launch_sector(p, l, st));
     if (icr::shell_tables(p)) BUILD_TRY(icr::launch_shell_sector(p, l, st));
   }
+  // everything the host needs back comes in one round: the status words and every
+  // level's host copies, then a single synchronisation
   int32_t host_status[kMaxLevels + 1];
   BUILD_TRY(hipMemcpyAsync(host_status, status, sizeof(host_status), hipMemcpyDeviceToHost, st));
+  std::vector<HostStage> stages(static_cast<size_t>(p->depth));
+  for (int l = 0; l < p->depth; ++l) {
+    const icr_status hs = stage_host_copies(p, l, &stages[l], st);
+    if (hs != ICR_OK) {
+      (void)hipStreamSynchronize(st);
+      if (dl_scratch) (void)hipFree(dl_scratch);
+      const std::string msg = icr_last_error();
+      return bail(hs, msg);
+    }
+  }
   {
     const hipError_t e = hipStreamSynchronize(st);
     if (dl_scratch) (void)hipFree(dl_scratch);
@@ -498,14 +543,7 @@ icr_status icr_build_matrices(const icr_config* cfg, void* hip_stream, icr_plan*
   }
 #undef BUILD_TRY
   for (int l = 0; l <= p->depth; ++l) p->clamped[l] = host_status[1 + l];
-  for (int l = 0; l < p->depth; ++l) {
-    const icr_status hs = refresh_host_copies(p, l);
-    if (hs != ICR_OK) {
-      (void)hipFree(p->pool);
-      delete p;
-      return hs;
-    }
-  }
+  for (int l = 0; l < p->depth; ++l) apply_host_copies(p, l, stages[l]);
   if (host_status[0] & 2)
     return bail(ICR_ERR_NOT_PD, "K_00 is not positive definite (a pivot needed clamping; clamping disabled)");
   if (p->hypergrad) {
@@ -590,8 +628,7 @@ icr_status icr_plan_set_refinement(icr_plan* p, int32_t level, const double* r, 
   ICR_HIP_TRY(icr::launch_level_convert(p, level, st));
   if (!p->charted) ICR_HIP_TRY(icr::launch_sector(p, level, st));
   if (icr::shell_tables(p)) ICR_HIP_TRY(icr::launch_shell_sector(p, level, st));
-  ICR_HIP_TRY(hipStreamSynchronize(st));
-  return refresh_host_copies(p, level);
+  return refresh_host_copies(p, level, st);
 }
 
 icr_status icr_forward(const icr_plan* p, int64_t batch, const void* xi, void* s, void* workspace,

@@ -1,21 +1,29 @@
 // Served ICR: a request server with continuous batching.
 //
 // Callers submit forward / adjoint / metric requests against plans registered with the
-// server; each request brings its own device input and output buffers. A worker thread
-//   1. retires batches whose completion event has fired (records the completion time,
-//      returns their memory to the arena, or marks their captured graph free),
-//   2. forms batches from pending requests with the same (plan, op), oldest first, up to
-//      the largest power of two <= min(pending, max_batch),
-//   3. admits a batch only if its buffers fit in the fixed HBM arena (first fit), and
-//      launches it on a stream with no batch in flight: gather the requests' inputs into a
-//      contiguous batch, run the batched sweep (replaying a hipGraph captured once per
-//      (plan, op, batch size) when graphs are enabled and the batch needs at most 1/32 of
-//      the arena; larger batches launch eagerly), scatter the outputs, record an event.
-//      A single request without a graph runs the sweep on its own buffers (only its
-//      workspace comes from the arena).
+// server, or against prior configurations whose plans a builder thread builds on first
+// use and caches; each request brings its own device input and output buffers. A worker
+// thread
+//   1. retires work whose completion events have fired (records completion times, returns
+//      memory to the arena, marks captured graphs free),
+//   2. in grouped mode, gathers the pending requests whose refinement levels are all
+//      below the large-step size, of any prior and op, oldest first, into a group while
+//      fewer than group_streams groups run: every request's workspace comes from the
+//      arena, the steps of all sweeps go to the device in one table, and the k-th grouped
+//      launch applies the k-th step of every sweep; each request's completion event
+//      follows its own last step,
+//   3. forms homogeneous batches from the other pending requests with the same
+//      (plan, op), oldest first, up to the largest power of two <= min(pending,
+//      max_batch), admits a batch only if its buffers fit in the fixed HBM arena (first
+//      fit), and launches it on a free stream: gather the inputs into a contiguous batch,
+//      run the batched sweep (replaying a hipGraph captured once per (plan, op, batch
+//      size) when graphs are enabled and the batch needs at most 1/32 of the arena;
+//      larger batches launch eagerly), scatter the outputs, record an event. A single
+//      request without a graph runs the sweep on its own buffers (only its workspace
+//      comes from the arena).
 // Requests that arrive while others run join the queue and are admitted as streams and
-// memory free up, so batches of different priors overlap on the device. With
-// max_batch = 1, one stream and no graphs the same server is the one-launch-per-request
+// memory free up, so work of different priors overlaps on the device. With max_batch = 1,
+// one stream, no graphs and no grouping the same server is the one-launch-per-request
 // baseline.
 #include <hip/hip_runtime.h>
 
@@ -30,9 +38,11 @@
 #include <string>
 #include <thread>
 #include <tuple>
+#include <utility>
 #include <unordered_map>
 #include <vector>
 
+#include "grouped.h"
 #include "icr_internal.h"
 #include "icr_server.h"
 
@@ -144,6 +154,29 @@ struct PlanEntry {
   const icr_plan* plan;
   int64_t n_xi, n_out;
   int elem, acc;
+  bool large = false;   // a refinement level has at least large_step fine pixels
+  bool owned = false;   // built by the server for a prior configuration (destroyed with it)
+  int64_t active = 0;   // requests pending or in flight
+  double last_used = 0.0;
+  std::string key;      // owned: the configuration it was built for
+};
+
+constexpr int kMaxSteps = 2 * (ICR_MAX_DEPTH + 1);  // steps of a metric sweep
+
+// A group: requests of any prior and op whose sweeps advance one step per grouped
+// launch, on one stream; each request's own event marks its end.
+struct Group {
+  std::vector<int64_t> ids;
+  int stream = -1;
+};
+
+// The plan cache entry of a prior configuration.
+struct CacheEntry {
+  int state = 0;                 // 0 building, 1 ready, 2 failed
+  int32_t plan_id = -1;
+  icr_status status = ICR_OK;
+  std::string message;
+  std::vector<int64_t> waiting;  // requests submitted while the plan was built
 };
 
 struct Request {
@@ -156,6 +189,10 @@ struct Request {
   double t_submit = 0.0, t_launch = 0.0, t_done = 0.0;
   int32_t batch_size = 0;
   bool done = false;
+  icr_status status = ICR_OK;  // the build status of a request whose plan failed to build
+  std::string message;
+  hipEvent_t finished = nullptr;  // grouped: recorded after the request's last step
+  void* ws = nullptr;             // grouped: the request's workspace in the arena
 };
 
 // Device buffers of one batch: [k][n_in] inputs, [k][n_out_op] outputs, [k][n_out] w,
@@ -194,10 +231,22 @@ struct icr_server {
   std::deque<int64_t> pending;
   std::vector<hipStream_t> streams;
   std::vector<Batch*> inflight;  // per stream
+  std::vector<Group*> grouped;   // per stream
   std::vector<hipEvent_t> event_pool;
   std::map<std::tuple<int, int, int>, std::vector<Graph*>> graphs;
+  // grouped launches: per stream a pinned host table of steps and its device copy
+  std::vector<icr::GroupTask*> host_tables;
+  std::vector<icr::GroupTask*> dev_tables;
+  size_t table_tasks = 0;        // tasks each table holds
+  // plan cache of prior configurations and its builder thread
+  std::map<std::string, CacheEntry> cache;
+  std::deque<std::string> build_jobs;
+  std::condition_variable build_cv;
+  std::thread builder;
+  hipStream_t build_stream = nullptr;
   int64_t next_id = 1;
   int64_t completed = 0, batches = 0, batched_requests = 0, graph_captures = 0, admissions_deferred = 0;
+  int64_t groups = 0, grouped_requests = 0, plans_built = 0, plan_cache_hits = 0;
   std::string error;
   std::mutex mu;
   std::condition_variable cv;
@@ -319,17 +368,23 @@ Graph* find_graph(icr_server* s, const PlanEntry& pe, int plan_id, int op, int k
   return g;
 }
 
+// An event from the pool (created when the pool is empty); nullptr if creation fails.
+hipEvent_t take_event(icr_server* s) {
+  if (s->event_pool.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return ev;
+  }
+  hipEvent_t ev = s->event_pool.back();
+  s->event_pool.pop_back();
+  return ev;
+}
+
 // Record the batch's completion event and book it as in flight on stream `si`.
 bool finish_launch(icr_server* s, int si, Batch* b, const std::vector<int64_t>& ids, hipError_t e) {
   hipStream_t st = s->streams[si];
   const int k = static_cast<int>(ids.size());
-  if (s->event_pool.empty()) {
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-    s->event_pool.push_back(ev);
-  }
-  b->done = s->event_pool.back();
-  s->event_pool.pop_back();
+  b->done = take_event(s);
   if (e == hipSuccess && b->done) e = hipEventRecord(b->done, st);
   if (e != hipSuccess) s->error = std::string("batch launch: ") + hipGetErrorString(e);
   if (b->graph) {
@@ -345,6 +400,117 @@ bool finish_launch(icr_server* s, int si, Batch* b, const std::vector<int64_t>& 
   ++s->batches;
   s->batched_requests += k;
   return true;
+}
+
+bool stream_free(const icr_server* s, size_t si) { return !s->inflight[si] && !s->grouped[si]; }
+
+// Launch a group on stream `si`: every request's workspace from the arena (requests that
+// do not fit wait for the next group), the steps of all sweeps in one table copy, then
+// per step and precision one grouped launch, and each request's event after its last
+// step. `ids` is reduced to the requests admitted; false if none was.
+bool launch_group(icr_server* s, int si, std::vector<int64_t>& ids) {
+  hipStream_t st = s->streams[si];
+  std::vector<int64_t> admitted;
+  std::vector<std::vector<icr::GroupTask>> steps;  // per request
+  for (int64_t id : ids) {
+    Request& r = s->requests[id];
+    const PlanEntry& pe = s->plans[r.plan_id];
+    const size_t bytes = up(size_t(std::max<int64_t>(ws_elems(pe, r.op), 1)) * pe.elem);
+    void* ws = alloc_evicting(s, bytes);
+    if (!ws) {
+      ++s->admissions_deferred;
+      break;  // keep arrival order: later requests wait with this one
+    }
+    r.ws = ws;
+    std::vector<icr::GroupTask> t(kMaxSteps);
+    int large = 0;
+    t.resize(icr::sweep_tasks(pe.plan, r.op, r.in, r.out, r.w, ws, INT64_MAX, t.data(), &large));
+    steps.push_back(std::move(t));
+    admitted.push_back(id);
+  }
+  ids = admitted;
+  if (ids.empty()) return false;
+  hipError_t e = hipSuccess;
+  for (int64_t id : ids) {
+    const Request& r = s->requests[id];
+    if (e == hipSuccess && r.ready) e = hipStreamWaitEvent(st, r.ready, 0);
+  }
+  // the table: step k of every request, per precision, tasks sorted by first workgroup
+  struct Launch {
+    int precision;
+    size_t first;
+    int ntasks;
+    int64_t workgroups;
+  };
+  std::vector<Launch> launches;
+  std::vector<std::pair<size_t, int64_t>> last_launch;  // per request: launch index of its last step
+  last_launch.assign(ids.size(), {0, 0});
+  icr::GroupTask* host = s->host_tables[si];
+  size_t used = 0;
+  size_t max_steps = 0;
+  for (const auto& t : steps) max_steps = std::max(max_steps, t.size());
+  for (size_t k = 0; k < max_steps; ++k) {
+    for (int prec = ICR_F64; prec <= ICR_BF16_F32ACC; ++prec) {
+      Launch L{prec, used, 0, 0};
+      for (size_t i = 0; i < ids.size(); ++i) {
+        const Request& r = s->requests[ids[i]];
+        if (k >= steps[i].size() || s->plans[r.plan_id].plan->precision != prec) continue;
+        icr::GroupTask t = steps[i][k];
+        t.wg0 = L.workgroups;
+        L.workgroups += icr::task_workgroups(t);
+        host[used++] = t;
+        ++L.ntasks;
+        if (k + 1 == steps[i].size()) last_launch[i] = {launches.size(), 0};
+      }
+      if (L.ntasks > 0) launches.push_back(L);
+    }
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->dev_tables[si], host, used * sizeof(icr::GroupTask), hipMemcpyHostToDevice, st);
+  Group* g = new Group;
+  g->ids = ids;
+  g->stream = si;
+  for (size_t li = 0; li < launches.size() && e == hipSuccess; ++li) {
+    const Launch& L = launches[li];
+    e = icr::launch_grouped_step(L.precision, s->dev_tables[si] + L.first, L.ntasks, L.workgroups, st);
+    for (size_t i = 0; i < ids.size() && e == hipSuccess; ++i) {
+      if (last_launch[i].first != li) continue;
+      Request& r = s->requests[ids[i]];
+      r.finished = take_event(s);
+      e = r.finished ? hipEventRecord(r.finished, st) : hipErrorOutOfMemory;
+    }
+  }
+  if (e != hipSuccess) s->error = std::string("group launch: ") + hipGetErrorString(e);
+  const double t = now_s();
+  for (int64_t id : ids) {
+    Request& r = s->requests[id];
+    r.t_launch = t;
+    r.batch_size = static_cast<int32_t>(ids.size());
+  }
+  s->grouped[si] = g;
+  ++s->groups;
+  s->grouped_requests += static_cast<int64_t>(ids.size());
+  return true;
+}
+
+// A request is done: times, counters, its plan's activity; events back to the pool.
+void complete(icr_server* s, Request& r, double t) {
+  r.t_done = t;
+  r.done = true;
+  if (r.ready) {
+    s->event_pool.push_back(r.ready);
+    r.ready = nullptr;
+  }
+  if (r.finished) {
+    s->event_pool.push_back(r.finished);
+    r.finished = nullptr;
+  }
+  if (r.plan_id >= 0) {
+    PlanEntry& pe = s->plans[r.plan_id];
+    pe.active -= 1;
+    pe.last_used = t;
+  }
+  ++s->completed;
 }
 
 
@@ -431,29 +597,72 @@ void retire(icr_server* s) {
     if (!b) continue;
     if (b->done && hipEventQuery(b->done) == hipErrorNotReady) continue;
     const double t = now_s();
-    for (int64_t id : b->ids) {
-      Request& r = s->requests[id];
-      r.t_done = t;
-      r.done = true;
-      if (r.ready) {
-        s->event_pool.push_back(r.ready);
-        r.ready = nullptr;
-      }
-      ++s->completed;
-    }
+    for (int64_t id : b->ids) complete(s, s->requests[id], t);
     if (b->graph) b->graph->busy = false;
     else if (b->buf.in) s->arena.release(b->buf.in);
     if (b->done) s->event_pool.push_back(b->done);
     delete b;
     s->inflight[si] = nullptr;
   }
+  for (size_t si = 0; si < s->grouped.size(); ++si) {
+    Group* g = s->grouped[si];
+    if (!g) continue;
+    bool all = true;
+    for (int64_t id : g->ids) {
+      Request& r = s->requests[id];
+      if (r.done) continue;
+      if (r.finished && hipEventQuery(r.finished) == hipErrorNotReady) {
+        all = false;
+        continue;
+      }
+      if (r.ws) s->arena.release(r.ws);
+      r.ws = nullptr;
+      complete(s, r, now_s());
+    }
+    if (all) {
+      delete g;
+      s->grouped[si] = nullptr;
+    }
+  }
 }
 
-// Form and launch batches on free streams; oldest pending request first.
+bool groupable(const icr_server* s, const Request& r) {
+  return s->cfg.grouped && !s->plans[r.plan_id].large;
+}
+
+void remove_pending(icr_server* s, const std::vector<int64_t>& ids) {
+  for (int64_t id : ids) {
+    auto it = std::find(s->pending.begin(), s->pending.end(), id);
+    if (it != s->pending.end()) s->pending.erase(it);
+  }
+}
+
+// Form and launch groups and batches on free streams; oldest pending request first.
 void schedule(icr_server* s) {
+  if (s->cfg.grouped) {
+    int running = 0;
+    for (Group* g : s->grouped) running += g != nullptr;
+    for (size_t si = 0; si < s->streams.size() && running < s->cfg.group_streams; ++si) {
+      if (!stream_free(s, si)) continue;
+      std::vector<int64_t> ids;
+      for (int64_t id : s->pending) {
+        if (groupable(s, s->requests[id])) ids.push_back(id);
+        if (static_cast<int>(ids.size()) >= s->cfg.max_batch) break;
+      }
+      if (ids.empty() || !launch_group(s, static_cast<int>(si), ids)) break;
+      remove_pending(s, ids);
+      ++running;
+    }
+  }
   for (size_t si = 0; si < s->inflight.size() && !s->pending.empty(); ++si) {
-    if (s->inflight[si]) continue;
-    const int64_t head = s->pending.front();
+    if (!stream_free(s, si)) continue;
+    int64_t head = -1;
+    for (int64_t id : s->pending)
+      if (!groupable(s, s->requests[id])) {
+        head = id;
+        break;
+      }
+    if (head < 0) break;
     const Request& rh = s->requests[head];
     std::vector<int64_t> ids;
     for (int64_t id : s->pending) {
@@ -475,10 +684,132 @@ void schedule(icr_server* s) {
       ids.resize(ids.size() / 2);  // a smaller batch may fit
     }
     if (!admitted) break;  // wait for memory to free up; keep arrival order
-    for (int64_t id : ids) {
-      auto it = std::find(s->pending.begin(), s->pending.end(), id);
-      if (it != s->pending.end()) s->pending.erase(it);
+    remove_pending(s, ids);
+  }
+}
+
+bool any_in_flight(const icr_server* s) {
+  for (size_t si = 0; si < s->streams.size(); ++si)
+    if (!stream_free(s, si)) return true;
+  return false;
+}
+
+// Host-side sizes of a prior configuration (the plan's n_xi and n_out).
+void config_sizes(const icr_config& c, int64_t* n_xi, int64_t* n_out) {
+  int64_t total = 0, last = 0;
+  int64_t n[3] = {1, 1, 1};
+  for (int a = 0; a < c.ndim; ++a) n[a] = c.shape0[a];
+  for (int l = 0; l <= c.depth; ++l) {
+    last = n[0] * n[1] * n[2];
+    total += last;
+    for (int a = 0; a < c.ndim; ++a) n[a] = 2 * (n[a] - 2);
+  }
+  *n_xi = total;
+  *n_out = last;
+}
+
+bool plan_is_large(const icr_plan* p, int64_t large) {
+  for (int l = 0; l < p->depth; ++l)
+    if (p->offsets[l + 2] - p->offsets[l + 1] >= large) return true;
+  return false;
+}
+
+int32_t add_plan(icr_server* s, const icr_plan* plan, bool owned, const std::string& key) {
+  PlanEntry pe{plan, plan->n_xi, plan->n_out, plan->elem_bytes, plan->precision == ICR_F64 ? 8 : 4};
+  pe.large = plan_is_large(plan, s->cfg.large_step);
+  pe.owned = owned;
+  pe.key = key;
+  pe.last_used = now_s();
+  s->plans.push_back(pe);
+  return static_cast<int32_t>(s->plans.size() - 1);
+}
+
+// Destroy the least recently used idle plans the server built while the cache holds
+// more than max_plans ready entries (entries stay as tombstones: their plan_id is reset).
+void evict_plans(icr_server* s) {
+  for (;;) {
+    int ready = 0;
+    for (auto& kv : s->cache) ready += kv.second.state == 1;
+    if (ready <= s->cfg.max_plans) return;
+    std::string victim;
+    double oldest = 0.0;
+    for (auto& kv : s->cache) {
+      if (kv.second.state != 1) continue;
+      const PlanEntry& pe = s->plans[kv.second.plan_id];
+      if (pe.active > 0) continue;
+      if (victim.empty() || pe.last_used < oldest) {
+        victim = kv.first;
+        oldest = pe.last_used;
+      }
     }
+    if (victim.empty()) return;
+    PlanEntry& pe = s->plans[s->cache[victim].plan_id];
+    // idle graphs captured for the plan go with it
+    for (auto& kv : s->graphs) {
+      if (std::get<0>(kv.first) != s->cache[victim].plan_id) continue;
+      for (Graph* g : kv.second) {
+        (void)hipGraphExecDestroy(g->exec);
+        s->arena.release(g->buf.in);
+        delete g;
+      }
+      kv.second.clear();
+    }
+    (void)icr_plan_destroy(const_cast<icr_plan*>(pe.plan));
+    pe.plan = nullptr;
+    s->cache.erase(victim);
+  }
+}
+
+// Builder thread: builds the plans of new prior configurations on its own stream while
+// the worker keeps serving; the requests waiting for a plan become pending when it is
+// ready, or complete with the build's status when it fails.
+void builder_loop(icr_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop.load()) {
+    if (s->build_jobs.empty()) {
+      s->build_cv.wait_for(lk, std::chrono::milliseconds(5));
+      continue;
+    }
+    const std::string key = s->build_jobs.front();
+    s->build_jobs.pop_front();
+    icr_config cfg;
+    std::memcpy(&cfg, key.data(), sizeof(cfg));
+    lk.unlock();
+    icr_plan* plan = nullptr;
+    const icr_status st = icr_build_matrices(&cfg, s->build_stream, &plan);
+    const std::string msg = st == ICR_OK ? std::string() : std::string(icr_last_error());
+    lk.lock();
+    CacheEntry& ce = s->cache[key];
+    const double t = now_s();
+    if (st == ICR_OK) {
+      ce.state = 1;
+      ce.plan_id = add_plan(s, plan, true, key);
+      ++s->plans_built;
+      PlanEntry& pe = s->plans[ce.plan_id];
+      for (int64_t id : ce.waiting) {
+        Request& r = s->requests[id];
+        r.plan_id = ce.plan_id;
+        pe.active += 1;
+        // back into arrival order among the pending requests
+        auto it = std::lower_bound(s->pending.begin(), s->pending.end(), id);
+        s->pending.insert(it, id);
+      }
+    } else {
+      ce.state = 2;
+      ce.status = st;
+      ce.message = msg;
+      for (int64_t id : ce.waiting) {
+        Request& r = s->requests[id];
+        r.status = st;
+        r.message = msg;
+        r.plan_id = -1;
+        complete(s, r, t);
+      }
+    }
+    ce.waiting.clear();
+    evict_plans(s);
+    s->cv.notify_one();
   }
 }
 
@@ -488,8 +819,7 @@ void worker_loop(icr_server* s) {
   while (!s->stop.load()) {
     retire(s);
     schedule(s);
-    bool busy = false;
-    for (Batch* b : s->inflight) busy = busy || b != nullptr;
+    const bool busy = any_in_flight(s);
     if (!busy && s->pending.empty()) {
       s->cv.wait_for(lk, std::chrono::milliseconds(2));
     } else {
@@ -512,12 +842,17 @@ icr_status icr_server_create(const icr_server_config* cfg, icr_server** out) {
   }
   *out = nullptr;
   if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch || cfg->n_streams < 1 || cfg->n_streams > 16 ||
-      cfg->hbm_budget_bytes < int64_t(kAlign)) {
-    icr::set_error("max_batch must be 1..64, n_streams 1..16, hbm_budget_bytes >= 256");
+      cfg->hbm_budget_bytes < int64_t(kAlign) || cfg->large_step < 0 || cfg->group_streams < 0 ||
+      cfg->group_streams > cfg->n_streams || cfg->max_plans < 0 || (cfg->grouped != 0 && cfg->grouped != 1)) {
+    icr::set_error("max_batch must be 1..64, n_streams 1..16, hbm_budget_bytes >= 256, grouped 0 or 1, "
+                   "large_step >= 0, group_streams 0..n_streams, max_plans >= 0");
     return ICR_ERR_INVALID_ARG;
   }
   icr_server* s = new icr_server;
   s->cfg = *cfg;
+  if (s->cfg.large_step == 0) s->cfg.large_step = int64_t(1) << 20;
+  if (s->cfg.group_streams == 0) s->cfg.group_streams = 1;
+  if (s->cfg.max_plans == 0) s->cfg.max_plans = 256;
   (void)hipGetDevice(&s->device);
   if (!s->arena.init(static_cast<size_t>(cfg->hbm_budget_bytes))) {
     delete s;
@@ -535,7 +870,30 @@ icr_status icr_server_create(const icr_server_config* cfg, icr_server** out) {
     s->streams.push_back(st);
   }
   s->inflight.assign(cfg->n_streams, nullptr);
+  s->grouped.assign(cfg->n_streams, nullptr);
+  s->table_tasks = size_t(kMaxSteps) * kMaxBatch;
+  bool ok = hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < cfg->n_streams && ok; ++i) {
+    void* h = nullptr;
+    void* d = nullptr;
+    ok = hipHostMalloc(&h, s->table_tasks * sizeof(icr::GroupTask), hipHostMallocDefault) == hipSuccess;
+    s->host_tables.push_back(static_cast<icr::GroupTask*>(h));
+    if (ok) ok = hipMalloc(&d, s->table_tasks * sizeof(icr::GroupTask)) == hipSuccess;
+    s->dev_tables.push_back(static_cast<icr::GroupTask*>(d));
+  }
+  if (!ok) {
+    for (void* h : s->host_tables)
+      if (h) (void)hipHostFree(h);
+    for (void* d : s->dev_tables)
+      if (d) (void)hipFree(d);
+    for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+    if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+    delete s;
+    icr::set_error("could not allocate the server's step tables or build stream");
+    return ICR_ERR_OUT_OF_MEMORY;
+  }
   s->worker = std::thread(worker_loop, s);
+  s->builder = std::thread(builder_loop, s);
   *out = s;
   return ICR_OK;
 }
@@ -547,9 +905,7 @@ icr_status icr_server_register_plan(icr_server* s, const icr_plan* plan, int32_t
     return ICR_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  PlanEntry pe{plan, plan->n_xi, plan->n_out, plan->elem_bytes, plan->precision == ICR_F64 ? 8 : 4};
-  s->plans.push_back(pe);
-  *plan_id = static_cast<int32_t>(s->plans.size() - 1);
+  *plan_id = add_plan(s, plan, false, std::string());
   return ICR_OK;
 }
 
@@ -565,11 +921,11 @@ icr_status icr_server_submit(icr_server* s, int32_t plan_id, int32_t op, const v
     return ICR_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (plan_id < 0 || plan_id >= static_cast<int32_t>(s->plans.size())) {
+  if (plan_id < 0 || plan_id >= static_cast<int32_t>(s->plans.size()) || !s->plans[plan_id].plan) {
     icr::set_error("unknown plan_id");
     return ICR_ERR_INVALID_ARG;
   }
-  const PlanEntry& pe = s->plans[plan_id];
+  PlanEntry& pe = s->plans[plan_id];
   if (batch_bytes(pe, op, 1) > s->arena.capacity()) {
     icr::set_error("request needs more memory than the server's HBM budget");
     return ICR_ERR_OUT_OF_MEMORY;
@@ -598,6 +954,78 @@ icr_status icr_server_submit(icr_server* s, int32_t plan_id, int32_t op, const v
   const int64_t id = s->next_id++;
   s->requests[id] = r;
   s->pending.push_back(id);
+  pe.active += 1;
+  *request_id = id;
+  s->cv.notify_one();
+  return ICR_OK;
+}
+
+icr_status icr_server_submit_prior(icr_server* s, const icr_config* cfg, int32_t op, const void* in, void* out,
+                                   const void* w, void* hip_stream, int64_t* request_id) {
+  icr::clear_error();
+  if (!s || !cfg || !in || !out || !request_id) {
+    icr::set_error("server, cfg, in, out or request_id is NULL");
+    return ICR_ERR_INVALID_ARG;
+  }
+  if (op < ICR_OP_FORWARD || op > ICR_OP_METRIC || (op == ICR_OP_METRIC && !w)) {
+    icr::set_error("unknown op, or a metric request without w");
+    return ICR_ERR_INVALID_ARG;
+  }
+  if (cfg->ndim < 1 || cfg->ndim > 3 || cfg->depth < 0 || cfg->depth > ICR_MAX_DEPTH ||
+      cfg->precision < ICR_F64 || cfg->precision > ICR_BF16_F32ACC) {
+    icr::set_error("invalid prior configuration");
+    return ICR_ERR_INVALID_ARG;
+  }
+  for (int a = 0; a < cfg->ndim; ++a)
+    if (cfg->shape0[a] < 3 || cfg->shape0[a] > 65536) {
+      icr::set_error("invalid prior configuration (level-0 shape)");
+      return ICR_ERR_INVALID_ARG;
+    }
+  const std::string key(reinterpret_cast<const char*>(cfg), sizeof(icr_config));
+  std::lock_guard<std::mutex> lk(s->mu);
+  // the buffers the request needs, from sizes alone: refused now if they never fit
+  PlanEntry sizes{nullptr, 0, 0, cfg->precision == ICR_F64 ? 8 : cfg->precision == ICR_F32 ? 4 : 2,
+                  cfg->precision == ICR_F64 ? 8 : 4};
+  config_sizes(*cfg, &sizes.n_xi, &sizes.n_out);
+  if (batch_bytes(sizes, op, 1) > s->arena.capacity()) {
+    icr::set_error("request needs more memory than the server's HBM budget");
+    return ICR_ERR_OUT_OF_MEMORY;
+  }
+  Request r;
+  r.plan_id = -1;
+  r.op = op;
+  r.in = in;
+  r.out = out;
+  r.w = w;
+  r.ready = take_event(s);
+  if (!r.ready || hipEventRecord(r.ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+    if (r.ready) s->event_pool.push_back(r.ready);
+    icr::set_error("hipEventRecord on the caller's stream failed");
+    return ICR_ERR_HIP;
+  }
+  r.t_submit = now_s();
+  const int64_t id = s->next_id++;
+  auto it = s->cache.find(key);
+  if (it == s->cache.end()) {
+    CacheEntry ce;
+    ce.waiting.push_back(id);
+    s->cache.emplace(key, std::move(ce));
+    s->build_jobs.push_back(key);
+    s->build_cv.notify_one();
+  } else if (it->second.state == 0) {
+    it->second.waiting.push_back(id);
+    ++s->plan_cache_hits;
+  } else if (it->second.state == 1) {
+    r.plan_id = it->second.plan_id;
+    s->plans[r.plan_id].active += 1;
+    ++s->plan_cache_hits;
+  } else {  // the configuration failed to build before: fail the same way
+    s->event_pool.push_back(r.ready);
+    icr::set_error(it->second.message);
+    return it->second.status;
+  }
+  s->requests[id] = r;
+  if (r.plan_id >= 0) s->pending.push_back(id);
   *request_id = id;
   s->cv.notify_one();
   return ICR_OK;
@@ -622,6 +1050,10 @@ icr_status icr_server_query(icr_server* s, int64_t request_id, int32_t* done, do
   if (t_launch) *t_launch = r.t_launch;
   if (t_done) *t_done = r.t_done;
   if (batch_size) *batch_size = r.batch_size;
+  if (r.status != ICR_OK) {
+    icr::set_error("the prior's plan could not be built: " + r.message);
+    return r.status;
+  }
   return ICR_OK;
 }
 
@@ -635,8 +1067,8 @@ icr_status icr_server_drain(icr_server* s, double timeout_s) {
   for (;;) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      bool busy = !s->pending.empty();
-      for (Batch* b : s->inflight) busy = busy || b != nullptr;
+      bool busy = !s->pending.empty() || any_in_flight(s) || !s->build_jobs.empty();
+      for (auto& kv : s->cache) busy = busy || kv.second.state == 0;
       if (!s->error.empty()) {
         icr::set_error(s->error);
         return ICR_ERR_HIP;
@@ -666,6 +1098,10 @@ icr_status icr_server_stats(icr_server* s, icr_server_statistics* st) {
   st->admissions_deferred = s->admissions_deferred;
   st->arena_bytes = static_cast<int64_t>(s->arena.capacity());
   st->arena_in_use = static_cast<int64_t>(s->arena.in_use());
+  st->groups = s->groups;
+  st->grouped_requests = s->grouped_requests;
+  st->plans_built = s->plans_built;
+  st->plan_cache_hits = s->plan_cache_hits;
   return ICR_OK;
 }
 
@@ -674,9 +1110,24 @@ icr_status icr_server_destroy(icr_server* s) {
   if (!s) return ICR_OK;
   s->stop.store(true);
   s->cv.notify_one();
+  s->build_cv.notify_one();
   if (s->worker.joinable()) s->worker.join();
+  if (s->builder.joinable()) s->builder.join();
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  if (s->build_stream) (void)hipStreamSynchronize(s->build_stream);
   for (Batch* b : s->inflight) delete b;
+  for (Group* g : s->grouped) delete g;
+  for (auto& kv : s->requests) {
+    if (kv.second.finished) (void)hipEventDestroy(kv.second.finished);
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  }
+  for (PlanEntry& pe : s->plans)
+    if (pe.owned && pe.plan) (void)icr_plan_destroy(const_cast<icr_plan*>(pe.plan));
+  for (void* h : s->host_tables)
+    if (h) (void)hipHostFree(h);
+  for (void* d : s->dev_tables)
+    if (d) (void)hipFree(d);
+  if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
   for (auto& kv : s->graphs)
     for (Graph* g : kv.second) {
       if (g->exec) (void)hipGraphExecDestroy(g->exec);

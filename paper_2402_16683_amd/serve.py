@@ -21,13 +21,15 @@ OPS = {"forward": 0, "adjoint": 1, "metric": 2}
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
-                ("n_streams", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_streams", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("grouped", ctypes.c_int32),
+                ("large_step", ctypes.c_int64), ("group_streams", ctypes.c_int32), ("max_plans", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("completed", "pending", "batches", "batched_requests",
                                               "graph_captures", "admissions_deferred", "arena_bytes",
-                                              "arena_in_use")]
+                                              "arena_in_use", "groups", "grouped_requests", "plans_built",
+                                              "plan_cache_hits")]
 
 
 def _lib():
@@ -38,6 +40,7 @@ def _lib():
             "icr_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
             "icr_server_register_plan": [vp, vp, ctypes.POINTER(i32)],
             "icr_server_submit": [vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(i64)],
+            "icr_server_submit_prior": [vp, ctypes.POINTER(B.IcrConfig), i32, vp, vp, vp, vp, ctypes.POINTER(i64)],
             "icr_server_query": [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl), ctypes.POINTER(i32)],
             "icr_server_drain": [vp, dbl],
@@ -55,8 +58,10 @@ def _lib():
 class Server:
     """An icr_server: continuous batching of ICR requests on the current device."""
 
-    def __init__(self, hbm_budget_bytes: int, max_batch: int = 16, n_streams: int = 4, use_graphs: bool = True):
-        cfg = ServerConfig(hbm_budget_bytes, max_batch, n_streams, 1 if use_graphs else 0, 0)
+    def __init__(self, hbm_budget_bytes: int, max_batch: int = 16, n_streams: int = 4, use_graphs: bool = True,
+                 grouped: bool = False, large_step: int = 0, group_streams: int = 0, max_plans: int = 0):
+        cfg = ServerConfig(hbm_budget_bytes, max_batch, n_streams, 1 if use_graphs else 0, 1 if grouped else 0,
+                           large_step, group_streams, max_plans)
         self.handle = ctypes.c_void_p()
         B._check(_lib().icr_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
         self.plans = []
@@ -76,6 +81,16 @@ class Server:
         B._check(_lib().icr_server_submit(self.handle, plan_id, OPS[op], inp.data_ptr(), out.data_ptr(),
                                           None if w is None else w.data_ptr(), B._stream_handle(stream),
                                           ctypes.byref(rid)))
+        self._held[rid.value] = (inp, out, w)
+        return rid.value
+
+    def submit_prior(self, cfg: B.IcrConfig, op: str, inp, out, w=None, stream=None) -> int:
+        """Queue one request against a prior configuration; the server builds its plan on
+        first use (inside that request's latency) and caches it."""
+        rid = ctypes.c_int64()
+        B._check(_lib().icr_server_submit_prior(self.handle, ctypes.byref(cfg), OPS[op], inp.data_ptr(),
+                                                out.data_ptr(), None if w is None else w.data_ptr(),
+                                                B._stream_handle(stream), ctypes.byref(rid)))
         self._held[rid.value] = (inp, out, w)
         return rid.value
 
@@ -118,6 +133,20 @@ class Prior:
     depth: int
     kernel: str
     length: float
+
+    def config(self, precision: str = "f32") -> B.IcrConfig:
+        return B.make_config(self.ndim, (self.n0,) * self.ndim, self.depth, (self.delta0,) * self.ndim,
+                             kernel=self.kernel, length=self.length, precision=precision)
+
+    @property
+    def sizes(self):
+        """(n_xi, n_out) of the prior: level sizes n_{l+1} = 2 (n_l - 2)."""
+        n, total = self.n0, 0
+        for _ in range(self.depth + 1):
+            total += n ** self.ndim
+            last = n ** self.ndim
+            n = 2 * (n - 2)
+        return total, last
 
     @property
     def delta0(self) -> float:
@@ -169,28 +198,31 @@ class Slots:
     last: list = field(default_factory=list)
 
 
-def build_pool(priors, precision="f32", slots=8, seed=11):
+def build_pool(priors, precision="f32", slots=8, seed=11, plans=True):
+    """Request buffers per prior (inputs drawn once, outputs per slot) and, with plans,
+    each prior's plan built here; without, the plans list is empty and requests go to
+    the server by configuration (the server builds and caches the plans)."""
     import torch
-    plans, pool = [], []
+    dtype = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[precision]
+    acc = torch.float64 if precision == "f64" else torch.float32
+    built, pool = [], []
     for k, pr in enumerate(priors):
-        cfg = B.make_config(pr.ndim, (pr.n0,) * pr.ndim, pr.depth, (pr.delta0,) * pr.ndim, kernel=pr.kernel,
-                            length=pr.length, precision=precision)
-        plan = B.icr_build_matrices(cfg)
-        plans.append(plan)
-        n_xi, n_out = plan.info["n_xi"], plan.info["n_out"]
+        if plans:
+            built.append(B.icr_build_matrices(pr.config(precision)))
+        n_xi, n_out = pr.sizes
         g = torch.Generator(device="cuda")
         g.manual_seed(seed + k)
         sl = Slots()
         for _ in range(slots):
-            sl.xi.append(torch.randn(n_xi, device="cuda", generator=g).to(plan.dtype))
-            sl.ybar.append(torch.randn(n_out, device="cuda", generator=g).to(plan.dtype))
-            sl.w.append((torch.rand(n_out, device="cuda", generator=g) < 0.7).to(plan.acc_dtype) * 100.0)
-            sl.out_s.append(torch.empty(n_out, dtype=plan.dtype, device="cuda"))
-            sl.out_x.append(torch.empty(n_xi, dtype=plan.dtype, device="cuda"))
+            sl.xi.append(torch.randn(n_xi, device="cuda", generator=g).to(dtype))
+            sl.ybar.append(torch.randn(n_out, device="cuda", generator=g).to(dtype))
+            sl.w.append((torch.rand(n_out, device="cuda", generator=g) < 0.7).to(acc) * 100.0)
+            sl.out_s.append(torch.empty(n_out, dtype=dtype, device="cuda"))
+            sl.out_x.append(torch.empty(n_xi, dtype=dtype, device="cuda"))
             sl.last.append(None)
         pool.append(sl)
     torch.cuda.synchronize()
-    return plans, pool
+    return built, pool
 
 
 def register_all(server: Server, plans) -> list:
@@ -199,9 +231,10 @@ def register_all(server: Server, plans) -> list:
 
 def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True, slot_timeout_s: float = 60.0):
     """Submit the stream at its arrival times; returns per-request latency (s), batch size
-    and the wall time of the run. `plan_ids` are the pool's ids in this server. A request
-    that can never fit the server's memory budget is refused at submission: its latency
-    is NaN and its batch size 0."""
+    and the wall time of the run. `plan_ids` are the pool's ids in this server, or the
+    priors' configurations (IcrConfig) to submit by configuration. A request that can
+    never fit the server's memory budget is refused at submission: its latency is NaN
+    and its batch size 0."""
     ids_for = list(plan_ids)
     names = ("forward", "adjoint", "metric")
     n = len(stream.op)
@@ -227,13 +260,14 @@ def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True
             while time.perf_counter() < target:
                 pass
         op = names[int(stream.op[i])]
+        submit = server.submit_prior if isinstance(ids_for[k], B.IcrConfig) else server.submit
         try:
             if op == "forward":
-                rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_s[j])
+                rid = submit(ids_for[k], op, sl.xi[j], sl.out_s[j])
             elif op == "adjoint":
-                rid = server.submit(ids_for[k], op, sl.ybar[j], sl.out_x[j])
+                rid = submit(ids_for[k], op, sl.ybar[j], sl.out_x[j])
             else:
-                rid = server.submit(ids_for[k], op, sl.xi[j], sl.out_x[j], sl.w[j])
+                rid = submit(ids_for[k], op, sl.xi[j], sl.out_x[j], sl.w[j])
         except B.ICRError as e:
             if e.status != 4:           # only "does not fit the server's budget" is a refusal
                 raise
@@ -255,7 +289,7 @@ def run_stream(server: Server, plan_ids, pool, stream: Stream, pace: bool = True
     return lat, bs, wall
 
 
-def fine_pixels(plans, stream: Stream, served=None) -> int:
+def fine_pixels(priors, stream: Stream, served=None) -> int:
     """Fine pixels of the stream's requests (only those with served[i] True, if given)."""
     keep = np.ones(len(stream.prior), dtype=bool) if served is None else np.asarray(served)
-    return int(sum(plans[int(k)].info["n_out"] for k, ok in zip(stream.prior, keep) if ok))
+    return int(sum(priors[int(k)].sizes[1] for k, ok in zip(stream.prior, keep) if ok))

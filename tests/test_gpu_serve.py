@@ -12,6 +12,7 @@ import math
 import numpy as np
 import pytest
 
+import workloads as W
 from tests import icr_cases as C
 
 pytestmark = pytest.mark.gpu
@@ -213,4 +214,129 @@ def test_idle_graphs_are_evicted_for_a_large_request():
     from paper_2402_16683_amd import icr as B
     assert torch.equal(out_b, B.icr_metric_apply(big, w, v[None])[0])
     assert torch.equal(out_s, B.icr_forward(small, xs[None])[0])
+    server.close()
+
+
+# --- grouped mode: requests of any prior and op share launches ----------------------
+
+def _serve_one_at_a_time(server, ids, r):
+    rid = server.submit(ids[r["k"]], r["op"], r["inp"], r["out"], r["w"] if r["op"] == "metric" else None)
+    server.drain(60.0)
+    return server.query(rid)
+
+
+def _oracle_check(reqs, models):
+    for r in reqs:
+        c, m = POOL[r["k"]], models[r["k"]]
+        inp = C.to_numpy(r["inp"])
+        if r["op"] == "forward":
+            ref = m.forward(inp)
+        elif r["op"] == "adjoint":
+            ref = m.adjoint(inp)
+        else:
+            ref = m.metric(C.to_numpy(r["w"]), inp)
+        got = C.to_numpy(r["out"])
+        assert np.all(np.isfinite(got)), (c["name"], r["op"])
+        rms, mx = C.rel_errors(got, ref)
+        tol_rms, tol_max = C.TOL[c["precision"]]
+        assert rms <= tol_rms and mx <= tol_max, (c["name"], r["op"], rms, mx)
+
+
+@pytest.mark.parametrize("group_streams", [1, 2])
+def test_grouped_requests_match_the_oracle_and_their_results_alone(group_streams):
+    """Every prior of the pool (1-D, 2-D, 3-D, charted, FP32 and BF16) with every op, in
+    groups sharing launches: each result matches the FP64 oracle and equals, bit for bit,
+    the same request served alone by a grouped server."""
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    models = [C.oracle_model(c) for c in POOL]
+    server = Server(hbm_budget_bytes=1 << 30, max_batch=16, n_streams=4, use_graphs=False, grouped=True,
+                    large_step=1 << 40, group_streams=group_streams)
+    reqs = _requests(plans, 150, seed=21)
+    info = _serve(server, plans, reqs)
+    assert all(q[0] for q in info)
+    torch.cuda.synchronize()
+    st = server.stats()
+    assert st["grouped_requests"] == 150 and st["batches"] == 0
+    assert st["groups"] < 150                    # requests shared launches
+    assert max(q[4] for q in info) > 1
+    _oracle_check(reqs, models)
+    alone = Server(hbm_budget_bytes=1 << 30, max_batch=16, n_streams=1, use_graphs=False, grouped=True,
+                   large_step=1 << 40)
+    ids = [alone.register(p) for p in plans]
+    for r in reqs[:60]:
+        mixed = r["out"].clone()
+        r["out"].fill_(float("nan"))
+        q = _serve_one_at_a_time(alone, ids, r)
+        torch.cuda.synchronize()
+        assert q[0] and q[4] == 1
+        assert torch.equal(r["out"], mixed), (r["k"], r["op"])
+    alone.close()
+    server.close()
+
+
+def test_grouped_and_homogeneous_paths_together():
+    """With a small large-step size some priors run as homogeneous batches beside the
+    groups; all results match the oracle, and a tight budget defers admissions."""
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    plans = _plans()
+    models = [C.oracle_model(c) for c in POOL]
+    for budget in (1 << 30, 3 * max(p.info["n_xi"] * 4 * 4 for p in plans)):
+        server = Server(hbm_budget_bytes=budget, max_batch=8, n_streams=4, use_graphs=False, grouped=True,
+                        large_step=2000, group_streams=2)
+        reqs = _requests(plans, 100, seed=22)
+        info = _serve(server, plans, reqs)
+        assert all(q[0] for q in info)
+        torch.cuda.synchronize()
+        st = server.stats()
+        assert st["grouped_requests"] > 0 and st["batched_requests"] > 0 and st["arena_in_use"] == 0
+        _oracle_check(reqs, models)
+        server.close()
+
+
+def test_submission_by_configuration_builds_caches_and_evicts_plans():
+    """Requests by prior configuration: the server builds each new configuration's plan
+    once (a builder thread, inside the request's latency), serves later requests from the
+    cache, evicts idle plans beyond max_plans, and reports a failed build through the
+    request's query."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    from paper_2402_16683_amd.serve import Server
+    cases = POOL[:4]
+    cfgs = [B.make_config(c["ndim"], c["shape0"], c["depth"], c["delta0"], kernel=c["kernel"], length=c["length"],
+                          chart=c["chart"], chart_params=c["chart_params"], precision=c["precision"]) for c in cases]
+    models = [C.oracle_model(c) for c in cases]
+    server = Server(hbm_budget_bytes=1 << 30, max_batch=8, n_streams=4, use_graphs=False, grouped=True,
+                    large_step=1 << 40, max_plans=2)
+    rng = np.random.default_rng(23)
+    done = []
+    for i in range(40):
+        k = int(rng.integers(0, 4))
+        n_xi = models[k].n_xi
+        v = torch.from_numpy(W.standard_normal(n_xi, seed=100 + i)).float().cuda()
+        out = torch.full((models[k].out_size,), float("nan"), device="cuda")
+        rid = server.submit_prior(cfgs[k], "forward", v, out)
+        done.append((rid, k, v, out))
+        if i % 10 == 9:
+            server.drain(60.0)
+    server.drain(60.0)
+    torch.cuda.synchronize()
+    for rid, k, v, out in done:
+        assert server.query(rid)[0]
+        rms, _ = C.rel_errors(C.to_numpy(out), models[k].forward(C.to_numpy(v)))
+        assert rms <= 1e-5
+    st = server.stats()
+    assert st["plans_built"] >= 4 and st["plan_cache_hits"] > 0 and st["completed"] == 40
+    # an indefinite configuration with clamping disabled fails to build
+    bad = B.make_config(2, (16, 16), 7, (128 / 1540,) * 2, kernel="sqexp", length=0.05, clamp=False)
+    n_xi = sum((2 ** l * (16 - 4) + 4) ** 2 if l else 256 for l in range(8))
+    v = torch.zeros(n_xi, device="cuda")
+    out = torch.zeros(1540 * 1540, device="cuda")
+    rid = server.submit_prior(bad, "forward", v, out)
+    server.drain(120.0)
+    with pytest.raises(B.ICRError) as e:
+        server.query(rid)
+    assert e.value.status == 2
     server.close()
