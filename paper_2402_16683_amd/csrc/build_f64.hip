@@ -76,91 +76,36 @@ __device__ double distance(const double* a, const double* b) {
   return sqrt(s);
 }
 
-// Conditioning matrices of one window. win: [NW][D], kid: [NC][D] physical
-// positions. Writes R [NC][NW] and sqrtD [NC][NC] (lower). Returns the number of
-// clamped pivots, or -1 if K_cc is not positive definite or a pivot of D needed
-// clamping with clamping disabled.
-// Derivatives with respect to the length scale of a window's R and sqrtD (dr_out,
-// ds_out; skipped when null): R K_cc = K_fc gives dR = (dK_fc - R dK_cc) K_cc^-1,
-// D = K_ff - R K_cf gives dD = dK_ff - dR K_cf - R dK_cf, and with dD = dS S^T + S dS^T,
-// dS = S Phi(S^-1 dD S^-T), Phi the lower triangle with its diagonal halved. A clamped
-// column of sqrtD (zero pivot) leaves dS undefined: returns -2 then.
+// Conditioning matrices of one window, computed by one 64-lane workgroup with the
+// matrices in LDS. win: [NW][D], kid: [NC][D] physical positions. Writes R [NC][NW] and
+// sqrtD [NC][NC] (lower) and returns, uniformly, the number of clamped pivots, or -1 if
+// K_cc is not positive definite or a pivot of D needed clamping with clamping disabled.
+//   K_cc = L L^T (right-looking, column by column; lanes share each column's scaling and
+//   the trailing update), R^T = K_cc^-1 K_cf by forward and backward substitution with
+//   the eight right-hand sides side by side, D = K_ff - R K_cf (symmetrised) one entry
+//   per lane, sqrtD = the clamped lower Cholesky factor of D (lane 0: 8 x 8).
+// Derivatives with respect to the length scale (dr_out, ds_out; skipped when null) are
+// computed by lane 0 afterwards from the same LDS matrices (condition_derivatives).
 template <int D>
-__device__ int condition_window(const KernelSpec& ks, const double* win, const double* kid,
-                                double tau, bool clamp, double* r_out, double* s_out,
-                                double* dr_out = nullptr, double* ds_out = nullptr) {
+struct WindowLds {
+  static constexpr int NW = pow3(D);
+  static constexpr int NC = 1 << D;
+  double lc[NW * NW];   // K_cc, then its lower factor (full rows)
+  double kfc[NC * NW];
+  double r[NC * NW];
+  double dm[NC * NC];
+  double s[NC * NC];
+  double win[NW * D];
+  double kid[NC * D];
+  int result;
+};
+
+template <int D>
+__device__ int condition_derivatives(const KernelSpec& ks, const double* win, const double* kid, double* lc,
+                                     double* kfc, double* r_out, double* s_out, double* dm, int clamped,
+                                     double* dr_out, double* ds_out) {
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
-  double lc[NW * NW];   // K_cc, factorised in place (lower)
-  double kfc[NC * NW];
-  double dm[NC * NC];
-  for (int i = 0; i < NW; ++i)
-    for (int j = 0; j <= i; ++j)
-      lc[i * NW + j] = kernel_value(ks, distance<D>(win + i * D, win + j * D));
-  for (int b = 0; b < NC; ++b)
-    for (int w = 0; w < NW; ++w)
-      kfc[b * NW + w] = kernel_value(ks, distance<D>(kid + b * D, win + w * D));
-
-  // Cholesky of K_cc, no clamping (R needs its inverse)
-  for (int j = 0; j < NW; ++j) {
-    double piv = lc[j * NW + j];
-    for (int k = 0; k < j; ++k) piv -= lc[j * NW + k] * lc[j * NW + k];
-    if (!(piv > 0.0)) return -1;
-    const double root = sqrt(piv);
-    lc[j * NW + j] = root;
-    for (int i = j + 1; i < NW; ++i) {
-      double v = lc[i * NW + j];
-      for (int k = 0; k < j; ++k) v -= lc[i * NW + k] * lc[j * NW + k];
-      lc[i * NW + j] = v / root;
-    }
-  }
-  // R[b, :] = K_cc^-1 K_cf[:, b]: forward then backward substitution
-  for (int b = 0; b < NC; ++b) {
-    double* x = r_out + b * NW;
-    for (int i = 0; i < NW; ++i) {
-      double v = kfc[b * NW + i];
-      for (int k = 0; k < i; ++k) v -= lc[i * NW + k] * x[k];
-      x[i] = v / lc[i * NW + i];
-    }
-    for (int i = NW - 1; i >= 0; --i) {
-      double v = x[i];
-      for (int k = i + 1; k < NW; ++k) v -= lc[k * NW + i] * x[k];
-      x[i] = v / lc[i * NW + i];
-    }
-  }
-  // D = K_ff - R K_cf, symmetrised
-  for (int b = 0; b < NC; ++b)
-    for (int c = 0; c < NC; ++c) {
-      double v = kernel_value(ks, distance<D>(kid + b * D, kid + c * D));
-      for (int w = 0; w < NW; ++w) v -= r_out[b * NW + w] * kfc[c * NW + w];
-      dm[b * NC + c] = v;
-    }
-  for (int b = 0; b < NC; ++b)
-    for (int c = 0; c < b; ++c) {
-      const double m = 0.5 * (dm[b * NC + c] + dm[c * NC + b]);
-      dm[b * NC + c] = m;
-      dm[c * NC + b] = m;
-    }
-  // clamped lower Cholesky of D, column by column
-  int clamped = 0;
-  for (int i = 0; i < NC * NC; ++i) s_out[i] = 0.0;
-  for (int j = 0; j < NC; ++j) {
-    double piv = dm[j * NC + j];
-    for (int k = 0; k < j; ++k) piv -= s_out[j * NC + k] * s_out[j * NC + k];
-    if (!(piv > tau)) {
-      if (!clamp) return -1;
-      ++clamped;  // column j stays zero
-      continue;
-    }
-    const double root = sqrt(piv);
-    s_out[j * NC + j] = root;
-    for (int i = j + 1; i < NC; ++i) {
-      double v = dm[i * NC + j];
-      for (int k = 0; k < j; ++k) v -= s_out[i * NC + k] * s_out[j * NC + k];
-      s_out[i * NC + j] = v / root;
-    }
-  }
-  if (!dr_out) return clamped;
   if (clamped > 0) return -2;
   // dR rows: K_cc dR[b,:]^T = dK_fc[b,:]^T - dK_cc R[b,:]^T, solved with the factor of K_cc
   for (int b = 0; b < NC; ++b) {
@@ -225,6 +170,109 @@ __device__ int condition_window(const KernelSpec& ks, const double* win, const d
   return 0;
 }
 
+template <int D>
+__device__ int condition_window(const KernelSpec& ks, WindowLds<D>& w, double tau, bool clamp, double* r_out,
+                                double* s_out, double* dr_out, double* ds_out) {
+  constexpr int NW = pow3(D);
+  constexpr int NC = 1 << D;
+  const int lane = threadIdx.x;
+  constexpr int kLanes = 64;
+  for (int e = lane; e < NW * NW; e += kLanes) {
+    const int i = e / NW, j = e % NW;
+    w.lc[e] = kernel_value(ks, distance<D>(w.win + i * D, w.win + j * D));
+  }
+  for (int e = lane; e < NC * NW; e += kLanes) {
+    const int b = e / NW, c = e % NW;
+    w.kfc[e] = kernel_value(ks, distance<D>(w.kid + b * D, w.win + c * D));
+    w.r[e] = w.kfc[e];
+  }
+  if (lane == 0) w.result = 0;
+  __syncthreads();
+  // Cholesky of K_cc, no clamping (R needs its inverse)
+  for (int j = 0; j < NW; ++j) {
+    const double piv = w.lc[j * NW + j];
+    if (!(piv > 0.0)) return -1;  // uniform: every lane read the same pivot
+    const double root = sqrt(piv);
+    __syncthreads();
+    for (int i = j + 1 + lane; i < NW; i += kLanes) w.lc[i * NW + j] /= root;
+    if (lane == 0) w.lc[j * NW + j] = root;
+    __syncthreads();
+    const int m = NW - j - 1;
+    for (int e = lane; e < m * m; e += kLanes) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) w.lc[i * NW + k] -= w.lc[i * NW + j] * w.lc[k * NW + j];
+    }
+    __syncthreads();
+  }
+  // R rows: L y = K_cf[:, b], then L^T x = y, all eight right-hand sides at once
+  for (int i = 0; i < NW; ++i) {
+    if (lane < NC) w.r[lane * NW + i] /= w.lc[i * NW + i];
+    __syncthreads();
+    const int m = NW - i - 1;
+    for (int e = lane; e < NC * m; e += kLanes) {
+      const int b = e / m, k = i + 1 + e % m;
+      w.r[b * NW + k] -= w.lc[k * NW + i] * w.r[b * NW + i];
+    }
+    __syncthreads();
+  }
+  for (int i = NW - 1; i >= 0; --i) {
+    if (lane < NC) w.r[lane * NW + i] /= w.lc[i * NW + i];
+    __syncthreads();
+    for (int e = lane; e < NC * i; e += kLanes) {
+      const int b = e / i, k = e % i;
+      w.r[b * NW + k] -= w.lc[i * NW + k] * w.r[b * NW + i];
+    }
+    __syncthreads();
+  }
+  // D = K_ff - R K_cf, symmetrised
+  double dv = 0.0;
+  if (lane < NC * NC) {
+    const int b = lane / NC, c = lane % NC;
+    dv = kernel_value(ks, distance<D>(w.kid + b * D, w.kid + c * D));
+    for (int k = 0; k < NW; ++k) dv -= w.r[b * NW + k] * w.kfc[c * NW + k];
+    w.dm[lane] = dv;
+  }
+  __syncthreads();
+  if (lane < NC * NC) {
+    const int b = lane / NC, c = lane % NC;
+    dv = b == c ? w.dm[lane] : 0.5 * (w.dm[b * NC + c] + w.dm[c * NC + b]);
+  }
+  __syncthreads();
+  if (lane < NC * NC) w.dm[lane] = dv;
+  for (int e = lane; e < NC * NW; e += kLanes) r_out[e] = w.r[e];
+  __syncthreads();
+  // clamped lower Cholesky of D, column by column (lane 0)
+  if (lane == 0) {
+    int clamped = 0;
+    for (int i = 0; i < NC * NC; ++i) w.s[i] = 0.0;
+    for (int j = 0; j < NC && clamped >= 0; ++j) {
+      double piv = w.dm[j * NC + j];
+      for (int k = 0; k < j; ++k) piv -= w.s[j * NC + k] * w.s[j * NC + k];
+      if (!(piv > tau)) {
+        if (!clamp) {
+          clamped = -1;
+          break;
+        }
+        ++clamped;  // column j stays zero
+        continue;
+      }
+      const double root = sqrt(piv);
+      w.s[j * NC + j] = root;
+      for (int i = j + 1; i < NC; ++i) {
+        double v = w.dm[i * NC + j];
+        for (int k = 0; k < j; ++k) v -= w.s[i * NC + k] * w.s[j * NC + k];
+        w.s[i * NC + j] = v / root;
+      }
+    }
+    for (int i = 0; i < NC * NC; ++i) s_out[i] = w.s[i];
+    if (clamped >= 0 && dr_out)
+      clamped = condition_derivatives<D>(ks, w.win, w.kid, w.lc, w.kfc, r_out, s_out, w.dm, clamped, dr_out, ds_out);
+    w.result = clamped;
+  }
+  __syncthreads();
+  return w.result;
+}
+
 struct LevelGeom {
   double origin[3];   // index-space origin o_l per axis (natural axis order)
   double spacing[3];  // delta_l per axis
@@ -233,17 +281,18 @@ struct LevelGeom {
   int shell;          // one set per interior index of the first axis, at pixel (c, 1, 1)
 };
 
-// One thread per set: a stationary level has one set, a charted level one per
+// One 64-lane workgroup per set: a stationary level has one set, a charted level one per
 // interior coarse pixel (C order) or one per radial shell.
 template <int D>
-__global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, double tau, int clamp,
-                                   double* __restrict__ r64, double* __restrict__ s64,
-                                   double* __restrict__ dr64, double* __restrict__ ds64,
-                                   int32_t* __restrict__ count, int32_t* __restrict__ status) {
+__global__ void __launch_bounds__(64) build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, double tau,
+                                                         int clamp, double* __restrict__ r64, double* __restrict__ s64,
+                                                         double* __restrict__ dr64, double* __restrict__ ds64,
+                                                         int32_t* __restrict__ count, int32_t* __restrict__ status) {
   constexpr int NW = pow3(D);
   constexpr int NC = 1 << D;
-  const int64_t set = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (set >= g.nsets) return;
+  __shared__ WindowLds<D> w;
+  const int64_t set = blockIdx.x;
+  const int lane = threadIdx.x;
   double centre[D];
   if (cs.chart == ICR_CHART_REGULAR) {
     for (int a = 0; a < D; ++a) centre[a] = 0.0;  // only relative positions matter
@@ -257,25 +306,26 @@ __global__ void build_level_kernel(KernelSpec ks, ChartSpec cs, LevelGeom g, dou
       centre[a] = g.origin[a] + ca * g.spacing[a];
     }
   }
-  double win[NW * D], kid[NC * D], pt[D];
-  for (int w = 0; w < NW; ++w) {
-    int rem = w;
+  double pt[D];
+  if (lane < NW) {
+    int rem = lane;
     for (int a = D - 1; a >= 0; --a) {
       pt[a] = centre[a] + ((rem % 3) - 1) * g.spacing[a];
       rem /= 3;
     }
-    chart_map<D>(cs, pt, win + w * D);
+    chart_map<D>(cs, pt, w.win + lane * D);
   }
-  for (int b = 0; b < NC; ++b) {
+  if (lane < NC) {
     for (int a = 0; a < D; ++a) {
-      const int ba = (b >> (D - 1 - a)) & 1;
+      const int ba = (lane >> (D - 1 - a)) & 1;
       pt[a] = centre[a] + (ba - 0.5) * 0.5 * g.spacing[a];
     }
-    chart_map<D>(cs, pt, kid + b * D);
+    chart_map<D>(cs, pt, w.kid + lane * D);
   }
-  const int n = condition_window<D>(ks, win, kid, tau, clamp != 0, r64 + set * NC * NW,
-                                    s64 + set * NC * NC, dr64 ? dr64 + set * NC * NW : nullptr,
-                                    ds64 ? ds64 + set * NC * NC : nullptr);
+  __syncthreads();
+  const int n = condition_window<D>(ks, w, tau, clamp != 0, r64 + set * NC * NW, s64 + set * NC * NC,
+                                    dr64 ? dr64 + set * NC * NW : nullptr, ds64 ? ds64 + set * NC * NC : nullptr);
+  if (lane != 0) return;
   if (n == -2) atomicOr(status, 4);
   else if (n < 0) atomicOr(status, 1);
   else if (n > 0) atomicAdd(count, n);
@@ -344,38 +394,73 @@ __global__ void dl00_product_kernel(const double* __restrict__ low, const double
 // Blocked right-looking Cholesky of the n x n matrix a (row-major, in place, lower) in
 // panels of kPanel columns. A pivot at or below tau makes its column zero and is
 // counted; a zero column leaves the rest of the matrix unchanged. The blocked order only
-// regroups the same updates: each panel is factored column by column by one workgroup
-// (rows j0 .. n-1), then one workgroup per 32 x 32 tile of the trailing lower triangle
-// subtracts the panel's contribution.
+// regroups the same updates: each panel's diagonal block is factored column by column in
+// LDS by one workgroup and the rows below it solved against that factor, then one
+// workgroup per 32 x 32 tile of the trailing lower triangle subtracts the panel's
+// contribution.
 constexpr int kPanel = 32;
 
 __global__ void __launch_bounds__(1024) chol_panel_kernel(double* __restrict__ a, int64_t n, int64_t j0, double tau,
                                                           int clamp, int32_t* __restrict__ count,
                                                           int32_t* __restrict__ status) {
+  // the diagonal block A11 (rows and columns j0 .. j1-1) is factored in LDS by the
+  // workgroup, column by column; then each thread solves rows of the panel below it,
+  // x L11^T = a[i][j0 .. j1-1], a clamped column giving zeros
+  __shared__ double l11[kPanel][kPanel + 1];
+  __shared__ int zero_col[kPanel];
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
   const int64_t j1 = j0 + kPanel < n ? j0 + kPanel : n;
+  const int nb = static_cast<int>(j1 - j0);
+  for (int e = tid; e < kPanel * kPanel; e += nthreads) {
+    const int r = e / kPanel, c = e % kPanel;
+    l11[r][c] = (r < nb && c <= r) ? a[(j0 + r) * n + j0 + c] : 0.0;
+  }
+  if (tid >= nb && tid < kPanel) zero_col[tid] = 1;  // columns past the matrix (last panel)
+  __syncthreads();
   int clamped = 0;
-  for (int64_t j = j0; j < j1; ++j) {
-    __syncthreads();  // the previous column's updates are complete
-    const double piv = a[j * n + j];
+  for (int j = 0; j < nb; ++j) {
+    const double piv = l11[j][j];
     __syncthreads();  // every thread holds the pivot before column j is written
-    if (!(piv > tau)) {  // uniform across the workgroup
+    const bool bad = !(piv > tau);  // uniform across the workgroup
+    if (tid == 0) zero_col[j] = bad ? 1 : 0;
+    if (bad) {
       ++clamped;
-      for (int64_t i = j + tid; i < n; i += nthreads) a[i * n + j] = 0.0;
+      if (tid > j && tid < nb) l11[tid][j] = 0.0;
+      if (tid == 0) l11[j][j] = 0.0;
+      __syncthreads();
       continue;
     }
     const double root = sqrt(piv);
-    const double inv = 1.0 / root;
-    for (int64_t i = j + 1 + tid; i < n; i += nthreads) a[i * n + j] *= inv;
-    if (tid == 0) a[j * n + j] = root;
+    if (tid > j && tid < nb) l11[tid][j] /= root;
+    if (tid == 0) l11[j][j] = root;
     __syncthreads();
-    // the panel's remaining columns: a[i][k] -= a[i][j] a[k][j], j < k < j1, k <= i
-    const int64_t cols = j1 - j - 1;
-    for (int64_t e = tid; e < (n - j - 1) * cols; e += nthreads) {
-      const int64_t i = j + 1 + e / cols, k = j + 1 + e % cols;
-      if (k <= i) a[i * n + k] -= a[i * n + j] * a[k * n + j];
+    // trailing update inside the block: one thread per (row, column) pair
+    const int i = tid / kPanel, k = tid % kPanel;
+    if (tid < kPanel * kPanel && i > j && k > j && k <= i && i < nb) l11[i][k] -= l11[i][j] * l11[k][j];
+    __syncthreads();
+  }
+  for (int e = tid; e < kPanel * kPanel; e += nthreads) {
+    const int r = e / kPanel, c = e % kPanel;
+    if (r < nb && c <= r) a[(j0 + r) * n + j0 + c] = l11[r][c];
+  }
+  // rows below the block: forward substitution against L11 (a zero column of L11 sets
+  // the row's entry to zero: the clamped column of the factor is zero)
+  for (int64_t i = j1 + tid; i < n; i += nthreads) {
+    double x[kPanel];
+    double* row = a + i * n + j0;
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) x[j] = j < nb ? row[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+      double v = x[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= x[k] * l11[j][k];
+      x[j] = zero_col[j] ? 0.0 : v / l11[j][j];
     }
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j)
+      if (j < nb) row[j] = x[j];
   }
   if (tid == 0) {
     *count += clamped;  // panels run one after another on the stream
@@ -638,8 +723,8 @@ hipError_t launch_build_level(const icr_plan* p, int level, int32_t* counts, int
   g.nsets = p->lev[level].nsets;
   g.shell = p->shell;
   const int clamp = (p->cfg.flags & ICR_FLAG_NO_CLAMP) ? 0 : 1;
-  const unsigned threads = 64;
-  const unsigned blocks = static_cast<unsigned>((g.nsets + threads - 1) / threads);
+  const unsigned threads = 64;  // one workgroup (one wavefront) per set
+  const unsigned blocks = static_cast<unsigned>(g.nsets);
   const LevelMats& m = p->lev[level];
   switch (d) {
     case 1: build_level_kernel<1><<<blocks, threads, 0, st>>>(kernel_spec(p), chart_spec(p), g, tau_of(p), clamp, m.r64, m.s64, m.dr64, m.ds64, counts, status); break;

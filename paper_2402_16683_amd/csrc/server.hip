@@ -49,6 +49,7 @@
 namespace {
 
 constexpr int kMaxBatch = 64;
+constexpr int kBuilders = 4;  // builder threads (and streams) of the plan cache
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -242,8 +243,8 @@ struct icr_server {
   std::map<std::string, CacheEntry> cache;
   std::deque<std::string> build_jobs;
   std::condition_variable build_cv;
-  std::thread builder;
-  hipStream_t build_stream = nullptr;
+  std::vector<std::thread> builders;      // builds of different configurations overlap
+  std::vector<hipStream_t> build_streams; // one per builder
   int64_t next_id = 1;
   int64_t completed = 0, batches = 0, batched_requests = 0, graph_captures = 0, admissions_deferred = 0;
   int64_t groups = 0, grouped_requests = 0, plans_built = 0, plan_cache_hits = 0;
@@ -763,8 +764,9 @@ void evict_plans(icr_server* s) {
 // Builder thread: builds the plans of new prior configurations on its own stream while
 // the worker keeps serving; the requests waiting for a plan become pending when it is
 // ready, or complete with the build's status when it fails.
-void builder_loop(icr_server* s) {
+void builder_loop(icr_server* s, int index) {
   (void)hipSetDevice(s->device);
+  hipStream_t build_stream = s->build_streams[index];
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop.load()) {
     if (s->build_jobs.empty()) {
@@ -777,7 +779,7 @@ void builder_loop(icr_server* s) {
     std::memcpy(&cfg, key.data(), sizeof(cfg));
     lk.unlock();
     icr_plan* plan = nullptr;
-    const icr_status st = icr_build_matrices(&cfg, s->build_stream, &plan);
+    const icr_status st = icr_build_matrices(&cfg, build_stream, &plan);
     const std::string msg = st == ICR_OK ? std::string() : std::string(icr_last_error());
     lk.lock();
     CacheEntry& ce = s->cache[key];
@@ -872,7 +874,12 @@ icr_status icr_server_create(const icr_server_config* cfg, icr_server** out) {
   s->inflight.assign(cfg->n_streams, nullptr);
   s->grouped.assign(cfg->n_streams, nullptr);
   s->table_tasks = size_t(kMaxSteps) * kMaxBatch;
-  bool ok = hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) == hipSuccess;
+  bool ok = true;
+  for (int i = 0; i < kBuilders && ok; ++i) {
+    hipStream_t bs = nullptr;
+    ok = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) == hipSuccess;
+    if (ok) s->build_streams.push_back(bs);
+  }
   for (int i = 0; i < cfg->n_streams && ok; ++i) {
     void* h = nullptr;
     void* d = nullptr;
@@ -887,13 +894,13 @@ icr_status icr_server_create(const icr_server_config* cfg, icr_server** out) {
     for (void* d : s->dev_tables)
       if (d) (void)hipFree(d);
     for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
-    if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+    for (hipStream_t x : s->build_streams) (void)hipStreamDestroy(x);
     delete s;
     icr::set_error("could not allocate the server's step tables or build stream");
     return ICR_ERR_OUT_OF_MEMORY;
   }
   s->worker = std::thread(worker_loop, s);
-  s->builder = std::thread(builder_loop, s);
+  for (int i = 0; i < kBuilders; ++i) s->builders.emplace_back(builder_loop, s, i);
   *out = s;
   return ICR_OK;
 }
@@ -1110,11 +1117,12 @@ icr_status icr_server_destroy(icr_server* s) {
   if (!s) return ICR_OK;
   s->stop.store(true);
   s->cv.notify_one();
-  s->build_cv.notify_one();
+  s->build_cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  if (s->builder.joinable()) s->builder.join();
+  for (std::thread& b : s->builders)
+    if (b.joinable()) b.join();
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-  if (s->build_stream) (void)hipStreamSynchronize(s->build_stream);
+  for (hipStream_t st : s->build_streams) (void)hipStreamSynchronize(st);
   for (Batch* b : s->inflight) delete b;
   for (Group* g : s->grouped) delete g;
   for (auto& kv : s->requests) {
@@ -1127,7 +1135,7 @@ icr_status icr_server_destroy(icr_server* s) {
     if (h) (void)hipHostFree(h);
   for (void* d : s->dev_tables)
     if (d) (void)hipFree(d);
-  if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
+  for (hipStream_t st : s->build_streams) (void)hipStreamDestroy(st);
   for (auto& kv : s->graphs)
     for (Graph* g : kv.second) {
       if (g->exec) (void)hipGraphExecDestroy(g->exec);
