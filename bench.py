@@ -469,10 +469,10 @@ def mgvi_bench(B, plan, wl: dict, pairs: int, quiet: bool) -> dict:
     ms = iteration_ms()
     products = pairs * 100 + 35 + 1   # metric products on single samples (the samples' CG runs batched)
     # the paper's example stops the samples' CG by the energy change: absdelta = 1e-4 size / 10,
-    # at most 100 steps; also with a threshold 100x lower (on this metric the first steps
+    # at most 100 steps; also with a threshold 10x lower (on this metric the first steps
     # lower the energy by about as much as the example's threshold)
     rules = []
-    for scale in (1.0, 0.01):
+    for scale in (1.0, 0.1):
         absdelta = scale * 1e-4 * n_xi / 10.0
         done = torch.zeros(pairs, dtype=torch.int32, device="cuda")
         ms_sl = iteration_ms(absdelta, done)

@@ -706,6 +706,15 @@ bool sector_eligible(const icr_plan* p, int level) {
   return nf < (int64_t(1) << 31);
 }
 
+// Compute units of the current device (256 on MI355X).
+int64_t compute_units() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 256;
+  return cus;
+}
+
 // Workgroups of `kernel` that the device holds at once (occupancy x compute units).
 int64_t resident_workgroups(const void* kernel, int threads) {
   int dev = 0, cus = 0, per_cu = 0;
@@ -746,14 +755,13 @@ hipError_t fwd_launch(const icr_plan* p, int level, const M& k, const RefineFwdA
   g.nfy = p->shapes[level + 1][1];
   g.nfx = p->shapes[level + 1][2];
   const int64_t xy_blocks = (int64_t(g.rows) * g.pairs + 255) / 256;
-  static const int64_t slots =
-      resident_workgroups(reinterpret_cast<const void*>(refine3_fwd_sector<TS, false, M>), 256);
+  // one workgroup per compute unit, each marching as many planes as that takes: the
+  // 196^3 -> 388^3 forward runs in 94 us as 3 chunks of 65 planes (222 workgroups),
+  // against 103 us in 10 chunks (four workgroups per compute unit), 111 us in 2 and
+  // 125 us in 4 (296 workgroups: a second, partial round); the 100^3 -> 196^3 forward
+  // is as fast in 12 or 13 chunks and slower below 8 planes per chunk
+  static const int64_t slots = compute_units();
   int64_t chunks = pick_chunks(xy_blocks, g.nz - 2, a.batch < 65535 ? a.batch : 65535, slots);
-  {  // mid-size levels: at least 8 planes per workgroup while ~200 workgroups remain (the
-     // 100^3 -> 196^3 forward: 98 planes in 12 chunks instead of 40; the step 3 us shorter)
-    const int64_t c8 = (g.nz - 2) / 8;
-    if (c8 >= 1 && c8 < chunks && xy_blocks * c8 * (a.batch < 65535 ? a.batch : 65535) >= 192) chunks = c8;
-  }
   g.zchunk = static_cast<int>((g.nz - 2 + chunks - 1) / chunks);
   const int64_t nchunks = (g.nz - 2 + g.zchunk - 1) / g.zchunk;
   g.xy_blocks = static_cast<int>(xy_blocks);

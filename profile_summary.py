@@ -3,12 +3,19 @@
     python profile_summary.py trace <dir>               # --kernel-trace --stats run
     python profile_summary.py counters <dir> <counter>  # --pmc run (FETCH_SIZE / WRITE_SIZE)
     python profile_summary.py traffic <fetch_dir> <write_dir> <workload> <precision>
+    python profile_summary.py pmc <dir> [<dir> ...]           # --pmc runs, any counters
 
 `trace` groups dispatches by kernel and grid (so the levels of one kernel are told
 apart) and reports count and average / min / max duration in microseconds.
 `counters` reports the counter per dispatch group in KiB, and the ratio of that
 counter to the known bytes of the copy probe (a 256 MiB device-to-device tensor copy
 that `bench.py --copy-probe` runs), which calibrates bytes per counter unit.
+`pmc` merges --pmc runs of the same command (one counter group each) per dispatch group
+and prints, for the groups with the most wave cycles, the per-launch averages and
+ratios: L2 (TCC) hit rate; bytes the L2 read from and wrote to memory from its request
+counters (32-, 64- and 128-byte read requests, 32- and 64-byte write requests); VALU,
+vector-memory and LDS instructions per wave; waiting and LDS bank-conflict cycles
+against wave cycles.
 `traffic` combines a FETCH_SIZE run and a WRITE_SIZE run of `bench.py --copy-probe`
 into HBM bytes per launch of the last-level forward and adjoint sweep kernels (the
 largest dispatch group of each), prints the summary and records it in
@@ -143,11 +150,55 @@ def counters(d: str, counter: str):
         print(f"{name[:70]:70s} {grid:>12s} {len(v):6d} {sum(v) / len(v):14.1f}")
 
 
+def pmc(dirs):
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        with open(_find(d, "counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                key = (short_name(row["Kernel_Name"]), row.get("Grid_Size", "?"))
+                vals[key][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+    calls = {k: max(len(v) for v in cs.values()) for k, cs in vals.items()}
+    order = sorted(avg, key=lambda k: -avg[k].get("SQ_WAVE_CYCLES", 0.0) * calls[k])
+    print(f"# sources: {', '.join(dirs)}; per-launch averages of each dispatch group")
+    for key in order[:12]:
+        c = avg[key]
+        g = lambda n: c.get(n, c.get(n + "_sum"))
+        parts = [f"{key[0]} grid {key[1]} ({calls[key]} launches)"]
+        hit, miss = g("TCC_HIT"), g("TCC_MISS")
+        if hit is not None and miss is not None and hit + miss > 0:
+            parts.append(f"L2 hit {hit / (hit + miss):.3f}")
+        rd, rd32, rd128 = g("TCC_EA0_RDREQ"), g("TCC_EA0_RDREQ_32B"), g("TCC_EA0_RDREQ_128B")
+        if rd is not None and rd32 is not None and rd128 is not None:
+            parts.append(f"read {(32 * rd32 + 128 * rd128 + 64 * (rd - rd32 - rd128)) / 1e6:.1f} MB "
+                         f"({rd128 / max(rd, 1):.2f} of requests 128 B)")
+        wr, wr64 = g("TCC_EA0_WRREQ"), g("TCC_EA0_WRREQ_64B")
+        if wr is not None and wr64 is not None:
+            parts.append(f"written {(64 * wr64 + 32 * (wr - wr64)) / 1e6:.1f} MB")
+        waves = g("SQ_WAVES")
+        if waves:
+            for n, label in (("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_VMEM", "VMEM"), ("SQ_INSTS_LDS", "LDS"),
+                             ("SQ_INSTS_SALU", "SALU")):
+                if g(n) is not None:
+                    parts.append(f"{label}/wave {g(n) / waves:.0f}")
+        cyc = g("SQ_WAVE_CYCLES")
+        if cyc:
+            if g("SQ_WAIT_INST_ANY") is not None:
+                parts.append(f"waiting {g('SQ_WAIT_INST_ANY') / cyc:.2f} of wave cycles")
+            if g("SQ_ACTIVE_INST_VALU") is not None:
+                parts.append(f"VALU issue {g('SQ_ACTIVE_INST_VALU') / cyc:.3f} of wave cycles")
+        if g("SQ_LDS_BANK_CONFLICT") is not None and g("SQ_INSTS_LDS"):
+            parts.append(f"LDS bank-conflict cycles/LDS instruction {g('SQ_LDS_BANK_CONFLICT') / g('SQ_INSTS_LDS'):.2f}")
+        print("; ".join(parts))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "trace":
         trace(sys.argv[2])
     elif len(sys.argv) >= 4 and sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 3 and sys.argv[1] == "pmc":
+        pmc(sys.argv[2:])
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
         traffic(*sys.argv[2:6])
     else:
