@@ -11,9 +11,10 @@
  * integer harmonic numbers |k| (the shorter way round the periodic grid) with
  * A(0) = zero_mode. The Poisson rate is lambda(xi) = exp(m + T(A xi)), so
  *   M_p v = v + A T(lambda(p) T(A v)).
- * All buffers are FP32 device arrays of n x n elements (row-major), caller-owned; one
- * sample per call; calls are asynchronous on hip_stream and allocate nothing (except
- * icr_cf_create, which allocates A). Status codes as in icr.h.
+ * All buffers are FP32 device arrays of n x n elements (row-major, 16-byte aligned),
+ * caller-owned; one sample per call; calls are asynchronous on hip_stream and allocate
+ * nothing (except icr_cf_create, which allocates A and the FFT twiddles). Status codes
+ * as in icr.h.
  */
 #ifndef ICR_CF_H
 #define ICR_CF_H
@@ -32,7 +33,8 @@ typedef struct icr_cf_plan icr_cf_plan;  /* opaque; owns the device amplitude sp
  * slope and offset_mean m finite. Synchronous. */
 icr_status icr_cf_create(int32_t n, double amplitude, double zero_mode, double length, double slope,
                          double offset_mean, void* hip_stream, icr_cf_plan** out_plan);
-/* Device workspace for the calls below: 12 n^2 bytes (three real grids). */
+/* Device workspace for the calls below: 4 n^2 bytes (one real grid, in the transforms'
+ * column-blocked order). */
 icr_status icr_cf_workspace_bytes(const icr_cf_plan* plan, int64_t* bytes);
 /* Copy A (FP32, n x n) to host memory. Synchronous. */
 icr_status icr_cf_copy_amplitude(const icr_cf_plan* plan, float* amp);

@@ -73,3 +73,15 @@ def test_invalid_sizes_are_rejected():
         with pytest.raises(B.ICRError) as exc:
             CorrelatedField(n)
         assert exc.value.status == 1 and "power of two" in str(exc.value)
+
+
+def test_misaligned_buffers_are_rejected():
+    import torch
+    from paper_2402_16683_amd import icr as B
+    from paper_2402_16683_amd.cf import CorrelatedField
+    n = 64
+    cf = CorrelatedField(n, **PARAMS)
+    x = torch.zeros(n * n + 1, dtype=torch.float32, device="cuda")[1:].reshape(n, n)  # 4 bytes off
+    with pytest.raises(B.ICRError) as exc:
+        cf.transform(x)
+    assert exc.value.status == 1 and "aligned" in str(exc.value)
