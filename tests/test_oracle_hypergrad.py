@@ -67,8 +67,9 @@ def test_conditioning_matrix_derivatives_match_finite_differences(ndim, kind, dl
 
 CFGS = [
     O.ICRConfig(ndim=1, shape0=(10,), depth=3, delta0=(0.1,), kernel="matern32", length=0.3),
-    O.ICRConfig(ndim=2, shape0=(6, 5), depth=2, delta0=(0.15, 0.12), kernel="matern52", length=0.35),
-    O.ICRConfig(ndim=3, shape0=(5, 4, 5), depth=1, delta0=(0.2, 0.25, 0.2), kernel="matern52", length=0.5),
+    O.ICRConfig(ndim=2, shape0=(6, 5), depth=2, delta0=(0.15, 0.12), kernel="matern52", scale=1.7, length=0.35),
+    O.ICRConfig(ndim=3, shape0=(5, 4, 5), depth=1, delta0=(0.2, 0.25, 0.2), kernel="matern52", scale=0.6,
+                length=0.5),
     O.ICRConfig(ndim=2, shape0=(5, 6), depth=2, delta0=(0.2, 1 / 6), kernel="matern32", length=0.1,
                 chart="logradial2d"),
     O.ICRConfig(ndim=3, shape0=(5, 5, 4), depth=1, delta0=(0.2, 0.2, 0.25), kernel="matern32", length=0.2,

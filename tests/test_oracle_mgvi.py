@@ -37,6 +37,25 @@ def test_cg_reaches_the_dense_solve():
     np.testing.assert_allclose(x, np.linalg.solve(mmat, b), rtol=1e-8, atol=1e-10)
 
 
+def test_cg_iterates_minimise_the_energy_over_the_krylov_space():
+    """After k steps from 0, CG's x_k is the minimiser of x.Mx/2 - b.x over
+    span{b, Mb, ..., M^(k-1) b} (its defining property), computed densely from an
+    orthonormal basis of that space."""
+    m, rng, w, lmat, mmat = _setup()
+    b = rng.standard_normal(m.n_xi)
+    for k in (1, 2, 3, 5, 8):
+        basis = [b]
+        for _ in range(k - 1):
+            basis.append(mmat @ basis[-1])
+        q, _ = np.linalg.qr(np.stack(basis, axis=1))
+        x_ref = q @ np.linalg.solve(q.T @ mmat @ q, q.T @ b)
+        x = O.conjugate_gradient(lambda v: m.metric(w, v), b, k)
+        np.testing.assert_allclose(x, x_ref, rtol=1e-7, atol=1e-9 * np.abs(x_ref).max())
+        xs, steps, _ = O.conjugate_gradient_sl(lambda v: m.metric(w, v), b, -np.inf, k)
+        assert steps == k
+        np.testing.assert_allclose(xs, x_ref, rtol=1e-7, atol=1e-9 * np.abs(x_ref).max())
+
+
 def test_drawn_sample_solves_the_metric_system():
     m, rng, w, lmat, mmat = _setup()
     eta, eta_d = rng.standard_normal(m.n_xi), rng.standard_normal(m.out_size)

@@ -97,6 +97,19 @@ def test_clamped_cholesky_clamps_rank_deficient_matrices():
         O.clamped_cholesky(a, 1e-10, clamp=False)
 
 
+def test_clamp_boundary_is_the_pivot_threshold():
+    """tau = 3^d eps k(0): a diagonal matrix (its own Schur complements) with pivots
+    just above and just below tau keeps exactly the ones above."""
+    for ndim, scale in ((1, 1.0), (2, 2.5), (3, 0.4)):
+        tau = O.pivot_threshold(ndim, scale)
+        assert tau == 3.0 ** ndim * np.finfo(np.float64).eps * scale ** 2
+        piv = np.array([scale ** 2, 1.5 * tau, 0.9 * tau, 4.0 * tau, tau])
+        low, cnt = O.clamped_cholesky(np.diag(piv), tau)
+        assert int(cnt) == 2
+        np.testing.assert_allclose(np.diag(low), [scale, np.sqrt(1.5 * tau), 0.0, 2.0 * np.sqrt(tau), 0.0],
+                                   rtol=1e-15)
+
+
 # --------------------------------------------------------------------------- conditioning
 
 @pytest.mark.parametrize("h", [0.05, 0.4, 1.7])
