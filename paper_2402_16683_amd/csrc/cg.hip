@@ -6,8 +6,10 @@
 // Per iteration, for every sample independently (x_0 = 0, r_0 = p_0 = b):
 //   q = M p;  alpha = (r.r) / (p.q);  x += alpha p;  r -= alpha q;
 //   beta = (r'.r') / (r.r);  p = r' + beta p.
-// Dot products accumulate in FP64 in a fixed order (per-block partial sums, then one
-// block sums the partials), so runs are bitwise reproducible.
+// Dot products accumulate in FP64 in a fixed order (per-block partial sums, then a
+// fixed-order sum of the partials), so runs are bitwise reproducible. Each update kernel
+// sums the partials it needs itself (every workgroup the same way), so a step is three
+// launches after the metric product: p.q partials; x, r and the r.r partials; p.
 //
 // Early stopping by the change of the CG energy E(x) = x.Mx / 2 - b.x (the "absdelta"
 // criterion of the sample-drawing CG in the paper's VI example): a step along p with the
@@ -16,22 +18,25 @@
 // r, p no longer change). Every iteration up to the maximum is enqueued at once; when the
 // last sample freezes, a device flag makes the remaining kernels (metric sweeps included)
 // return at once, so nothing waits on the host.
+#include <algorithm>
+
 #include "icr_internal.h"
 
 namespace icr {
 namespace {
 
 constexpr int kDotThreads = 256;
-constexpr int kDotBlocks = 1024;  // partial sums per sample
+constexpr int kDotBlocks = 1024;  // at most this many partial sums per sample
 
+// Per-sample state. r.r and the active flag are kept per iteration parity: the p update
+// of iteration i reads the entries of parity i and its workgroup 0 writes those of
+// parity i + 1, so no workgroup reads an entry another one writes in the same launch.
 struct CgScalars {
-  double rr;       // r.r of the current residual
-  double alpha;
-  double beta;
+  double rr[2];      // r.r at the start of an iteration
+  double alpha;      // of the last step taken
   double pq;
-  double decrease; // alpha rr / 2: the energy decrease of the current step
-  int32_t active;  // 0 once the sample has stopped
-  int32_t iters;   // steps taken
+  int32_t active[2]; // whether the sample takes the iteration
+  int32_t iters;     // steps taken
 };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -77,6 +82,27 @@ __device__ __forceinline__ void stv(T* p, const Chunk<T, V>& c) {
   }
 }
 
+// Partial sums per sample: one per workgroup of the vector kernels, which stride over
+// the sample's vector with `blocks` workgroups; `blocks` depends on n alone, so the
+// partition and every partial sum are fixed by n. At least two workgroups per compute
+// unit: on the charted 2-D workload (2.2 M elements) a CG step took 115.5, 96.7, 88.9,
+// 86.1 and 86.5 us with 64, 128, 256, 512 and 1024 workgroups.
+int dot_blocks(int64_t n, int v) {
+  const int64_t b = (n / v + int64_t(kDotThreads) * 4 - 1) / (int64_t(kDotThreads) * 4);
+  return static_cast<int>(std::min<int64_t>(kDotBlocks, std::max<int64_t>(512, b)));
+}
+
+// The sum of sample b's `blocks` partials in a fixed order, in every thread (every
+// workgroup that calls it gets the same value).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t b, int blocks,
+                                               double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < blocks; k += kDotThreads) v += partial[b * kDotBlocks + k];
+  const double s = block_sum(v, sh);
+  __syncthreads();  // sh is reused by the caller
+  return s;
+}
+
 // partial[b][blk] = sum over this block's share of a[b] * c[b]
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__ a, const T* __restrict__ c,
@@ -88,7 +114,8 @@ __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__
   const T* pa = a + b * n;
   const T* pc = c + b * n;
   double acc = 0.0;
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
     const Chunk<T, V> u = ldv<T, V>(pa + g * V), w = ldv<T, V>(pc + g * V);
 #pragma unroll
     for (int k = 0; k < V; ++k) acc += static_cast<double>(u.v[k]) * static_cast<double>(w.v[k]);
@@ -97,66 +124,35 @@ __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
-// which = 0: pq = sum, alpha = rr / pq, decrease = alpha rr / 2;
-// which = 1: rr' = sum, beta = rr' / rr, rr = rr', one more step taken, and the sample
-// stops when its step lowered the energy by less than absdelta (absdelta > 0) or r = 0
-// (also records sqrt(rr) into norms[b][iter + 1] when norms is given, frozen samples
-// repeating their last value);
-// which = 2: rr = sum (initialisation, records norms[b][0]).
-// A stopped sample's scalars no longer change.
-__global__ void __launch_bounds__(kDotThreads) dot_finish(const double* __restrict__ partial, CgScalars* sc,
-                                                          int which, double* norms, int iter, int stride,
-                                                          double absdelta, const int32_t* halt) {
-  __shared__ double sh[kDotThreads];
-  if (halted(halt)) return;
-  const int64_t b = blockIdx.x;
-  double v = 0.0;
-  for (int k = threadIdx.x; k < kDotBlocks; k += kDotThreads) v += partial[b * kDotBlocks + k];
-  const double s = block_sum(v, sh);
-  if (threadIdx.x != 0) return;
-  CgScalars& c = sc[b];
-  if (which == 2) {
-    c.rr = s;
-    c.active = s != 0.0 ? 1 : 0;
-    c.iters = 0;
-    if (norms) norms[b * stride] = sqrt(s);
-    return;
-  }
-  if (!c.active) {
-    if (which == 1 && norms) norms[b * stride + iter + 1] = sqrt(c.rr);
-    return;
-  }
-  if (which == 0) {
-    c.pq = s;
-    c.alpha = s != 0.0 ? c.rr / s : 0.0;
-    c.decrease = 0.5 * c.alpha * c.rr;
-  } else {
-    c.beta = c.rr != 0.0 ? s / c.rr : 0.0;
-    c.rr = s;
-    c.iters += 1;
-    if (norms) norms[b * stride + iter + 1] = sqrt(s);
-    if (s == 0.0 || (absdelta > 0.0 && !(c.decrease >= absdelta))) c.active = 0;
-  }
-}
-
-// x += alpha p; r -= alpha q; partial sums of r.r
+// Iteration with parity `par` of an active sample: p.q from its partials, alpha =
+// (r.r) / (p.q); x += alpha p; r -= alpha q; partial sums of the new r.r. Workgroup 0
+// records p.q and alpha for the p update.
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                         const T* __restrict__ q, int64_t n, const CgScalars* sc,
-                                                         double* __restrict__ partial, const int32_t* halt) {
+                                                         const T* __restrict__ q, int64_t n, CgScalars* sc,
+                                                         const double* __restrict__ pq_partial,
+                                                         double* __restrict__ rr_partial, int par,
+                                                         const int32_t* halt) {
   __shared__ double sh[kDotThreads];
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
-  if (!sc[b].active) return;  // uniform per workgroup (one sample per grid row)
-  const T a = static_cast<T>(sc[b].alpha);
+  if (!sc[b].active[par]) return;  // uniform per workgroup (one sample per grid row)
+  const double pq = sum_partials(pq_partial, b, gridDim.x, sh);
+  const double alpha = pq != 0.0 ? sc[b].rr[par] / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[b].pq = pq;
+    sc[b].alpha = alpha;
+  }
+  const T a = static_cast<T>(alpha);
   T* px = x + b * n;
   T* pr = r + b * n;
   const T* pp = p + b * n;
-  const T* pq = q + b * n;
+  const T* pqv = q + b * n;
   double acc = 0.0;
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
     Chunk<T, V> xv = ldv<T, V>(px + g * V), rv = ldv<T, V>(pr + g * V);
-    const Chunk<T, V> pv = ldv<T, V>(pp + g * V), qv = ldv<T, V>(pq + g * V);
+    const Chunk<T, V> pv = ldv<T, V>(pp + g * V), qv = ldv<T, V>(pqv + g * V);
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       xv.v[k] += a * pv.v[k];
@@ -167,47 +163,77 @@ __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* _
     stv<T, V>(pr + g * V, rv);
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
-// p = r + beta p. With a halt flag, workgroup (0, 0) also raises it once every sample has
-// stopped: the flag is read only by later kernels.
+// End of iteration `iter` (parity par): the new r.r from its partials, beta = r'.r' / r.r,
+// and p = r + beta p. The sample stops when its step lowered the energy by less than
+// absdelta (absdelta > 0) or r = 0; its step is kept and p is no longer needed.
+// Workgroup 0 writes the sample's entries of the next parity, counts the step, records
+// the residual norm (a stopped sample repeats its last one), and when the last active
+// sample stops raises the halt flag (halt[1] counts the active samples).
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const T* __restrict__ r, int64_t n,
-                                                        const CgScalars* sc, int32_t* halt, int batch) {
+                                                        CgScalars* sc, const double* __restrict__ rr_partial, int par,
+                                                        int iter, double absdelta, double* norms, int stride,
+                                                        int32_t* halt) {
+  __shared__ double sh[kDotThreads];
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
-  if (halt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    int any = 0;
-    for (int k = 0; k < batch; ++k) any |= sc[k].active;
-    if (!any) *halt = 1;
+  const int nx = par ^ 1;
+  CgScalars& c = sc[b];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!c.active[par]) {
+    if (lead) {
+      c.active[nx] = 0;
+      c.rr[nx] = c.rr[par];
+      if (norms) norms[b * stride + iter + 1] = sqrt(c.rr[par]);
+    }
+    return;
   }
-  if (!sc[b].active) return;
-  const T beta = static_cast<T>(sc[b].beta);
+  const double rr_new = sum_partials(rr_partial, b, gridDim.x, sh);
+  const double rr = c.rr[par];
+  const double beta = rr != 0.0 ? rr_new / rr : 0.0;
+  const double decrease = 0.5 * c.alpha * rr;
+  const bool stop = rr_new == 0.0 || (absdelta > 0.0 && !(decrease >= absdelta));
+  if (lead) {
+    c.rr[nx] = rr_new;
+    c.active[nx] = stop ? 0 : 1;
+    c.iters += 1;
+    if (norms) norms[b * stride + iter + 1] = sqrt(rr_new);
+    if (stop && halt && atomicSub(&halt[1], 1) == 1) halt[0] = 1;
+  }
+  if (stop) return;
+  const T bt = static_cast<T>(beta);
   T* pp = p + b * n;
   const T* pr = r + b * n;
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
     Chunk<T, V> pv = ldv<T, V>(pp + g * V);
     const Chunk<T, V> rv = ldv<T, V>(pr + g * V);
 #pragma unroll
-    for (int k = 0; k < V; ++k) pv.v[k] = rv.v[k] + beta * pv.v[k];
+    for (int k = 0; k < V; ++k) pv.v[k] = rv.v[k] + bt * pv.v[k];
     stv<T, V>(pp + g * V, pv);
   }
 }
 
-// x = 0, r = p = b, partial sums of b.b; clears the halt flag
+// x = 0, r = p = b, partial sums of b.b; clears the halt flag and the active count
 template <typename T, int V>
 __global__ void __launch_bounds__(kDotThreads) cg_init(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                        const T* __restrict__ bvec, int64_t n,
                                                        double* __restrict__ partial, int32_t* halt) {
   __shared__ double sh[kDotThreads];
   const int64_t b = blockIdx.y;
-  if (halt && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) *halt = 0;
+  if (halt && blockIdx.x == 0 && b == 0 && threadIdx.x == 0) {
+    halt[0] = 0;
+    halt[1] = 0;
+  }
   double acc = 0.0;
   Chunk<T, V> zero;
 #pragma unroll
   for (int k = 0; k < V; ++k) zero.v[k] = T(0);
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += int64_t(kDotBlocks) * kDotThreads) {
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
     const Chunk<T, V> v = ldv<T, V>(bvec + b * n + g * V);
     stv<T, V>(x + b * n + g * V, zero);
     stv<T, V>(r + b * n + g * V, v);
@@ -219,11 +245,29 @@ __global__ void __launch_bounds__(kDotThreads) cg_init(T* __restrict__ x, T* __r
   if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = s;
 }
 
+// r.r of the start (one workgroup per sample): a sample with b = 0 takes no step; the
+// others are counted in halt[1]
+__global__ void __launch_bounds__(kDotThreads) cg_start(const double* __restrict__ partial, CgScalars* sc,
+                                                        double* norms, int stride, int blocks, int32_t* halt) {
+  __shared__ double sh[kDotThreads];
+  const int64_t b = blockIdx.x;
+  const double s = sum_partials(partial, b, blocks, sh);
+  if (threadIdx.x != 0) return;
+  CgScalars& c = sc[b];
+  c.rr[0] = c.rr[1] = s;
+  c.active[0] = s != 0.0 ? 1 : 0;
+  c.active[1] = 0;
+  c.alpha = c.pq = 0.0;
+  c.iters = 0;
+  if (norms) norms[b * stride] = sqrt(s);
+  if (halt && c.active[0]) atomicAdd(&halt[1], 1);
+}
+
 // norms[b][k] for k past the steps sample b took: its last residual norm
 __global__ void cg_fill_norms(const CgScalars* sc, double* norms, int stride) {
   const int64_t b = blockIdx.x;
   const int taken = sc[b].iters;
-  const double last = sqrt(sc[b].rr);
+  const double last = sqrt(sc[b].rr[taken & 1]);
   for (int k = taken + 1 + threadIdx.x; k < stride; k += blockDim.x) norms[b * stride + k] = last;
 }
 
@@ -236,34 +280,29 @@ __global__ void cg_report(const CgScalars* sc, int32_t* iterations_done, int bat
 template <typename T, int V>
 hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec, void* x,
                   int32_t iterations, double absdelta, int32_t* iterations_done, double* norms, void* mws, T* r,
-                  T* pv, T* q, double* partial, CgScalars* sc, int32_t* halt_flag, hipStream_t st,
-                  MetricFn metric) {
+                  T* pv, T* q, double* pq_partial, double* rr_partial, CgScalars* sc, int32_t* halt_flag,
+                  hipStream_t st, MetricFn metric) {
   const int64_t n = p->n_xi;
-  const dim3 grid(kDotBlocks, static_cast<unsigned>(batch));
+  const int blocks = dot_blocks(n, V);
+  const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(batch));
   const int stride = iterations + 1;
   const int nb = static_cast<int>(batch);
   // the halt flag only with early stopping: fixed-count runs pay nothing for it
   int32_t* halt = absdelta > 0.0 ? halt_flag : nullptr;
   T* xv = static_cast<T*>(x);
-  cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, partial, halt);
+  cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, rr_partial, halt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 2, norms, 0, stride, absdelta,
-                                                                   nullptr);
+  cg_start<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(rr_partial, sc, norms, stride, blocks, halt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int it = 0; it < iterations; ++it) {
+    const int par = it & 1;
     if ((e = metric(p, batch, w, w_bs, pv, q, mws, halt, st)) != hipSuccess) return e;
-    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, partial, halt);
+    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, pq_partial, halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 0, nullptr, it, stride, absdelta,
-                                                                     halt);
+    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, pq_partial, rr_partial, par, halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, partial, halt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    dot_finish<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(partial, sc, 1, norms, it, stride, absdelta,
-                                                                     halt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, halt, nb);
+    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride, halt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (halt && norms) {
@@ -288,9 +327,9 @@ int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch) {
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
   return up(batch * p->n_xi * el)          // metric workspace
          + 3 * up(vec)                     // r, p, q
-         + up(batch * kDotBlocks * 8)      // partial sums
+         + 2 * up(batch * kDotBlocks * 8)  // partial sums of p.q and r.r
          + up(batch * int64_t(sizeof(CgScalars)))
-         + 256;                            // halt flag
+         + 256;                            // halt flag and active count
 }
 
 hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
@@ -305,7 +344,8 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   void* r = base; base += up(batch * n * el);
   void* pv = base; base += up(batch * n * el);
   void* q = base; base += up(batch * n * el);
-  double* partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
+  double* pq_partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
+  double* rr_partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
   CgScalars* sc = reinterpret_cast<CgScalars*>(base);
   base += up(batch * int64_t(sizeof(CgScalars)));
   int32_t* halt = reinterpret_cast<int32_t*>(base);
@@ -316,17 +356,17 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   if (p->precision == ICR_F64) {
     return vec ? run_cg<double, 2>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                    static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
-                                   partial, sc, halt, st, metric)
+                                   pq_partial, rr_partial, sc, halt, st, metric)
                : run_cg<double, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                    static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
-                                   partial, sc, halt, st, metric);
+                                   pq_partial, rr_partial, sc, halt, st, metric);
   }
   return vec ? run_cg<float, 4>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
-                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), partial,
-                                sc, halt, st, metric)
+                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), pq_partial,
+                                rr_partial, sc, halt, st, metric)
              : run_cg<float, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
-                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), partial,
-                                sc, halt, st, metric);
+                                static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), pq_partial,
+                                rr_partial, sc, halt, st, metric);
 }
 
 }  // namespace icr
