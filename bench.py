@@ -456,15 +456,19 @@ def mgvi_bench(B, plan, wl: dict, pairs: int, quiet: bool) -> dict:
     mean0 = mean.clone()
 
     def iteration_ms(absdelta=None, done=None):
-        mean.copy_(mean0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(2):
-            B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss, absdelta=absdelta,
-                        iterations_done=done)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 2
+        # median of three timed pairs of iterations (one timing has been seen far off)
+        times = []
+        for _ in range(3):
+            mean.copy_(mean0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                B.mgvi_step(plan, w, b, mean, eta, eta_d, 100, 35, workspaces=wss, absdelta=absdelta,
+                            iterations_done=done)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 2)
+        return statistics.median(times)
 
     ms = iteration_ms()
     products = pairs * 100 + 35 + 1   # metric products on single samples (the samples' CG runs batched)

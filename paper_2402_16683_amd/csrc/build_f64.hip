@@ -404,8 +404,7 @@ __global__ void __launch_bounds__(1024) chol_panel_kernel(double* __restrict__ a
                                                           int clamp, int32_t* __restrict__ count,
                                                           int32_t* __restrict__ status) {
   // the diagonal block A11 (rows and columns j0 .. j1-1) is factored in LDS by the
-  // workgroup, column by column; then each thread solves rows of the panel below it,
-  // x L11^T = a[i][j0 .. j1-1], a clamped column giving zeros
+  // workgroup, column by column (the rows below it are solved by chol_solve_kernel)
   __shared__ double l11[kPanel][kPanel + 1];
   __shared__ int zero_col[kPanel];
   const int tid = threadIdx.x;
@@ -444,24 +443,6 @@ __global__ void __launch_bounds__(1024) chol_panel_kernel(double* __restrict__ a
     const int r = e / kPanel, c = e % kPanel;
     if (r < nb && c <= r) a[(j0 + r) * n + j0 + c] = l11[r][c];
   }
-  // rows below the block: forward substitution against L11 (a zero column of L11 sets
-  // the row's entry to zero: the clamped column of the factor is zero)
-  for (int64_t i = j1 + tid; i < n; i += nthreads) {
-    double x[kPanel];
-    double* row = a + i * n + j0;
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j) x[j] = j < nb ? row[j] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j) {
-      double v = x[j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) v -= x[k] * l11[j][k];
-      x[j] = zero_col[j] ? 0.0 : v / l11[j][j];
-    }
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j)
-      if (j < nb) row[j] = x[j];
-  }
   if (tid == 0) {
     *count += clamped;  // panels run one after another on the stream
     if (clamped > 0 && !clamp) *status |= 2;
@@ -470,6 +451,43 @@ __global__ void __launch_bounds__(1024) chol_panel_kernel(double* __restrict__ a
 
 // Trailing update after the panel j0 .. j0+kPanel-1: a[i][k] -= sum_p a[i][p] a[k][p] for
 // j1 <= k <= i < n; one workgroup per 32 x 32 tile (tiles above the diagonal leave).
+// The panel's rows below its diagonal block: x L11^T = a[i][j0 .. j1-1] for i >= j1,
+// one thread per row (forward substitution; a clamped column of L11, zero on its
+// diagonal, gives a zero entry: the clamped column of the factor is zero). A separate
+// launch over many workgroups: solving them in the panel's single workgroup held 32
+// doubles per lane under a 1024-thread bound and spilled to scratch (up to 214 us per
+// panel at n = 1000). The workgroup's rows go through LDS: loaded and stored as whole
+// row segments (coalesced), solved in place with each thread's row in a column of xs.
+constexpr int kSolveRows = 256;
+__global__ void __launch_bounds__(kSolveRows) chol_solve_kernel(double* __restrict__ a, int64_t n, int64_t j0) {
+  __shared__ double l11[kPanel][kPanel + 1];
+  __shared__ double xs[kPanel][kSolveRows + 1];
+  const int tid = threadIdx.x;
+  const int64_t j1 = j0 + kPanel < n ? j0 + kPanel : n;
+  const int nb = static_cast<int>(j1 - j0);
+  const int64_t i0 = j1 + int64_t(blockIdx.x) * kSolveRows;  // first row of this workgroup
+  const int rows = static_cast<int>(n - i0 < kSolveRows ? n - i0 : kSolveRows);
+  for (int e = tid; e < kPanel * kPanel; e += kSolveRows) {
+    const int r = e / kPanel, c = e % kPanel;
+    l11[r][c] = (r < nb && c <= r) ? a[(j0 + r) * n + j0 + c] : 0.0;
+  }
+  for (int e = tid; e < kPanel * kSolveRows; e += kSolveRows) {  // (row, column): rows of 32 doubles
+    const int r = e / kPanel, c = e % kPanel;
+    xs[c][r] = (r < rows && c < nb) ? a[(i0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    double v = xs[j][tid];
+    for (int k = 0; k < j; ++k) v -= xs[k][tid] * l11[j][k];
+    xs[j][tid] = l11[j][j] == 0.0 ? 0.0 : v / l11[j][j];
+  }
+  __syncthreads();
+  for (int e = tid; e < kPanel * kSolveRows; e += kSolveRows) {
+    const int r = e / kPanel, c = e % kPanel;
+    if (r < rows && c < nb) a[(i0 + r) * n + j0 + c] = xs[c][r];
+  }
+}
+
 __global__ void __launch_bounds__(256) chol_update_kernel(double* __restrict__ a, int64_t n, int64_t j0) {
   const int64_t j1 = j0 + kPanel;
   const int ti = blockIdx.y, tk = blockIdx.x;
@@ -689,6 +707,7 @@ hipError_t launch_cholesky_level0(const icr_plan* p, double* a, int32_t* counts,
     chol_panel_kernel<<<1, 1024, 0, st>>>(a, n, j0, tau_of(p), clamp, counts, status);
     const int64_t m = n - j0 - kPanel;  // trailing size
     if (m > 0) {
+      chol_solve_kernel<<<static_cast<unsigned>((m + kSolveRows - 1) / kSolveRows), kSolveRows, 0, st>>>(a, n, j0);
       const unsigned tiles = static_cast<unsigned>((m + 31) / 32);
       chol_update_kernel<<<dim3(tiles, tiles), 256, 0, st>>>(a, n, j0);
     }
