@@ -14,7 +14,9 @@ from tests import icr_cases as C
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [32, 64, 256, 1024, 4096]
+# every path: one workgroup (32, 64), three passes with radix 4 (128 .. 1024; 512 ends on a
+# radix-2 stage), radix 16 (2048 ends on a radix-8 stage, 4096)
+SIZES = [32, 64, 128, 256, 512, 1024, 2048, 4096]
 PARAMS = dict(amplitude=1.0, zero_mode=0.1, length=0.05, slope=3.0, offset_mean=2.0)
 
 
