@@ -376,26 +376,16 @@ __global__ void __launch_bounds__((fft_threads<N, 2>())) cf_rows(const float* __
   }
 }
 
-// Column pairs per column-pass workgroup: a whole block. (Half a block at n = 4096, two
-// workgroups per compute unit, measured slower: 95 against 90 us.)
+// Block of workgroup i. From n = 512 on, the eight blocks whose columns share 128-byte
+// lines of lambda run together on one XCD (workgroup i runs on XCD i mod 8), so the
+// column-wise reads of lambda hit in that XCD's L2.
 template <int N>
-constexpr int col_pairs() {
-  return 4;
-}
-
-// Block and half (first pair 2 half) of workgroup i, with H = 4 / FC workgroups per
-// block. From n = 512 on, the 8 H workgroups whose columns share 128-byte lines of lambda
-// run together on one XCD (workgroup i runs on XCD i mod 8), so the column-wise reads of
-// lambda hit in that XCD's L2.
-template <int N, int FC>
-__device__ __forceinline__ int2 col_block(int i) {
-  constexpr int H = 4 / FC;
+__device__ __forceinline__ int col_block(int i) {
   if constexpr (N / 8 >= 64) {
     const int x = i & 7, t = i >> 3;
-    const int g = x + 8 * (t / (8 * H)), u = t % (8 * H);
-    return make_int2(8 * g + u / H, u % H);
+    return 8 * (x + 8 * (t >> 3)) + (t & 7);
   } else {
-    return make_int2(i / H, i % H);
+    return i;
   }
 }
 
@@ -433,25 +423,24 @@ __device__ __forceinline__ void scale_by_rate(float2* buf, const float* __restri
   }
 }
 
-// Column transforms of FC column pairs of one block (complex FFTs over the rows; sequence
-// f is column c + i column partner(c), c = 4b + 2 half + f) and the combine: T at column c
-// is Re Z[k], at its partner Im Z[-k] (the block-0 pair (0, n/2) by the plain split).
+// Column transforms of one block (four complex FFTs over the rows; sequence j is column
+// c + i column partner(c), c = 4b + j) and the combine: T at column c is Re Z[k], at its
+// partner Im Z[-k] (the block-0 pair (0, n/2) by the plain split).
 //   kPostPlain / kPostExp: out = T / n (or exp(mean + T / n)), row-major.
 //   kPostMetric: u = lambda T / n, then the column transforms of u, written back to the
 //   block in place with row k at slot 0 (k = 0), 1 (k = n/2), 2k (k < n/2), 2(n-k)+1.
+// (Half a block per workgroup, two per compute unit at n = 4096, measured slower.)
 template <int N, int kPost>
-__global__ void __launch_bounds__((fft_threads<N, col_pairs<N>()>())) cf_cols(float2* __restrict__ blk,
-                                                                              const float* __restrict__ lam,
-                                                                              float* __restrict__ out,
-                                                                              const float2* __restrict__ tw,
-                                                                              float mean) {
-  constexpr int F = col_pairs<N>(), NT = fft_threads<N, F>(), S = seq_stride<N>();
+__global__ void __launch_bounds__((fft_threads<N, 4>())) cf_cols(float2* __restrict__ blk,
+                                                                 const float* __restrict__ lam,
+                                                                 float* __restrict__ out,
+                                                                 const float2* __restrict__ tw, float mean) {
+  constexpr int F = 4, NT = fft_threads<N, F>(), S = seq_stride<N>();
   __shared__ float2 buf[F * S];
   __shared__ float2 tws[kTwEntries];
-  const int2 bh = col_block<N, F>(blockIdx.x);
-  const int b = bh.x, j0 = 2 * bh.y;  // first pair of this workgroup
-  // float4 = pairs (j, j+1) at one row; a row of the block is two float4
-  float4* region = reinterpret_cast<float4*>(blk + int64_t(b) * N * 4) + j0 / 2;
+  const int b = col_block<N>(blockIdx.x);
+  // a row of the block is two float4, each the pairs (2 jj, 2 jj + 1)
+  float4* region = reinterpret_cast<float4*>(blk + int64_t(b) * N * 4);
   load_twiddles<NT>(tws, tw);
   constexpr int kLd = N * F / 2, kItL = trips(kLd, NT);
   {
@@ -459,13 +448,13 @@ __global__ void __launch_bounds__((fft_threads<N, col_pairs<N>()>())) cf_cols(fl
 #pragma unroll
     for (int it = 0; it < kItL; ++it) {
       const int e = static_cast<int>(threadIdx.x) + it * NT;
-      if (kLd % NT == 0 || e < kLd) r4[it] = region[2 * (e / (F / 2)) + e % (F / 2)];
+      if (kLd % NT == 0 || e < kLd) r4[it] = region[e];
     }
 #pragma unroll
     for (int it = 0; it < kItL; ++it) {
       const int e = static_cast<int>(threadIdx.x) + it * NT;
       if (kLd % NT == 0 || e < kLd) {
-        const int row = e / (F / 2), f = 2 * (e % (F / 2));
+        const int row = e >> 1, f = 2 * (e & 1);
         buf[f * S + pad16(row)] = make_float2(r4[it].x, r4[it].y);
         buf[(f + 1) * S + pad16(row)] = make_float2(r4[it].z, r4[it].w);
       }
@@ -481,7 +470,7 @@ __global__ void __launch_bounds__((fft_threads<N, col_pairs<N>()>())) cf_cols(fl
       const int e = static_cast<int>(threadIdx.x) + it * NT;
       if (kItems % NT == 0 || e < kItems) {
         const int k = e / (2 * F), h = (e / F) & 1, f = e % F;
-        const int c = 4 * b + j0 + f;
+        const int c = 4 * b + f;
         const float2* z = buf + f * S;
         const float2 P = z[pad16(k)], Q = z[pad16(reflect<N>(k))];
         float t = inv * (h ? combine_m(c == 0, P, Q) : combine_c(c == 0, P, Q));
@@ -490,20 +479,19 @@ __global__ void __launch_bounds__((fft_threads<N, col_pairs<N>()>())) cf_cols(fl
       }
     }
   } else {
-    scale_by_rate<N, F, NT>(buf, lam, [b, j0](int f) { return 4 * b + j0 + f; });
+    scale_by_rate<N, F, NT>(buf, lam, [b](int f) { return 4 * b + f; });
     __syncthreads();
     fft_lds<N, F, NT>(buf, tws);
 #pragma unroll
     for (int it = 0; it < kItL; ++it) {  // (slot, pair of sequences)
       const int e = static_cast<int>(threadIdx.x) + it * NT;
       if (kLd % NT == 0 || e < kLd) {
-        const int slot = e / (F / 2), f = 2 * (e % (F / 2));
+        const int slot = e >> 1, f = 2 * (e & 1);
         const int p = slot >> 1;
         const int k = (slot & 1) ? partner<N>(p) : p;
         const float2 P0 = buf[f * S + pad16(k)], Q0 = buf[f * S + pad16(reflect<N>(k))];
         const float2 P1 = buf[(f + 1) * S + pad16(k)], Q1 = buf[(f + 1) * S + pad16(reflect<N>(k))];
-        region[2 * slot + e % (F / 2)] =
-            make_float4(hartley_a(P0, Q0), hartley_b(P0, Q0), hartley_a(P1, Q1), hartley_b(P1, Q1));
+        region[e] = make_float4(hartley_a(P0, Q0), hartley_b(P0, Q0), hartley_a(P1, Q1), hartley_b(P1, Q1));
       }
     }
   }
@@ -672,7 +660,7 @@ hipError_t transform_n(const icr_cf_plan* p, const float* x, const float* pre, f
     else cf_small<N, kPostPlain><<<1, nt, 0, st>>>(x, pre, nullptr, nullptr, out, p->tw, mean);
   } else {
     cf_rows<N><<<N / 4, fft_threads<N, 2>(), 0, st>>>(x, pre, p->tw, work);
-    constexpr unsigned wgs = N / 8 * (4 / col_pairs<N>()), nt = fft_threads<N, col_pairs<N>()>();
+    constexpr unsigned wgs = N / 8, nt = fft_threads<N, 4>();
     if (post == kPostExp) cf_cols<N, kPostExp><<<wgs, nt, 0, st>>>(work, nullptr, out, p->tw, mean);
     else cf_cols<N, kPostPlain><<<wgs, nt, 0, st>>>(work, nullptr, out, p->tw, mean);
   }
@@ -687,7 +675,7 @@ hipError_t metric_n(const icr_cf_plan* p, const float* lam, const float* v, floa
     cf_small<N, kPostMetric><<<1, fft_threads<N, N / 2>(), 0, st>>>(v, p->amp, lam, v, out, p->tw, 0.0f);
   } else {
     cf_rows<N><<<N / 4, fft_threads<N, 2>(), 0, st>>>(v, p->amp, p->tw, work);
-    constexpr unsigned wgs = N / 8 * (4 / col_pairs<N>()), nt = fft_threads<N, col_pairs<N>()>();
+    constexpr unsigned wgs = N / 8, nt = fft_threads<N, 4>();
     cf_cols<N, kPostMetric><<<wgs, nt, 0, st>>>(work, lam, nullptr, p->tw, 0.0f);
     cf_rows_final<N><<<N / 4, fft_threads<N, 2>(), 0, st>>>(work, v, p->amp, out, p->tw);
   }
