@@ -477,9 +477,16 @@ __global__ void __launch_bounds__(kSolveRows) chol_solve_kernel(double* __restri
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    double v = xs[j][tid];
-    for (int k = 0; k < j; ++k) v -= xs[k][tid] * l11[j][k];
-    xs[j][tid] = l11[j][j] == 0.0 ? 0.0 : v / l11[j][j];
+    // four partial sums, so the LDS reads of one step do not wait on the previous FMA
+    double v[4] = {xs[j][tid], 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= j; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] -= xs[k + u][tid] * l11[j][k + u];
+    }
+    for (; k < j; ++k) v[0] -= xs[k][tid] * l11[j][k];
+    const double sum = (v[0] + v[1]) + (v[2] + v[3]);
+    xs[j][tid] = l11[j][j] == 0.0 ? 0.0 : sum / l11[j][j];
   }
   __syncthreads();
   for (int e = tid; e < kPanel * kSolveRows; e += kSolveRows) {
