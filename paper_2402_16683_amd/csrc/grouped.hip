@@ -50,7 +50,7 @@ __device__ void level0_task(const GroupTask& t, int64_t u0) {
   const TS* in = static_cast<const TS*>(t.in);
   const int64_t j0 = kLower ? 0 : row;
   const int64_t j1 = kLower ? row + 1 : n;
-  constexpr int kU = 8;
+  constexpr int kU = 16;  // as level0_kernel, so both compute the same sums
   TA part[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) part[u] = 0;

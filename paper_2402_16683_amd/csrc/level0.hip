@@ -31,10 +31,11 @@ __global__ void __launch_bounds__(256) level0_kernel(const typename Acc<TS>::typ
   const TA* m = mat + row * n;
   const int64_t j0 = kLower ? 0 : row;
   const int64_t j1 = kLower ? row + 1 : n;
-  // kU independent partial sums so kU loads of the row are in flight at once; a lane
-  // past the end of the row reads an in-bounds element and adds zero, so no load sits
-  // in a divergent branch
-  constexpr int kU = 8;
+  // kU independent partial sums so kU loads of the row are in flight at once (rows of up
+  // to 1024, the 3-D workload's 10^3 level 0 included, in one round); a lane past the end
+  // of the row reads an in-bounds element and adds zero, so no load sits in a divergent
+  // branch
+  constexpr int kU = 16;
   TA part[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) part[u] = 0;
