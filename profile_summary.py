@@ -100,7 +100,10 @@ def traffic(fetch_dir: str, write_dir: str, workload: str, precision: str):
         shapes.append(n)
     el = {"f32": 4, "bf16": 2}[precision]
     prod = lambda v: int(__import__("math").prod(v))
-    alg = wl.get("batch", 1) * (2 * prod(shapes[-1]) + prod(shapes[-2])) * el
+    # algorithmic bytes of one launch: the fine level read and written; the coarse level
+    # (read by the forward, written by the adjoint) apart
+    alg = wl.get("batch", 1) * 2 * prod(shapes[-1]) * el
+    coarse = wl.get("batch", 1) * prod(shapes[-2]) * el
     _, fetch, _ = _counter_groups(fetch_dir, "FETCH_SIZE")
     _, write, calls = _counter_groups(write_dir, "WRITE_SIZE")
     f_probe = max(v for (nm, g), v in fetch.items() if "copy" in nm.lower())
@@ -122,9 +125,11 @@ def traffic(fetch_dir: str, write_dir: str, workload: str, precision: str):
         rd, wr = fetch[key] * f_scale, write[key] * w_scale
         print(f"{tag:16s} {key[0]} grid {key[1]:>8s} ({calls[key]} launches): FETCH {fetch[key]:9.0f} KiB -> "
               f"{rd / 1e6:6.1f} MB read; WRITE {write[key]:9.0f} KiB -> {wr / 1e6:6.1f} MB written; total "
-              f"{(rd + wr) / 1e6:6.1f} MB vs algorithmic {alg / 1e6:.1f} MB ({(rd + wr) / alg:.2f}x)")
+              f"{(rd + wr) / 1e6:6.1f} MB vs algorithmic {alg / 1e6:.1f} MB ({(rd + wr) / alg:.2f}x; "
+              f"{(rd + wr) / (alg + coarse):.2f}x of {(alg + coarse) / 1e6:.1f} MB with the coarse level)")
         rec[f"{tag}:{workload}:{precision}"] = {"source_digest": digest, "hbm_bytes_per_launch": rd + wr,
-                                               "read_bytes": rd, "write_bytes": wr, "alg_bytes": alg}
+                                               "read_bytes": rd, "write_bytes": wr, "alg_bytes": alg,
+                                               "coarse_bytes": coarse}
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
