@@ -100,10 +100,13 @@ void* at(const void* base, int64_t elems, int el) {
 
 // Adjoint sweep from the fine cotangent y (level `depth`) down to level 0. Every kernel of
 // the sweep does nothing while the device flag `halt` is set (NULL: never).
+// With top < depth the sweep starts at level `top`, whose cotangent is y (the metric's
+// fused finest level leaves it in the workspace).
 icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t y_bs, void* xi_bar,
-                       void* ws, int64_t ws_bs, const void* add, hipStream_t st, const int32_t* halt = nullptr) {
+                       void* ws, int64_t ws_bs, const void* add, hipStream_t st, const int32_t* halt = nullptr,
+                       int top = -1) {
   const int el = p->elem_bytes;
-  const int L = p->depth;
+  const int L = top < 0 ? p->depth : top;
   if (L == 0) {
     icr::Level0Args a{y, y_bs, xi_bar, p->n_xi, nullptr, 0, add, add ? p->n_xi : 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_adj(p, a, st));
@@ -111,6 +114,7 @@ icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t 
   }
   bool fuse0 = false;
   const int K = icr::fused_levels(p, &fuse0);  // the smallest levels in one launch
+  if (K > L) return fail(ICR_ERR_UNSUPPORTED, "adjoint sweep starts inside the fused levels");
   for (int l = L - 1; l >= K; --l) {
     icr::RefineAdjArgs a;
     a.y = l == L - 1 ? y : at(ws, p->offsets[l + 1], el);
@@ -137,11 +141,18 @@ icr_status run_adjoint(const icr_plan* p, int64_t batch, const void* y, int64_t 
 
 // Forward sweep; the last level goes to `out` (stride out_bs), optionally times w. Every
 // kernel does nothing while the device flag `halt` is set (NULL: never).
+// With stop < depth the sweep ends at level `stop`, which stays in the workspace (out
+// and w are not used).
 icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* out, int64_t out_bs,
                        void* ws, int64_t ws_bs, const void* w, int64_t w_bs, hipStream_t st,
-                       const int32_t* halt = nullptr) {
+                       const int32_t* halt = nullptr, int stop = -1) {
   const int el = p->elem_bytes;
-  const int L = p->depth;
+  const int L = stop < 0 ? p->depth : stop;
+  if (L < p->depth) {  // level L is an intermediate: it goes to the workspace
+    out = at(ws, p->offsets[L], el);
+    out_bs = ws_bs;
+    w = nullptr;
+  }
   if (L == 0) {
     icr::Level0Args a{xi, p->n_xi, out, out_bs, w, w_bs, nullptr, 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_fwd(p, a, st));
@@ -149,6 +160,7 @@ icr_status run_forward(const icr_plan* p, int64_t batch, const void* xi, void* o
   }
   bool fuse0 = false;
   const int K = icr::fused_levels(p, &fuse0);  // the smallest levels in one launch
+  if (K > L) return fail(ICR_ERR_UNSUPPORTED, "forward sweep ends inside the fused levels");
   if (!fuse0) {
     icr::Level0Args a0{xi, p->n_xi, at(ws, p->offsets[0], el), ws_bs, nullptr, 0, nullptr, 0, batch, halt};
     ICR_HIP_TRY(icr::launch_level0_fwd(p, a0, st));
@@ -179,17 +191,50 @@ icr_status check_call(const icr_plan* p, int64_t batch) {
   return ICR_OK;
 }
 
-// The metric as CG applies it: v -> L^T (w * L v) + v on `batch` samples; its kernels do
-// nothing while the device flag `halt` is set (NULL: never).
-hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v,
-                         void* out, void* ws, const int32_t* halt, hipStream_t st) {
+// The metric v -> L^T (w * L v) + v on `batch` samples, with a workspace of n_xi elements
+// per sample (the levels at their offsets). The finest level's weighted field goes to
+// offsets[depth] and the adjoint reads it back, except where a fused kernel takes the
+// finest level both ways: the forward then stops one level short and that kernel leaves
+// the coarse cotangent at offsets[depth] (not at offsets[depth-1], where the coarse
+// field it reads lies). The kernels do nothing while the device flag `halt` is set
+// (NULL: never).
+icr_status run_metric(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v, void* out,
+                      void* ws, hipStream_t st, const int32_t* halt = nullptr) {
   const int el = p->elem_bytes;
   const int64_t bs = p->n_xi;
-  if (run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), bs, ws, bs, w, w_bs, st, halt) != ICR_OK)
-    return hipErrorLaunchFailure;
-  if (run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), bs, out, ws, bs, v, st, halt) != ICR_OK)
-    return hipErrorLaunchFailure;
-  return hipSuccess;
+  const int L = p->depth;
+  void* top = at(ws, p->offsets[L], el);
+  bool fuse0 = false;
+  if (L >= 1 && icr::fused_levels(p, &fuse0) < L) {
+    icr::RefineMetricArgs a;
+    a.s_in = at(ws, p->offsets[L - 1], el);
+    a.s_in_bs = bs;
+    a.v = at(v, p->offsets[L], el);
+    a.v_bs = bs;
+    a.w = w;
+    a.w_bs = w_bs;
+    a.out = at(out, p->offsets[L], el);
+    a.out_bs = bs;
+    a.s_bar = top;
+    a.s_bar_bs = bs;
+    a.batch = batch;
+    a.halt = halt;
+    if (icr::refine2_metric_ok(p, L - 1, a)) {
+      icr_status r = run_forward(p, batch, v, nullptr, 0, ws, bs, nullptr, 0, st, halt, L - 1);
+      if (r != ICR_OK) return r;
+      ICR_HIP_TRY(icr::launch_refine2_metric(p, L - 1, a, st));
+      return run_adjoint(p, batch, top, bs, out, ws, bs, v, st, halt, L - 1);
+    }
+  }
+  icr_status r = run_forward(p, batch, v, top, bs, ws, bs, w, w_bs, st, halt);
+  if (r != ICR_OK) return r;
+  return run_adjoint(p, batch, top, bs, out, ws, bs, v, st, halt);
+}
+
+// The metric as CG applies it (see run_metric).
+hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v,
+                         void* out, void* ws, const int32_t* halt, hipStream_t st) {
+  return run_metric(p, batch, w, w_bs, v, out, ws, st, halt) == ICR_OK ? hipSuccess : hipErrorLaunchFailure;
 }
 
 // Argument checks shared by the CG entry points.
@@ -681,14 +726,7 @@ icr_status icr_metric_apply(const icr_plan* p, int64_t batch, const void* w, int
   const size_t nx = size_t(batch) * p->n_xi * el;
   if (icr::overlaps(v, nx, out, nx) || icr::overlaps(v, nx, workspace, nx) || icr::overlaps(out, nx, workspace, nx))
     return fail(ICR_ERR_INVALID_ARG, "v, out and workspace overlap");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int64_t ws_bs = p->n_xi;
-  // forward into the workspace; the final level (times w) lands at offsets[depth]
-  icr_status r = run_forward(p, batch, v, at(workspace, p->offsets[p->depth], el), ws_bs, workspace,
-                             ws_bs, w, w_batch_stride, st);
-  if (r != ICR_OK) return r;
-  return run_adjoint(p, batch, at(workspace, p->offsets[p->depth], el), ws_bs, out, workspace, ws_bs,
-                     v, st);
+  return run_metric(p, batch, w, w_batch_stride, v, out, workspace, static_cast<hipStream_t>(hip_stream));
 }
 
 icr_status icr_metric_apply_static(const icr_plan* p, int64_t batch, const void* w, int64_t w_batch_stride,
@@ -711,13 +749,9 @@ icr_status icr_metric_apply_static(const icr_plan* p, int64_t batch, const void*
   void* ws = nullptr;
   cs = scratch_ptr(&ws);
   if (cs != ICR_OK) return cs;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int64_t ws_bs = p->n_xi;
   // the same sweep as icr_metric_apply, its workspace in the scratch array: every element
   // it reads there is written earlier in the same call, so nothing needs clearing
-  icr_status r = run_forward(p, batch, v, at(ws, p->offsets[p->depth], el), ws_bs, ws, ws_bs, w, w_batch_stride, st);
-  if (r != ICR_OK) return r;
-  return run_adjoint(p, batch, at(ws, p->offsets[p->depth], el), ws_bs, out, ws, ws_bs, v, st);
+  return run_metric(p, batch, w, w_batch_stride, v, out, ws, static_cast<hipStream_t>(hip_stream));
 }
 
 icr_status icr_hyper_grad(const icr_plan* p, int64_t batch, const void* xi, const void* s,

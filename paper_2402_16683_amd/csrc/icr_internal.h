@@ -207,6 +207,19 @@ struct RefineAdjArgs {
   int64_t batch;
   const int32_t* halt = nullptr;        // device flag: when set (non-zero) the kernel does nothing
 };
+// The metric's last level both ways in one launch (M v = L^T (w * L v) + v at the finest
+// level): the coarse field s_l, the level's v (excitations of the forward, values added
+// to the excitation cotangent), w (arithmetic type) in; v's excitation cotangent plus v
+// and the coarse cotangent s_bar_l out.
+struct RefineMetricArgs {
+  const void* s_in; int64_t s_in_bs;    // coarse field, level l
+  const void* v; int64_t v_bs;          // level l+1 part of v
+  const void* w; int64_t w_bs;          // weights of level l+1 (arithmetic type)
+  void* out; int64_t out_bs;            // level l+1 part of M v
+  void* s_bar; int64_t s_bar_bs;        // coarse cotangent, level l
+  int64_t batch;
+  const int32_t* halt = nullptr;        // device flag: when set (non-zero) the kernel does nothing
+};
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st);
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
 // The 3-D fast forward with the derivative matrices of the level and a dot-product
@@ -225,6 +238,10 @@ bool try_refine3_adj_sector(const icr_plan* p, int level, const RefineAdjArgs& a
                             hipError_t* err);
 bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st, hipError_t* err);
 bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err);
+// Whether the fused kernel takes this level and these buffers (else the caller runs the
+// two sweeps), and its launch.
+bool refine2_metric_ok(const icr_plan* p, int level, const RefineMetricArgs& a);
+hipError_t launch_refine2_metric(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);
 

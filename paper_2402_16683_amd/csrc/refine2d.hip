@@ -344,6 +344,187 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
   }
 }
 
+// The metric's last level both ways in one pass: M v = L^T (w * L v) + v needs, at the
+// finest level, the forward block s_c = R window_c + sqrtD v_c, the weighted block
+// y_c = w_c * s_c and then the adjoint of y_c, which is a function of y_c alone (plus
+// the neighbouring blocks' window contributions). A lane that computes s_c can hand
+// y_c straight to the adjoint arithmetic, so the weighted fine field is never stored
+// and read back. The layout is the adjoint's (strips of kOwnedPairs pairs whose first
+// and last lanes recompute the neighbouring strips' edge pairs, a wavefront marching
+// block rows y0-1 .. y1); each block row also runs the forward: its three coarse rows
+// slide in registers (one new row per block row), and the excitations of the level are
+// the values v the metric adds to the excitation cotangent, loaded once for both.
+template <typename TS, typename M>
+__global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Geom g, RefineMetricArgs a, M mats) {
+  fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.s_in, a.s_in_bs, a.v, a.v_bs, a.w, a.w_bs,
+             a.out, a.out_bs, a.s_bar, a.s_bar_bs);
+  if (halted(a.halt)) return;
+  const int lane = threadIdx.x % kLanes;
+  const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+  if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
+  const int strip = wave % g.strips, chunk = wave / g.strips;
+  const int P = strip * kOwnedPairs + lane - 1;  // blocks x = 2P+1, 2P+2
+  const bool pair_ok = P >= 0 && P < g.pairs;
+  const bool owner = lane >= 1 && lane <= kOwnedPairs && pair_ok;
+  const int y0 = chunk * g.ychunk;
+  const int y1 = min(y0 + g.ychunk, g.ny);
+  const int64_t b = blockIdx.y;
+  const TS* sc = static_cast<const TS*>(a.s_in) + b * a.s_in_bs;
+  const TS* v = static_cast<const TS*>(a.v) + b * a.v_bs;
+  const float* w = static_cast<const float*>(a.w) + b * a.w_bs;
+  TS* out = static_cast<TS*>(a.out) + b * a.out_bs;
+  TS* sb = static_cast<TS*>(a.s_bar) + b * a.s_bar_bs;
+  // every load goes to an in-bounds address (clamped pair, row and block row); blocks
+  // outside the interior are zeroed after the forward
+  const int Pc = min(max(P, 0), g.pairs - 1);
+  auto fine_off = [&](int yb, int by) { return static_cast<int64_t>(2 * (yb - 1) + by) * g.nfx + 4 * Pc; };
+  auto coarse_row = [&](int y, float (&r)[4]) {
+    const TS* row = sc + static_cast<int64_t>(min(max(y, 0), g.ny - 1)) * g.nx + 2 * Pc;
+    const float2 u = Io<TS>::ld2(row), t = Io<TS>::ld2(row + 2);
+    r[0] = u.x; r[1] = u.y; r[2] = t.x; r[3] = t.y;
+  };
+
+  struct Step {
+    float c[4];    // coarse row yb + 1, columns 2P .. 2P+3
+    float4 x[2];   // v on the pair's fine rows 2(yb-1), 2(yb-1)+1
+    float4 wr[2];  // w on the same rows
+  };
+  auto load_step = [&](int yb, Step& st) {
+    coarse_row(yb + 1, st.c);
+    const int yc = min(max(yb, 1), g.ny - 2);
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      st.x[by] = Io<TS>::ld4(v + fine_off(yc, by));
+      st.wr[by] = *reinterpret_cast<const float4*>(w + fine_off(yc, by));
+    }
+  };
+
+  float rm[4], r0[4];        // coarse rows yb-1 and yb
+  float A0[2][3], A1[2][3];  // partial coarse cotangents of rows yb-1 and yb, per block and wx
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) { A0[p][x] = 0.0f; A1[p][x] = 0.0f; }
+
+  auto process = [&](int yb, const Step& st) {
+    const bool ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
+    float R[36], S[10];  // this block row's matrices
+    if constexpr (kShell2<M>) {
+      const auto row = row_of(mats, yb - 1);
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
+#pragma unroll
+      for (int e = 0; e < 10; ++e) S[e] = mats.m.s[e];
+    }
+    // forward and weight: yv[p][by * 2 + bx] of block 2P+1+p
+    float yv[2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float win[9];  // columns 2P+p .. 2P+p+2 of rows yb-1, yb, yb+1
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        win[x] = rm[p + x];
+        win[3 + x] = r0[p + x];
+        win[6 + x] = st.c[p + x];
+      }
+      float xv[4], wv[4];
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        xv[by * 2] = p == 0 ? st.x[by].x : st.x[by].z;
+        xv[by * 2 + 1] = p == 0 ? st.x[by].y : st.x[by].w;
+        wv[by * 2] = p == 0 ? st.wr[by].x : st.wr[by].z;
+        wv[by * 2 + 1] = p == 0 ? st.wr[by].y : st.wr[by].w;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s = fmaf(R[c * 9 + k], win[k], s);
+#pragma unroll
+        for (int cp = 0; cp <= c; ++cp) s = fmaf(S[sd2(c, cp)], xv[cp], s);
+        yv[p][c] = ok ? s * wv[c] : 0.0f;
+      }
+    }
+    // adjoint: excitation cotangent plus v
+    if (ok && owner && yb >= y0 && yb < y1) {
+      float xo[2][4];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int cp = 0; cp < 4; ++cp) {
+          float t = 0.0f;
+#pragma unroll
+          for (int c = cp; c < 4; ++c) t = fmaf(S[sd2(c, cp)], yv[p][c], t);
+          xo[p][cp] = t;
+        }
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        const float4 av = st.x[by];
+        const float4 o = make_float4(xo[0][by * 2] + av.x, xo[0][by * 2 + 1] + av.y, xo[1][by * 2] + av.z,
+                                     xo[1][by * 2 + 1] + av.w);
+        st4_stream<TS>(out + fine_off(yb, by), o);
+      }
+    }
+    // window contributions, then the y march: row yb-1 is complete after this block row
+    float G[2][3];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      float u[9];
+#pragma unroll
+      for (int wi = 0; wi < 9; ++wi) {
+        float t = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t = fmaf(R[c * 9 + wi], yv[p][c], t);
+        u[wi] = t;
+      }
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        G[p][x] = A0[p][x] + u[x];       // wy = -1: coarse row yb - 1
+        A0[p][x] = A1[p][x] + u[3 + x];  // wy =  0: coarse row yb
+        A1[p][x] = u[6 + x];             // wy = +1: coarse row yb + 1
+      }
+    }
+    if (yb >= y0 + 1) {  // uniform over the wavefront
+      const float from_left = dpp_from_left(G[1][2]);
+      const float from_right = dpp_from_right(G[0][0]);
+      if (owner) {
+        TS* row = sb + static_cast<int64_t>(yb - 1) * g.nx;
+        Io<TS>::st1(row + 2 * P + 1, from_left + G[0][1] + G[1][0]);
+        Io<TS>::st1(row + 2 * P + 2, G[0][2] + G[1][1] + from_right);
+        if (P == 0) Io<TS>::st1(row, G[0][0]);
+        if (P == g.pairs - 1) Io<TS>::st1(row + g.nx - 1, G[1][2]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { rm[k] = r0[k]; r0[k] = st.c[k]; }
+  };
+
+  // block rows y0-1 .. y1; the window of block row yb is coarse rows yb-1 .. yb+1
+  coarse_row(y0 - 2, rm);
+  coarse_row(y0 - 1, r0);
+  Step sa, sb2, sc2;
+  load_step(y0 - 1, sa);
+  load_step(y0, sb2);
+  for (int yb = y0 - 1; yb <= y1; yb += 3) {  // scheduling barriers: as in the adjoint
+    load_step(yb + 2, sc2);
+    __builtin_amdgcn_sched_barrier(0);
+    process(yb, sa);
+    if (yb + 1 > y1) break;
+    load_step(yb + 3, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    process(yb + 1, sb2);
+    if (yb + 2 > y1) break;
+    load_step(yb + 4, sb2);
+    __builtin_amdgcn_sched_barrier(0);
+    process(yb + 2, sc2);
+  }
+}
+
 bool aligned2(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
 
 Mat2 mat2_of(const icr_plan* p, int level) {
@@ -355,12 +536,17 @@ Mat2 mat2_of(const icr_plan* p, int level) {
   return m;
 }
 
-// rows per wavefront for a sweep of `rows` rows in `strips` strips: enough wavefronts
-// to keep every SIMD busy (about 16 per SIMD over 1024 SIMDs: 2-D step 0.2447 ms at 8,
-// 0.2405 at 16, 0.252 at 32, 0.265 at 64 per SIMD for 1540^2 x 16); a small level gets
-// one row per wavefront (a march is a chain of dependent steps), a large one long marches
+// rows per wavefront for a sweep of `rows` rows in `strips` strips. A wavefront that
+// marches one row per chunk also recomputes the two halo rows (the adjoint) or loads the
+// two window rows (the forward) for it, so long marches save work, while short ones
+// spread the level over more SIMDs. The wavefront budget grows with the batch up to
+// 16384 (16 per SIMD over 1024 SIMDs: 2-D step 0.2447 ms at 8, 0.2405 at 16, 0.252 at
+// 32, 0.265 at 64 per SIMD for 1540^2 x 16); one sample gets 2048 (charted 1284^2
+// metric 57.6 us against 62.0 at 16384 and 57.1 at 1024), three get 4096 (76.2 us
+// against 93.7 at 16384).
 int pick_ychunk(int rows, int strips, int64_t batch) {
-  int64_t chunks = 16384 / (int64_t(strips) * batch);
+  const int64_t budget = std::min<int64_t>(16384, 1024 * (batch + 1));
+  int64_t chunks = budget / (int64_t(strips) * batch);
   chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, rows));
   return static_cast<int>((rows + chunks - 1) / chunks);
 }
@@ -423,6 +609,42 @@ hipError_t adj2_launch(const icr_plan* p, int level, const M& m, const RefineAdj
   return hipSuccess;
 }
 
+template <typename TS, typename M>
+hipError_t metric2_launch(const icr_plan* p, int level, const M& m, const RefineMetricArgs& a, hipStream_t st) {
+  Adj2Geom g;
+  g.ny = p->shapes[level][1];
+  g.nx = p->shapes[level][2];
+  g.pairs = (g.nx - 2) / 2;
+  g.strips = (g.pairs + kOwnedPairs - 1) / kOwnedPairs;
+  g.nfx = p->shapes[level + 1][2];
+  const int64_t batch = a.batch < 65535 ? a.batch : 65535;
+  g.ychunk = pick_ychunk(g.ny, g.strips, batch);
+  const int nchunks = (g.ny + g.ychunk - 1) / g.ychunk;
+  g.waves = g.strips * nchunks;
+  const unsigned groups = static_cast<unsigned>((g.waves + kWavesPerGroup - 1) / kWavesPerGroup);
+  for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
+    RefineMetricArgs c = a;
+    c.batch = a.batch - b0 < 65535 ? a.batch - b0 : 65535;
+    c.s_in = static_cast<const TS*>(a.s_in) + b0 * a.s_in_bs;
+    c.v = static_cast<const TS*>(a.v) + b0 * a.v_bs;
+    c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
+    c.out = static_cast<TS*>(a.out) + b0 * a.out_bs;
+    c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
+    const dim3 grid(groups, static_cast<unsigned>(c.batch));
+    refine2_metric<TS, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TS>
+hipError_t metric2_any(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st) {
+  if (p->shell)
+    return metric2_launch<TS>(p, level, Shell2{p->lev[level].shell_tab, static_cast<int>(p->lev[level].nsets)}, a, st);
+  return metric2_launch<TS>(p, level, Stat2{mat2_of(p, level)}, a, st);
+}
+
 template <typename TS>
 hipError_t fwd2_any(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st) {
   if (p->shell) return fwd2_launch<TS>(p, level, Shell2{p->lev[level].shell_tab, static_cast<int>(p->lev[level].nsets)}, a, st);
@@ -465,6 +687,18 @@ bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipSt
   if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;
   *err = p->precision == ICR_F32 ? adj2_any<float>(p, level, a, st) : adj2_any<bf16_t>(p, level, a, st);
   return true;
+}
+
+bool refine2_metric_ok(const icr_plan* p, int level, const RefineMetricArgs& a) {
+  if (!eligible2(p, level)) return false;
+  const int vec = 4 * p->elem_bytes;
+  if (!aligned2(a.v, vec) || !aligned2(a.out, vec) || !aligned2(a.s_in, 2 * p->elem_bytes) || !aligned2(a.w, 16))
+    return false;
+  return a.v_bs % 4 == 0 && a.out_bs % 4 == 0 && a.s_in_bs % 2 == 0 && a.w_bs % 4 == 0;
+}
+
+hipError_t launch_refine2_metric(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st) {
+  return p->precision == ICR_F32 ? metric2_any<float>(p, level, a, st) : metric2_any<bf16_t>(p, level, a, st);
 }
 
 }  // namespace icr

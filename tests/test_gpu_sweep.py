@@ -19,8 +19,8 @@ CASES = [
     C.from_workload("icr2d_se_16to1540_b16", batch=2, name="2d_se_full_b2_f32"),
     C.from_workload("icr2d_se_16to1540_b16", batch=2, precision="bf16", name="2d_se_full_b2_bf16"),
     # the 2-D workload at its benchmarked batch of 16: the 2-D kernels size their row marches
-    # by the batch, so the last two levels march 6 and 2 rows per wavefront (batch <= 3
-    # gives one row per wavefront at every level)
+    # by the batch, so the last two levels march 6 and 2 rows per wavefront (batch 2 marches
+    # 4 and 2 rows there)
     C.from_workload("icr2d_se_16to1540_b16", name="2d_se_full_b16_f32"),
     C.from_workload("icr2d_se_16to1540_b16", precision="bf16", name="2d_se_full_b16_bf16"),
     # a large batch of small grids: marches of 2 to 7 rows with a ragged last chunk
