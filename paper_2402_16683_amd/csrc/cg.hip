@@ -9,7 +9,11 @@
 // Dot products accumulate in FP64 in a fixed order (per-block partial sums, then a
 // fixed-order sum of the partials), so runs are bitwise reproducible. Each update kernel
 // sums the partials it needs itself (every workgroup the same way), so a step is three
-// launches after the metric product: p.q partials; x, r and the r.r partials; p.
+// launches after the metric product: p.q partials; x, r and the r.r partials; p. Where the
+// metric's finest level runs in the fused 2-D kernel, p.q comes without the first launch:
+// p.q = p.(L^T W L p + p) = <L p, w * L p> + p.p, the first sum from that kernel (it sees
+// L p and w * L p of the whole finest level), the second from the p update of the
+// previous iteration (at the first, p = r: p.p = r.r).
 //
 // Early stopping by the change of the CG energy E(x) = x.Mx / 2 - b.x (the "absdelta"
 // criterion of the sample-drawing CG in the paper's VI example): a step along p with the
@@ -27,6 +31,7 @@ namespace {
 
 constexpr int kDotThreads = 256;
 constexpr int kDotBlocks = 1024;  // at most this many partial sums per sample
+constexpr int kMetricDots = 1024; // partial sums of <L p, w * L p> per sample (fused metric level)
 
 // Per-sample state. r.r and the active flag are kept per iteration parity: the p update
 // of iteration i reads the entries of parity i and its workgroup 0 writes those of
@@ -92,12 +97,25 @@ int dot_blocks(int64_t n, int v) {
   return static_cast<int>(std::min<int64_t>(kDotBlocks, std::max<int64_t>(512, b)));
 }
 
-// The sum of sample b's `blocks` partials in a fixed order, in every thread (every
-// workgroup that calls it gets the same value).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t b, int blocks,
+// The sum of sample b's `count` partials (at partial[b * kStride + k], 1 <= count <=
+// kStride) in a fixed order, in every thread (every workgroup that calls it gets the same
+// value). Each thread loads all of its kStride / kDotThreads values before adding them (in
+// index order): the partials were just written by other compute units, so each load waits
+// on memory, and a loop of dependent loads waited once per value.
+template <int kStride = kDotBlocks>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t b, int count,
                                                double* sh) {
+  constexpr int kPer = kStride / kDotThreads;
+  double u[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = threadIdx.x + i * kDotThreads;
+    const double x = partial[b * kStride + min(k, count - 1)];  // in bounds; unused past count
+    u[i] = k < count ? x : 0.0;
+  }
   double v = 0.0;
-  for (int k = threadIdx.x; k < blocks; k += kDotThreads) v += partial[b * kDotBlocks + k];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) v += u[i];
   const double s = block_sum(v, sh);
   __syncthreads();  // sh is reused by the caller
   return s;
@@ -126,18 +144,27 @@ __global__ void __launch_bounds__(kDotThreads) dot_partial(const T* __restrict__
 
 // Iteration with parity `par` of an active sample: p.q from its partials, alpha =
 // (r.r) / (p.q); x += alpha p; r -= alpha q; partial sums of the new r.r. Workgroup 0
-// records p.q and alpha for the p update.
-template <typename T, int V>
+// records p.q and alpha for the p update. kSplit: p.q = <L p, w * L p> (npq partials of
+// stride kMetricDots) + p.p (the p update's partials, or r.r when `first`).
+template <typename T, int V, bool kSplit>
 __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                                                          const T* __restrict__ q, int64_t n, CgScalars* sc,
-                                                         const double* __restrict__ pq_partial,
+                                                         const double* __restrict__ pq_partial, int npq,
+                                                         const double* __restrict__ pp_partial, int first,
                                                          double* __restrict__ rr_partial, int par,
                                                          const int32_t* halt) {
   __shared__ double sh[kDotThreads];
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
   if (!sc[b].active[par]) return;  // uniform per workgroup (one sample per grid row)
-  const double pq = sum_partials(pq_partial, b, gridDim.x, sh);
+  double pq;
+  if constexpr (kSplit) {
+    const double lik = sum_partials<kMetricDots>(pq_partial, b, npq, sh);
+    const double pp = first ? sc[b].rr[par] : sum_partials(pp_partial, b, gridDim.x, sh);
+    pq = lik + pp;
+  } else {
+    pq = sum_partials(pq_partial, b, gridDim.x, sh);
+  }
   const double alpha = pq != 0.0 ? sc[b].rr[par] / pq : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[b].pq = pq;
@@ -171,12 +198,13 @@ __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* _
 // absdelta (absdelta > 0) or r = 0; its step is kept and p is no longer needed.
 // Workgroup 0 writes the sample's entries of the next parity, counts the step, records
 // the residual norm (a stopped sample repeats its last one), and when the last active
-// sample stops raises the halt flag (halt[1] counts the active samples).
-template <typename T, int V>
+// sample stops raises the halt flag (halt[1] counts the active samples). kPP: also the
+// partial sums of the new p.p.
+template <typename T, int V, bool kPP>
 __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const T* __restrict__ r, int64_t n,
                                                         CgScalars* sc, const double* __restrict__ rr_partial, int par,
                                                         int iter, double absdelta, double* norms, int stride,
-                                                        int32_t* halt) {
+                                                        int32_t* halt, double* __restrict__ pp_partial) {
   __shared__ double sh[kDotThreads];
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
@@ -207,13 +235,21 @@ __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const
   const T bt = static_cast<T>(beta);
   T* pp = p + b * n;
   const T* pr = r + b * n;
+  double acc = 0.0;
   const int64_t step = int64_t(gridDim.x) * kDotThreads;
   for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
     Chunk<T, V> pv = ldv<T, V>(pp + g * V);
     const Chunk<T, V> rv = ldv<T, V>(pr + g * V);
 #pragma unroll
-    for (int k = 0; k < V; ++k) pv.v[k] = rv.v[k] + bt * pv.v[k];
+    for (int k = 0; k < V; ++k) {
+      pv.v[k] = rv.v[k] + bt * pv.v[k];
+      if constexpr (kPP) acc += static_cast<double>(pv.v[k]) * static_cast<double>(pv.v[k]);
+    }
     stv<T, V>(pp + g * V, pv);
+  }
+  if constexpr (kPP) {
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) pp_partial[b * kDotBlocks + blockIdx.x] = s;
   }
 }
 
@@ -280,8 +316,8 @@ __global__ void cg_report(const CgScalars* sc, int32_t* iterations_done, int bat
 template <typename T, int V>
 hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec, void* x,
                   int32_t iterations, double absdelta, int32_t* iterations_done, double* norms, void* mws, T* r,
-                  T* pv, T* q, double* pq_partial, double* rr_partial, CgScalars* sc, int32_t* halt_flag,
-                  hipStream_t st, MetricFn metric) {
+                  T* pv, T* q, double* pq_partial, double* rr_partial, double* lik_partial, double* pp_partial,
+                  CgScalars* sc, int32_t* halt_flag, hipStream_t st, MetricFn metric) {
   const int64_t n = p->n_xi;
   const int blocks = dot_blocks(n, V);
   const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(batch));
@@ -295,15 +331,32 @@ hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs,
   if (e != hipSuccess) return e;
   cg_start<<<static_cast<unsigned>(batch), kDotThreads, 0, st>>>(rr_partial, sc, norms, stride, blocks, halt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  bool pp_ready = true;  // p.p is known for the current p (r.r at the start)
   for (int it = 0; it < iterations; ++it) {
     const int par = it & 1;
-    if ((e = metric(p, batch, w, w_bs, pv, q, mws, halt, st)) != hipSuccess) return e;
-    dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, pq_partial, halt);
+    int nlik = 0;
+    if ((e = metric(p, batch, w, w_bs, pv, q, mws, halt, st, lik_partial, kMetricDots, &nlik)) != hipSuccess)
+      return e;
+    const bool split = nlik > 0 && pp_ready;
+    if (split) {
+      update_xr<T, V, true><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, lik_partial, nlik, pp_partial,
+                                                          it == 0, rr_partial, par, halt);
+    } else {
+      dot_partial<T, V><<<grid, kDotThreads, 0, st>>>(pv, q, n, pq_partial, halt);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      update_xr<T, V, false><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, pq_partial, 0, nullptr, 0,
+                                                           rr_partial, par, halt);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_xr<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, q, n, sc, pq_partial, rr_partial, par, halt);
+    // the next iteration can split p.q only if this p update sums p.p
+    if (nlik > 0)
+      update_p<T, V, true><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride,
+                                                         halt, pp_partial);
+    else
+      update_p<T, V, false><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride,
+                                                          halt, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    update_p<T, V><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride, halt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    pp_ready = nlik > 0;
   }
   if (halt && norms) {
     // the iterations after the halt wrote nothing: repeat each sample's last norm there
@@ -327,7 +380,8 @@ int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch) {
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
   return up(batch * p->n_xi * el)          // metric workspace
          + 3 * up(vec)                     // r, p, q
-         + 2 * up(batch * kDotBlocks * 8)  // partial sums of p.q and r.r
+         + 3 * up(batch * kDotBlocks * 8)  // partial sums of p.q, r.r and p.p
+         + up(batch * kMetricDots * 8)     // partial sums of <L p, w * L p>
          + up(batch * int64_t(sizeof(CgScalars)))
          + 256;                            // halt flag and active count
 }
@@ -346,6 +400,8 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   void* q = base; base += up(batch * n * el);
   double* pq_partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
   double* rr_partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
+  double* pp_partial = reinterpret_cast<double*>(base); base += up(batch * kDotBlocks * 8);
+  double* lik_partial = reinterpret_cast<double*>(base); base += up(batch * kMetricDots * 8);
   CgScalars* sc = reinterpret_cast<CgScalars*>(base);
   base += up(batch * int64_t(sizeof(CgScalars)));
   int32_t* halt = reinterpret_cast<int32_t*>(base);
@@ -356,17 +412,17 @@ hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_
   if (p->precision == ICR_F64) {
     return vec ? run_cg<double, 2>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                    static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
-                                   pq_partial, rr_partial, sc, halt, st, metric)
+                                   pq_partial, rr_partial, lik_partial, pp_partial, sc, halt, st, metric)
                : run_cg<double, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                    static_cast<double*>(r), static_cast<double*>(pv), static_cast<double*>(q),
-                                   pq_partial, rr_partial, sc, halt, st, metric);
+                                   pq_partial, rr_partial, lik_partial, pp_partial, sc, halt, st, metric);
   }
   return vec ? run_cg<float, 4>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                 static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), pq_partial,
-                                rr_partial, sc, halt, st, metric)
+                                rr_partial, lik_partial, pp_partial, sc, halt, st, metric)
              : run_cg<float, 1>(p, batch, w, w_bs, bvec, x, iterations, absdelta, iterations_done, norms, mws,
                                 static_cast<float*>(r), static_cast<float*>(pv), static_cast<float*>(q), pq_partial,
-                                rr_partial, sc, halt, st, metric);
+                                rr_partial, lik_partial, pp_partial, sc, halt, st, metric);
 }
 
 }  // namespace icr

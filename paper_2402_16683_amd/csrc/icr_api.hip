@@ -197,9 +197,12 @@ icr_status check_call(const icr_plan* p, int64_t batch) {
 // finest level both ways: the forward then stops one level short and that kernel leaves
 // the coarse cotangent at offsets[depth] (not at offsets[depth-1], where the coarse
 // field it reads lies). The kernels do nothing while the device flag `halt` is set
-// (NULL: never).
+// (NULL: never). With `dot` (see MetricFn) the fused kernel also writes its partial sums
+// of <L v, w * L v>; *ndot gets their count per sample, 0 where none were written.
 icr_status run_metric(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v, void* out,
-                      void* ws, hipStream_t st, const int32_t* halt = nullptr) {
+                      void* ws, hipStream_t st, const int32_t* halt = nullptr, double* dot = nullptr,
+                      int dot_cap = 0, int* ndot = nullptr) {
+  if (ndot) *ndot = 0;
   const int el = p->elem_bytes;
   const int64_t bs = p->n_xi;
   const int L = p->depth;
@@ -220,6 +223,12 @@ icr_status run_metric(const icr_plan* p, int64_t batch, const void* w, int64_t w
     a.batch = batch;
     a.halt = halt;
     if (icr::refine2_metric_ok(p, L - 1, a)) {
+      const int64_t parts = icr::refine2_metric_partials(p, L - 1, batch);
+      if (dot && ndot && parts <= dot_cap) {
+        a.dot = dot;
+        a.dot_bs = dot_cap;
+        *ndot = static_cast<int>(parts);
+      }
       icr_status r = run_forward(p, batch, v, nullptr, 0, ws, bs, nullptr, 0, st, halt, L - 1);
       if (r != ICR_OK) return r;
       ICR_HIP_TRY(icr::launch_refine2_metric(p, L - 1, a, st));
@@ -231,10 +240,12 @@ icr_status run_metric(const icr_plan* p, int64_t batch, const void* w, int64_t w
   return run_adjoint(p, batch, top, bs, out, ws, bs, v, st, halt);
 }
 
-// The metric as CG applies it (see run_metric).
+// The metric as CG applies it (see run_metric and MetricFn).
 hipError_t metric_for_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* v,
-                         void* out, void* ws, const int32_t* halt, hipStream_t st) {
-  return run_metric(p, batch, w, w_bs, v, out, ws, st, halt) == ICR_OK ? hipSuccess : hipErrorLaunchFailure;
+                         void* out, void* ws, const int32_t* halt, hipStream_t st, double* dot, int dot_cap,
+                         int* ndot) {
+  return run_metric(p, batch, w, w_bs, v, out, ws, st, halt, dot, dot_cap, ndot) == ICR_OK ? hipSuccess
+                                                                                          : hipErrorLaunchFailure;
 }
 
 // Argument checks shared by the CG entry points.
@@ -875,7 +886,7 @@ icr_status icr_mgvi_newton_step(const icr_plan* p, int64_t batch, const void* w,
   void* cg_ws = base + 2 * vec;
   // g = M mean - b (the KL gradient over antithetic pairs), delta = M^-1 g, mean -= delta;
   // CG's own metric workspace serves the first product
-  ICR_HIP_TRY(metric_for_cg(p, batch, w, w_batch_stride, mean, g, cg_ws, nullptr, st));
+  ICR_HIP_TRY(metric_for_cg(p, batch, w, w_batch_stride, mean, g, cg_ws, nullptr, st, nullptr, 0, nullptr));
   ICR_HIP_TRY(icr::launch_sub(p, batch, g, b, p->n_xi, st));
   ICR_HIP_TRY(icr::launch_cg(p, batch, w, w_batch_stride, g, delta, iterations, 0.0, nullptr, residual_norms,
                              cg_ws, st, metric_for_cg));

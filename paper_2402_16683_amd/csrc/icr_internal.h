@@ -219,6 +219,9 @@ struct RefineMetricArgs {
   void* s_bar; int64_t s_bar_bs;        // coarse cotangent, level l
   int64_t batch;
   const int32_t* halt = nullptr;        // device flag: when set (non-zero) the kernel does nothing
+  // optional: per-workgroup partial sums of <s, w * s> over the level (s the forward's
+  // fine field) at dot[b * dot_bs + workgroup], FP64, each in a fixed order
+  double* dot = nullptr; int64_t dot_bs = 0;
 };
 hipError_t launch_refine_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st);
 hipError_t launch_refine_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st);
@@ -241,6 +244,7 @@ bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipSt
 // Whether the fused kernel takes this level and these buffers (else the caller runs the
 // two sweeps), and its launch.
 bool refine2_metric_ok(const icr_plan* p, int level, const RefineMetricArgs& a);
+int64_t refine2_metric_partials(const icr_plan* p, int level, int64_t batch);  // workgroups per sample
 hipError_t launch_refine2_metric(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st);
 hipError_t launch_refine_adj_generic(const icr_plan* p, int level, const RefineAdjArgs& a,
                                      hipStream_t st);
@@ -265,8 +269,11 @@ __device__ __forceinline__ bool halted(const int32_t* halt) {
 // doing nothing while `halt` (NULL: never) is set. absdelta > 0 stops a sample once one
 // step lowers its CG energy by less than absdelta; iterations_done (optional, device
 // [batch]) receives the steps each sample took.
+// When `dot` is not NULL and the metric's finest level runs in the fused kernel with at
+// most dot_cap wavefronts per sample, that kernel also writes its partial sums of
+// <L v, w * L v> (dot[b * dot_cap + k], k < *ndot) and *ndot is their count; else *ndot = 0.
 using MetricFn = hipError_t (*)(const icr_plan*, int64_t, const void*, int64_t, const void*, void*, void*,
-                                const int32_t*, hipStream_t);
+                                const int32_t*, hipStream_t, double* dot, int dot_cap, int* ndot);
 int64_t cg_workspace_bytes(const icr_plan* p, int64_t batch);
 hipError_t launch_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec,
                      void* x, int32_t iterations, double absdelta, int32_t* iterations_done, double* norms,

@@ -354,14 +354,20 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
 // block rows y0-1 .. y1); each block row also runs the forward: its three coarse rows
 // slide in registers (one new row per block row), and the excitations of the level are
 // the values v the metric adds to the excitation cotangent, loaded once for both.
-template <typename TS, typename M>
+// kDot: the kernel also sums <s, w * s> over the fine blocks it stores (per lane in its
+// march order, a fixed butterfly over each wavefront's lanes, then the workgroup's
+// wavefronts in order), the likelihood part of <v, M v> = <L v, w * L v> + <v, v>, which
+// CG needs as p.q: one partial sum per workgroup.
+template <typename TS, typename M, bool kDot>
 __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Geom g, RefineMetricArgs a, M mats) {
   fetch_args(g.ny, g.nx, g.pairs, g.strips, g.ychunk, g.nfx, g.waves, a.s_in, a.s_in_bs, a.v, a.v_bs, a.w, a.w_bs,
              a.out, a.out_bs, a.s_bar, a.s_bar_bs);
+  if (kDot) fetch_args(a.dot, a.dot_bs);
   if (halted(a.halt)) return;
   const int lane = threadIdx.x % kLanes;
   const int wave = blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
-  if (wave >= g.waves) return;  // whole wavefronts leave; the kernel has no barrier
+  const bool live = wave < g.waves;  // uniform per wavefront
+  if (!kDot && !live) return;        // whole wavefronts leave; without kDot there is no barrier
   const int strip = wave % g.strips, chunk = wave / g.strips;
   const int P = strip * kOwnedPairs + lane - 1;  // blocks x = 2P+1, 2P+2
   const bool pair_ok = P >= 0 && P < g.pairs;
@@ -400,6 +406,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
   };
 
   float rm[4], r0[4];        // coarse rows yb-1 and yb
+  double dot_acc = 0.0;      // kDot
   float A0[2][3], A1[2][3];  // partial coarse cotangents of rows yb-1 and yb, per block and wx
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -422,7 +429,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
       for (int e = 0; e < 10; ++e) S[e] = mats.m.s[e];
     }
     // forward and weight: yv[p][by * 2 + bx] of block 2P+1+p
-    float yv[2][4];
+    float yv[2][4], sv[2][4];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       float win[9];  // columns 2P+p .. 2P+p+2 of rows yb-1, yb, yb+1
@@ -447,6 +454,7 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
         for (int k = 0; k < 9; ++k) s = fmaf(R[c * 9 + k], win[k], s);
 #pragma unroll
         for (int cp = 0; cp <= c; ++cp) s = fmaf(S[sd2(c, cp)], xv[cp], s);
+        sv[p][c] = s;
         yv[p][c] = ok ? s * wv[c] : 0.0f;
       }
     }
@@ -468,6 +476,12 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
         const float4 o = make_float4(xo[0][by * 2] + av.x, xo[0][by * 2 + 1] + av.y, xo[1][by * 2] + av.z,
                                      xo[1][by * 2 + 1] + av.w);
         st4_stream<TS>(out + fine_off(yb, by), o);
+      }
+      if constexpr (kDot) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dot_acc += static_cast<double>(sv[p][c]) * static_cast<double>(yv[p][c]);
       }
     }
     // window contributions, then the y march: row yb-1 is complete after this block row
@@ -505,23 +519,38 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
   };
 
   // block rows y0-1 .. y1; the window of block row yb is coarse rows yb-1 .. yb+1
-  coarse_row(y0 - 2, rm);
-  coarse_row(y0 - 1, r0);
-  Step sa, sb2, sc2;
-  load_step(y0 - 1, sa);
-  load_step(y0, sb2);
-  for (int yb = y0 - 1; yb <= y1; yb += 3) {  // scheduling barriers: as in the adjoint
-    load_step(yb + 2, sc2);
-    __builtin_amdgcn_sched_barrier(0);
-    process(yb, sa);
-    if (yb + 1 > y1) break;
-    load_step(yb + 3, sa);
-    __builtin_amdgcn_sched_barrier(0);
-    process(yb + 1, sb2);
-    if (yb + 2 > y1) break;
-    load_step(yb + 4, sb2);
-    __builtin_amdgcn_sched_barrier(0);
-    process(yb + 2, sc2);
+  if (live) {
+    coarse_row(y0 - 2, rm);
+    coarse_row(y0 - 1, r0);
+    Step sa, sb2, sc2;
+    load_step(y0 - 1, sa);
+    load_step(y0, sb2);
+    for (int yb = y0 - 1; yb <= y1; yb += 3) {  // scheduling barriers: as in the adjoint
+      load_step(yb + 2, sc2);
+      __builtin_amdgcn_sched_barrier(0);
+      process(yb, sa);
+      if (yb + 1 > y1) break;
+      load_step(yb + 3, sa);
+      __builtin_amdgcn_sched_barrier(0);
+      process(yb + 1, sb2);
+      if (yb + 2 > y1) break;
+      load_step(yb + 4, sb2);
+      __builtin_amdgcn_sched_barrier(0);
+      process(yb + 2, sc2);
+    }
+  }
+  if constexpr (kDot) {
+    __shared__ double red[kWavesPerGroup];
+#pragma unroll
+    for (int off = kLanes / 2; off > 0; off >>= 1) dot_acc += __shfl_xor(dot_acc, off, kLanes);
+    if (lane == 0) red[threadIdx.x / kLanes] = dot_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < kWavesPerGroup; ++k) s += red[k];
+      a.dot[b * a.dot_bs + blockIdx.x] = s;
+    }
   }
 }
 
@@ -609,18 +638,23 @@ hipError_t adj2_launch(const icr_plan* p, int level, const M& m, const RefineAdj
   return hipSuccess;
 }
 
-template <typename TS, typename M>
-hipError_t metric2_launch(const icr_plan* p, int level, const M& m, const RefineMetricArgs& a, hipStream_t st) {
+// the metric kernel's layout (the adjoint's) for `batch` samples per launch
+Adj2Geom metric2_geom(const icr_plan* p, int level, int64_t batch) {
   Adj2Geom g;
   g.ny = p->shapes[level][1];
   g.nx = p->shapes[level][2];
   g.pairs = (g.nx - 2) / 2;
   g.strips = (g.pairs + kOwnedPairs - 1) / kOwnedPairs;
   g.nfx = p->shapes[level + 1][2];
-  const int64_t batch = a.batch < 65535 ? a.batch : 65535;
-  g.ychunk = pick_ychunk(g.ny, g.strips, batch);
+  g.ychunk = pick_ychunk(g.ny, g.strips, batch < 65535 ? batch : 65535);
   const int nchunks = (g.ny + g.ychunk - 1) / g.ychunk;
   g.waves = g.strips * nchunks;
+  return g;
+}
+
+template <typename TS, typename M>
+hipError_t metric2_launch(const icr_plan* p, int level, const M& m, const RefineMetricArgs& a, hipStream_t st) {
+  const Adj2Geom g = metric2_geom(p, level, a.batch);
   const unsigned groups = static_cast<unsigned>((g.waves + kWavesPerGroup - 1) / kWavesPerGroup);
   for (int64_t b0 = 0; b0 < a.batch; b0 += 65535) {
     RefineMetricArgs c = a;
@@ -630,8 +664,10 @@ hipError_t metric2_launch(const icr_plan* p, int level, const M& m, const Refine
     c.w = static_cast<const float*>(a.w) + b0 * a.w_bs;
     c.out = static_cast<TS*>(a.out) + b0 * a.out_bs;
     c.s_bar = static_cast<TS*>(a.s_bar) + b0 * a.s_bar_bs;
+    if (a.dot) c.dot = a.dot + b0 * a.dot_bs;
     const dim3 grid(groups, static_cast<unsigned>(c.batch));
-    refine2_metric<TS, M><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    if (a.dot) refine2_metric<TS, M, true><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
+    else refine2_metric<TS, M, false><<<grid, kLanes * kWavesPerGroup, 0, st>>>(g, c, m);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -695,6 +731,10 @@ bool refine2_metric_ok(const icr_plan* p, int level, const RefineMetricArgs& a) 
   if (!aligned2(a.v, vec) || !aligned2(a.out, vec) || !aligned2(a.s_in, 2 * p->elem_bytes) || !aligned2(a.w, 16))
     return false;
   return a.v_bs % 4 == 0 && a.out_bs % 4 == 0 && a.s_in_bs % 2 == 0 && a.w_bs % 4 == 0;
+}
+
+int64_t refine2_metric_partials(const icr_plan* p, int level, int64_t batch) {
+  return (metric2_geom(p, level, batch).waves + kWavesPerGroup - 1) / kWavesPerGroup;
 }
 
 hipError_t launch_refine2_metric(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st) {

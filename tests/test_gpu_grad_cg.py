@@ -312,23 +312,27 @@ def test_cg_energy_rule_halts_the_remaining_kernels():
     """On the full charted workload (FP32) a threshold reached early stops CG on the
     device: the result equals a fixed-count run of that many steps bit for bit, and the
     call takes far less time than the fixed-count run to the limit (the remaining sweep
-    kernels return at once)."""
+    kernels return at once). Three copies of the right-hand side are solved together, so
+    that a step's work outweighs its launches: a kernel that returns at once still costs
+    its launch and the read of the flag (~4 us), and at one right-hand side the ~15
+    launches of a halted step cost ~60 us against ~79 us for a working one."""
     import torch
     from paper_2402_16683_amd import icr as B
     plan, model, w, b = _workload_problem(CHART_FULL, "f32")
     wd = torch.from_numpy(w).float().cuda()
-    bd = C.to_device(b, plan)
+    bd = C.to_device(np.repeat(b, 3, axis=0), plan)
     mb = model.metric(w, C.stored_values(b[0], "f32"))
     bs = C.stored_values(b[0], "f32")
     first = 0.5 * (bs @ bs) ** 2 / (bs @ mb)   # the first step's energy decrease
     absdelta = 1e-3 * first
-    ws = torch.empty(B.icr_cg_workspace_bytes(plan, 1), dtype=torch.uint8, device="cuda")
-    done = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.icr_cg_workspace_bytes(plan, 3), dtype=torch.uint8, device="cuda")
+    done = torch.zeros(3, dtype=torch.int32, device="cuda")
     maxiter = 100
     x_sl = B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws, absdelta=absdelta, iterations_done=done)
     torch.cuda.synchronize()
-    steps = int(done.item())
-    assert 2 <= steps <= 60, steps
+    counts = done.cpu().numpy()
+    steps = int(counts[0])
+    assert np.all(counts == steps) and 2 <= steps <= 60, counts
     x_fix = B.icr_cg_metric(plan, wd, bd, steps, workspace=ws)
     torch.cuda.synchronize()
     assert torch.equal(x_sl, x_fix)
