@@ -174,6 +174,37 @@ def test_cg_batched_right_hand_sides_are_independent():
     assert torch.equal(xb[1:], x0)
 
 
+
+def test_fp32_cg_with_the_split_dot_on_two_right_hand_sides():
+    """FP32 CG on a 2-D chart, where p.q comes from the fused metric level (<L p, w L p>)
+    and the previous p update (p.p) instead of a pass over p and q. Two right-hand sides of
+    different size under the energy rule stop after different step counts; each sample's
+    result equals, bit for bit, the fixed-count run of its step count in the same batch
+    (a stopped sample's x, r, p no longer change), and agrees with the FP64 plan's
+    fixed-count run of that many steps."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan32, _, w, b = _charted_problem("f32", sigma_n=math.sqrt(10.0))
+    plan64 = C.gpu_plan(CHART, "f64")
+    n_xi = plan32.info["n_xi"]
+    b2 = np.concatenate([b, 5.0 * b + W.standard_normal(n_xi, seed=8, batch=1)])
+    wd = torch.from_numpy(w).float().cuda()
+    bd = C.to_device(b2, plan32)
+    absdelta = 1e-4 * n_xi / 10.0
+    done = torch.zeros(2, dtype=torch.int32, device="cuda")
+    x_sl = B.icr_cg_metric(plan32, wd, bd, 80, absdelta=absdelta, iterations_done=done)
+    torch.cuda.synchronize()
+    steps = done.cpu().numpy()
+    print(f"[steps] FP32 energy rule on two right-hand sides: {steps.tolist()}")
+    assert steps[0] != steps[1] and np.all((steps >= 2) & (steps < 80)), steps
+    for k in range(2):
+        x_fix = B.icr_cg_metric(plan32, wd, bd, int(steps[k]))
+        x64 = B.icr_cg_metric(plan64, torch.from_numpy(w).cuda(), C.to_device(b2[k:k + 1], plan64), int(steps[k]))
+        torch.cuda.synchronize()
+        assert torch.equal(x_sl[k], x_fix[k]), k
+        rms, _ = C.rel_errors(C.to_numpy(x_sl[k]), C.to_numpy(x64[0]))
+        assert rms <= 1e-4, (k, rms)
+
 # --- the charted workload at its stated size and shape -------------------------------
 
 CHART_FULL = C.from_workload("icr2d_chart_24to1284", name="cg_chart_24to1284")
