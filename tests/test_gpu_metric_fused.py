@@ -26,6 +26,11 @@ CASES = [
     C.case(2, (11, 8), 4, (0.03, 0.035), "matern52", 0.15, batch=3, name="2d_ragged_m52_b3_f32"),
     C.case(2, (12, 9), 3, (1 / 12, 1 / 9), "matern52", 0.1, chart="logradial2d", batch=2,
            name="2d_chart_oddx_b2_f32"),
+    # the forward stops where the one-launch smallest levels end (16^2 -> 28^2 in one launch,
+    # then the fused 28^2 -> 52^2 level), and the adjoint starts there
+    C.from_workload("icr2d_se_16to1540_b16", depth=2, batch=2, name="2d_se_16to52_b2_f32"),
+    # depth 1: level 0, then the fused 24^2 -> 44^2 level
+    C.from_workload("icr2d_chart_24to1284", depth=1, batch=2, name="2d_chart_24to44_b2_f32"),
     # a 3-D plan takes the two sweeps (the same kernels with and without the w and +v
     # epilogues)
     C.from_workload("icr3d_m52_10to388", depth=3, batch=2, name="3d_m52_10to52_b2_f32"),
