@@ -53,6 +53,28 @@ constexpr bool kShell2 = false;
 template <>
 constexpr bool kShell2<Shell2> = true;
 
+// Shell levels: a wavefront's matrix rows for the block rows it marches, staged in its own
+// LDS slice by one round of vector loads. Read with scalar loads instead, every block row
+// waits for its own row (the scheduling barriers that keep the data prefetch ahead keep
+// those loads in place), and a short march is a chain of such waits. Marches longer than
+// kStagedRows block rows read the table directly.
+constexpr int kStagedRows = 10;
+constexpr int kRowFloats = 48;  // R (36) and the lower sqrtD (10), padded to whole 16-byte vectors
+__device__ __forceinline__ void stage_rows(const Shell2& m, float* lds, int set0, int n, int lane) {
+  constexpr int kVec = kRowFloats / 4;
+  constexpr int kRounds = (kStagedRows * kVec + 63) / 64;
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) {
+    const int i = lane + k * 64;
+    if (i < n * kVec) {
+      const int r = i / kVec, q = i - r * kVec;
+      const int set = min(max(set0 + r, 0), m.nsets - 1);
+      reinterpret_cast<float4*>(lds + r * kRowFloats)[q] =
+          reinterpret_cast<const float4*>(m.tab + static_cast<int64_t>(set) * kShellStride)[q];
+    }
+  }
+}
+
 struct Adj2Geom {
   int ny, nx;   // coarse shape
   int pairs;    // (nx - 2) / 2 block pairs per row
@@ -94,6 +116,13 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
   // zeroed after the load, so no load sits under a branch
   const int Pc = min(max(P, 0), g.pairs - 1);
   auto fine_off = [&](int yb, int by) { return static_cast<int64_t>(2 * (yb - 1) + by) * g.nfx + 4 * Pc; };
+  // shell levels: the matrix rows of block rows y0-1 .. y1 (sets yb - 1) in LDS
+  __shared__ float staged_rows[kShell2<M> ? kWavesPerGroup : 1][kShell2<M> ? kStagedRows * kRowFloats : 1];
+  float* my_rows = staged_rows[kShell2<M> ? threadIdx.x / kLanes : 0];
+  const bool staged = kShell2<M> && y1 - y0 + 2 <= kStagedRows;  // uniform per wavefront
+  if constexpr (kShell2<M>) {
+    if (staged) stage_rows(mats, my_rows, y0 - 2, y1 - y0 + 2, lane);
+  }
 
   struct Row {
     float4 r[2];  // cotangent of the pair's fine rows 2(yb-1) and 2(yb-1)+1
@@ -118,11 +147,19 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_adj(Adj2Geom 
     const bool ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
     float R[36], S[10];  // this block row's matrices
     if constexpr (kShell2<M>) {
-      const auto row = row_of(mats, yb - 1);
+      if (staged) {
+        const float* lr = my_rows + (yb - (y0 - 1)) * kRowFloats;
 #pragma unroll
-      for (int e = 0; e < 36; ++e) R[e] = row[e];
+        for (int e = 0; e < 36; ++e) R[e] = lr[e];
 #pragma unroll
-      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+        for (int e = 0; e < 10; ++e) S[e] = lr[36 + e];
+      } else {
+        const auto row = row_of(mats, yb - 1);
+#pragma unroll
+        for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
@@ -253,6 +290,13 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
     const float2 u = Io<TS>::ld2(row), v = Io<TS>::ld2(row + 2);
     r[0] = u.x; r[1] = u.y; r[2] = v.x; r[3] = v.y;
   };
+  // shell levels: the matrix rows of coarse rows y0 .. y1-1 (sets y - 1) in LDS
+  __shared__ float staged_rows[kShell2<M> ? kWavesPerGroup : 1][kShell2<M> ? kStagedRows * kRowFloats : 1];
+  float* my_rows = staged_rows[kShell2<M> ? threadIdx.x / kLanes : 0];
+  const bool staged = kShell2<M> && y1 - y0 <= kStagedRows;  // uniform per wavefront
+  if constexpr (kShell2<M>) {
+    if (staged) stage_rows(mats, my_rows, y0 - 1, y1 - y0, lane);
+  }
 
   struct Step {
     float c[4];    // coarse row y + 1, columns 2P .. 2P+3
@@ -273,11 +317,19 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_fwd(Fwd2Geom 
     float o[2][4];
     float R[36], S[10];  // this coarse row's matrices
     if constexpr (kShell2<M>) {
-      const auto row = row_of(mats, y - 1);
+      if (staged) {
+        const float* lr = my_rows + (y - y0) * kRowFloats;
 #pragma unroll
-      for (int e = 0; e < 36; ++e) R[e] = row[e];
+        for (int e = 0; e < 36; ++e) R[e] = lr[e];
 #pragma unroll
-      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+        for (int e = 0; e < 10; ++e) S[e] = lr[36 + e];
+      } else {
+        const auto row = row_of(mats, y - 1);
+#pragma unroll
+        for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
@@ -389,6 +441,13 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
     const float2 u = Io<TS>::ld2(row), t = Io<TS>::ld2(row + 2);
     r[0] = u.x; r[1] = u.y; r[2] = t.x; r[3] = t.y;
   };
+  // shell levels: the matrix rows of block rows y0-1 .. y1 (sets yb - 1) in LDS
+  __shared__ float staged_rows[kShell2<M> ? kWavesPerGroup : 1][kShell2<M> ? kStagedRows * kRowFloats : 1];
+  float* my_rows = staged_rows[kShell2<M> ? threadIdx.x / kLanes : 0];
+  const bool staged = kShell2<M> && live && y1 - y0 + 2 <= kStagedRows;  // uniform per wavefront
+  if constexpr (kShell2<M>) {
+    if (staged) stage_rows(mats, my_rows, y0 - 2, y1 - y0 + 2, lane);
+  }
 
   struct Step {
     float c[4];    // coarse row yb + 1, columns 2P .. 2P+3
@@ -417,11 +476,19 @@ __global__ void __launch_bounds__(kLanes * kWavesPerGroup) refine2_metric(Adj2Ge
     const bool ok = pair_ok && yb >= 1 && yb <= g.ny - 2;
     float R[36], S[10];  // this block row's matrices
     if constexpr (kShell2<M>) {
-      const auto row = row_of(mats, yb - 1);
+      if (staged) {
+        const float* lr = my_rows + (yb - (y0 - 1)) * kRowFloats;
 #pragma unroll
-      for (int e = 0; e < 36; ++e) R[e] = row[e];
+        for (int e = 0; e < 36; ++e) R[e] = lr[e];
 #pragma unroll
-      for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+        for (int e = 0; e < 10; ++e) S[e] = lr[36 + e];
+      } else {
+        const auto row = row_of(mats, yb - 1);
+#pragma unroll
+        for (int e = 0; e < 36; ++e) R[e] = row[e];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) S[e] = row[36 + e];
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 36; ++e) R[e] = mats.m.r[e];
