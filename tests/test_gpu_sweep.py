@@ -29,6 +29,10 @@ CASES = [
     C.from_workload("icr3d_m52_10to388", depth=4, batch=2, name="3d_m52_10to100_b2_f32"),
     C.from_workload("icr3d_m52_10to388", depth=4, precision="bf16", name="3d_m52_10to100_bf16"),
     C.from_workload("icr2d_chart_24to1284", depth=4, name="2d_chart_24to324_f32"),
+    # shell rows: marches of at most 10 block rows take their matrix rows from LDS, longer
+    # ones read the table row by row; at batch 4096 the 44^2 -> 84^2 level marches 11 rows
+    # per wavefront (forward, adjoint and the metric's fused level)
+    C.from_workload("icr2d_chart_24to1284", depth=2, batch=4096, name="2d_chart_24to84_b4096_f32"),
     C.from_workload("icr3d_chart_10to388", depth=4, batch=2, name="3d_chart_10to100_b2_f32"),
     C.from_workload("icr3d_chart_10to388", depth=3, precision="bf16", name="3d_chart_10to52_bf16"),
     C.from_workload("icr3d_chart_10to388", depth=3, precision="f64", name="3d_chart_10to52_f64"),
