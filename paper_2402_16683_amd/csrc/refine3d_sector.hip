@@ -820,9 +820,11 @@ hipError_t adj_launch_tile(const icr_plan* p, int level, const M& k, const Refin
 
 // 16 block pairs (x) by 32 block rows (y): one 512-thread workgroup per CU at this
 // register budget; measured fastest of 16x16, 32x8, 64x4, 32x16, 16x32 and 64x8 on
-// the 388^3 level. With FP32 storage 16 x 24 tiles (two 384-thread workgroups per CU)
-// do better there (110-114 us against 115-118 us over repeated sweeps; 16 x 20, 26, 28,
-// 48 and 32 x 32 were slower), with BF16 storage they do not (80-88 us against 76-80).
+// the 388^3 level. With FP32 storage 16 x 24 tiles (one 384-thread workgroup per CU:
+// about 200 registers per lane leave room for two wavefronts per SIMD) do better there
+// (110-114 us against 115-118 us over repeated sweeps; 16 x 20, 26, 28, 48 and 32 x 32
+// were slower, and so was capping the registers for two workgroups per CU, which
+// spilled), with BF16 storage they do not (80-88 us against 76-80).
 // Levels of at most 100 rows take 16x16 tiles (two workgroups per CU; the step 1.7 us
 // shorter, the shell-charted step 1 us); 16x8 tiles on the smallest levels changed nothing.
 template <typename TS>
