@@ -38,7 +38,7 @@ __device__ __forceinline__ TA gwave_sum(TA v) {
   return v;
 }
 
-// one wavefront per output row; lanes stride the row with eight loads in flight
+// one wavefront per output row; lanes stride the row with sixteen loads in flight
 template <typename TS, bool kLower>
 __device__ void level0_task(const GroupTask& t, int64_t u0) {
   using TA = typename Acc<TS>::type;
@@ -55,16 +55,18 @@ __device__ void level0_task(const GroupTask& t, int64_t u0) {
 #pragma unroll
   for (int u = 0; u < kU; ++u) part[u] = 0;
   for (int64_t base = j0; base < j1; base += 64 * kU) {
-    TA mv[kU], xv[kU];
+    TA mv[kU];
+    TS xr[kU];  // widened after all loads are issued, as in level0_kernel
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int64_t j = base + u * 64 + lane;
       const int64_t jc = j < j1 ? j : j0;
       mv[u] = m[jc];
-      xv[u] = load_acc(in + jc);
+      xr[u] = in[jc];
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) part[u] += (base + u * 64 + lane < j1 ? mv[u] : TA(0)) * xv[u];
+    for (int u = 0; u < kU; ++u) part[u] += (base + u * 64 + lane < j1 ? mv[u] : TA(0)) * load_acc(&xr[u]);
   }
 #pragma unroll
   for (int w = kU / 2; w > 0; w >>= 1)

@@ -34,22 +34,26 @@ __global__ void __launch_bounds__(256) level0_kernel(const typename Acc<TS>::typ
   // kU independent partial sums so kU loads of the row are in flight at once (rows of up
   // to 1024, the 3-D workload's 10^3 level 0 included, in one round); a lane past the end
   // of the row reads an in-bounds element and adds zero, so no load sits in a divergent
-  // branch
+  // branch. The input is loaded in its storage type and widened after the scheduling
+  // barrier: widening each bfloat16 as it arrived made the compiler wait for every input
+  // load in turn (8.6 against 4.2 us per product at 1000 x 1000).
   constexpr int kU = 16;
   TA part[kU];
 #pragma unroll
   for (int u = 0; u < kU; ++u) part[u] = 0;
   for (int64_t base = j0; base < j1; base += 64 * kU) {
-    TA mv[kU], xv[kU];
+    TA mv[kU];
+    TS xr[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int64_t j = base + u * 64 + lane;
       const int64_t jc = j < j1 ? j : j0;
       mv[u] = m[jc];
-      xv[u] = load_acc(in + jc);
+      xr[u] = in[jc];
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) part[u] += (base + u * 64 + lane < j1 ? mv[u] : TA(0)) * xv[u];
+    for (int u = 0; u < kU; ++u) part[u] += (base + u * 64 + lane < j1 ? mv[u] : TA(0)) * load_acc(&xr[u]);
   }
 #pragma unroll
   for (int w = kU / 2; w > 0; w >>= 1)
