@@ -102,24 +102,44 @@ int dot_blocks(int64_t n, int v) {
 // value). Each thread loads all of its kStride / kDotThreads values before adding them (in
 // index order): the partials were just written by other compute units, so each load waits
 // on memory, and a loop of dependent loads waited once per value.
+// load_partials issues the loads, reduce_partials adds them, so a kernel can have other
+// loads in flight in the same round.
+template <int kStride>
+struct Partials {
+  double u[kStride / kDotThreads];
+};
 template <int kStride = kDotBlocks>
-__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t b, int count,
-                                               double* sh) {
-  constexpr int kPer = kStride / kDotThreads;
-  double u[kPer];
+__device__ __forceinline__ Partials<kStride> load_partials(const double* __restrict__ partial, int64_t b,
+                                                           int count) {
+  Partials<kStride> h;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
+  for (int i = 0; i < kStride / kDotThreads; ++i) {
     const int k = threadIdx.x + i * kDotThreads;
-    const double x = partial[b * kStride + min(k, count - 1)];  // in bounds; unused past count
-    u[i] = k < count ? x : 0.0;
+    h.u[i] = partial[b * kStride + min(k, count - 1)];  // in bounds; unused past count
   }
+  return h;
+}
+template <int kStride>
+__device__ __forceinline__ double reduce_partials(const Partials<kStride>& h, int count, double* sh) {
   double v = 0.0;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) v += u[i];
+  for (int i = 0; i < kStride / kDotThreads; ++i) v += threadIdx.x + i * kDotThreads < count ? h.u[i] : 0.0;
   const double s = block_sum(v, sh);
   __syncthreads();  // sh is reused by the caller
   return s;
 }
+template <int kStride = kDotBlocks>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int64_t b, int count,
+                                               double* sh) {
+  return reduce_partials(load_partials<kStride>(partial, b, count), count, sh);
+}
+
+// The update kernels load a thread's first kPre groups before the step size is known (the
+// loads do not depend on it), so they are in flight with the loads of the partial sums
+// instead of after them: one memory round for what took three to five. Groups past the
+// end are loaded at the last group and left unused. A charted 2-D step (2.2 M elements,
+// 537 workgroups) gives every thread four groups.
+constexpr int kPre = 4;
 
 // partial[b][blk] = sum over this block's share of a[b] * c[b]
 template <typename T, int V>
@@ -157,37 +177,55 @@ __global__ void __launch_bounds__(kDotThreads) update_xr(T* __restrict__ x, T* _
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
   if (!sc[b].active[par]) return;  // uniform per workgroup (one sample per grid row)
+  T* px = x + b * n;
+  T* pr = r + b * n;
+  const T* pp = p + b * n;
+  const T* pqv = q + b * n;
+  const int64_t ng = n / V;
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  const int64_t g0 = int64_t(blockIdx.x) * kDotThreads + threadIdx.x;
+  Chunk<T, V> xv[kPre], rv[kPre], pv[kPre], qv[kPre];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const int64_t g = min(g0 + j * step, ng - 1) * V;
+    xv[j] = ldv<T, V>(px + g);
+    rv[j] = ldv<T, V>(pr + g);
+    pv[j] = ldv<T, V>(pp + g);
+    qv[j] = ldv<T, V>(pqv + g);
+  }
+  const double rr = sc[b].rr[par];
   double pq;
   if constexpr (kSplit) {
-    const double lik = sum_partials<kMetricDots>(pq_partial, b, npq, sh);
-    const double pp = first ? sc[b].rr[par] : sum_partials(pp_partial, b, gridDim.x, sh);
-    pq = lik + pp;
+    const auto hl = load_partials<kMetricDots>(pq_partial, b, npq);
+    const auto hp = load_partials(pp_partial, b, first ? 1 : gridDim.x);  // unused at the first
+    const double lik = reduce_partials(hl, npq, sh);
+    pq = lik + (first ? rr : reduce_partials(hp, gridDim.x, sh));
   } else {
     pq = sum_partials(pq_partial, b, gridDim.x, sh);
   }
-  const double alpha = pq != 0.0 ? sc[b].rr[par] / pq : 0.0;
+  const double alpha = pq != 0.0 ? rr / pq : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[b].pq = pq;
     sc[b].alpha = alpha;
   }
   const T a = static_cast<T>(alpha);
-  T* px = x + b * n;
-  T* pr = r + b * n;
-  const T* pp = p + b * n;
-  const T* pqv = q + b * n;
   double acc = 0.0;
-  const int64_t step = int64_t(gridDim.x) * kDotThreads;
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
-    Chunk<T, V> xv = ldv<T, V>(px + g * V), rv = ldv<T, V>(pr + g * V);
-    const Chunk<T, V> pv = ldv<T, V>(pp + g * V), qv = ldv<T, V>(pqv + g * V);
+  auto update = [&](Chunk<T, V>& xc, Chunk<T, V>& rc, const Chunk<T, V>& pc, const Chunk<T, V>& qc, int64_t g) {
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      xv.v[k] += a * pv.v[k];
-      rv.v[k] = rv.v[k] - a * qv.v[k];
-      acc += static_cast<double>(rv.v[k]) * static_cast<double>(rv.v[k]);
+      xc.v[k] += a * pc.v[k];
+      rc.v[k] = rc.v[k] - a * qc.v[k];
+      acc += static_cast<double>(rc.v[k]) * static_cast<double>(rc.v[k]);
     }
-    stv<T, V>(px + g * V, xv);
-    stv<T, V>(pr + g * V, rv);
+    stv<T, V>(px + g * V, xc);
+    stv<T, V>(pr + g * V, rc);
+  };
+#pragma unroll
+  for (int j = 0; j < kPre; ++j)
+    if (g0 + j * step < ng) update(xv[j], rv[j], pv[j], qv[j], g0 + j * step);
+  for (int64_t g = g0 + kPre * step; g < ng; g += step) {
+    Chunk<T, V> xc = ldv<T, V>(px + g * V), rc = ldv<T, V>(pr + g * V);
+    update(xc, rc, ldv<T, V>(pp + g * V), ldv<T, V>(pqv + g * V), g);
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) rr_partial[b * kDotBlocks + blockIdx.x] = s;
@@ -219,6 +257,18 @@ __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const
     }
     return;
   }
+  T* pp = p + b * n;
+  const T* pr = r + b * n;
+  const int64_t ng = n / V;
+  const int64_t step = int64_t(gridDim.x) * kDotThreads;
+  const int64_t g0 = int64_t(blockIdx.x) * kDotThreads + threadIdx.x;
+  Chunk<T, V> pv[kPre], rv[kPre];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const int64_t g = min(g0 + j * step, ng - 1) * V;
+    pv[j] = ldv<T, V>(pp + g);
+    rv[j] = ldv<T, V>(pr + g);
+  }
   const double rr_new = sum_partials(rr_partial, b, gridDim.x, sh);
   const double rr = c.rr[par];
   const double beta = rr != 0.0 ? rr_new / rr : 0.0;
@@ -233,19 +283,21 @@ __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const
   }
   if (stop) return;
   const T bt = static_cast<T>(beta);
-  T* pp = p + b * n;
-  const T* pr = r + b * n;
   double acc = 0.0;
-  const int64_t step = int64_t(gridDim.x) * kDotThreads;
-  for (int64_t g = int64_t(blockIdx.x) * kDotThreads + threadIdx.x; g < n / V; g += step) {
-    Chunk<T, V> pv = ldv<T, V>(pp + g * V);
-    const Chunk<T, V> rv = ldv<T, V>(pr + g * V);
+  auto update = [&](Chunk<T, V>& pc, const Chunk<T, V>& rc, int64_t g) {
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      pv.v[k] = rv.v[k] + bt * pv.v[k];
-      if constexpr (kPP) acc += static_cast<double>(pv.v[k]) * static_cast<double>(pv.v[k]);
+      pc.v[k] = rc.v[k] + bt * pc.v[k];
+      if constexpr (kPP) acc += static_cast<double>(pc.v[k]) * static_cast<double>(pc.v[k]);
     }
-    stv<T, V>(pp + g * V, pv);
+    stv<T, V>(pp + g * V, pc);
+  };
+#pragma unroll
+  for (int j = 0; j < kPre; ++j)
+    if (g0 + j * step < ng) update(pv[j], rv[j], g0 + j * step);
+  for (int64_t g = g0 + kPre * step; g < ng; g += step) {
+    Chunk<T, V> pc = ldv<T, V>(pp + g * V);
+    update(pc, ldv<T, V>(pr + g * V), g);
   }
   if constexpr (kPP) {
     const double s = block_sum(acc, sh);
