@@ -343,21 +343,23 @@ def test_cg_energy_rule_halts_the_remaining_kernels():
     """On the full charted workload (FP32) a threshold reached early stops CG on the
     device: the result equals a fixed-count run of that many steps bit for bit, and the
     call takes far less time than the fixed-count run to the limit (the remaining sweep
-    kernels return at once). Three copies of the right-hand side are solved together, so
-    that a step's work outweighs its launches: a kernel that returns at once still costs
-    its launch and the read of the flag (~4 us), and at one right-hand side the ~15
-    launches of a halted step cost ~60 us against ~79 us for a working one."""
+    kernels return at once). Eight copies of the right-hand side are solved together, so
+    that a step's work outweighs its launches: every iteration is enqueued at once, and a
+    halted step still costs the host its ~15 launches (36-80 us per step, depending on the
+    host's speed at the time), against ~113 us for a working step at three right-hand
+    sides and over twice that at eight."""
     import torch
     from paper_2402_16683_amd import icr as B
     plan, model, w, b = _workload_problem(CHART_FULL, "f32")
     wd = torch.from_numpy(w).float().cuda()
-    bd = C.to_device(np.repeat(b, 3, axis=0), plan)
+    nrhs = 8
+    bd = C.to_device(np.repeat(b, nrhs, axis=0), plan)
     mb = model.metric(w, C.stored_values(b[0], "f32"))
     bs = C.stored_values(b[0], "f32")
     first = 0.5 * (bs @ bs) ** 2 / (bs @ mb)   # the first step's energy decrease
     absdelta = 1e-3 * first
-    ws = torch.empty(B.icr_cg_workspace_bytes(plan, 3), dtype=torch.uint8, device="cuda")
-    done = torch.zeros(3, dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.icr_cg_workspace_bytes(plan, nrhs), dtype=torch.uint8, device="cuda")
+    done = torch.zeros(nrhs, dtype=torch.int32, device="cuda")
     maxiter = 100
     x_sl = B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws, absdelta=absdelta, iterations_done=done)
     torch.cuda.synchronize()
