@@ -36,6 +36,13 @@ struct GroupTask {
   const void* add;  // adjoint epilogue: out += add (storage type)
 };
 
+// Up to kInlineTasks tasks of one grouped launch passed by value in the kernel arguments
+// (about 1.3 KB), so a small group needs no table copy before its launches.
+constexpr int kInlineTasks = 8;
+struct TaskPack {
+  GroupTask t[kInlineTasks];
+};
+
 // Workgroups a task takes in a grouped launch.
 int64_t task_workgroups(const GroupTask& t);
 
@@ -43,6 +50,11 @@ int64_t task_workgroups(const GroupTask& t);
 // of one storage precision; `workgroups` = the sum of task_workgroups.
 hipError_t launch_grouped_step(int precision, const GroupTask* dev_tasks, int ntasks, int64_t workgroups,
                                hipStream_t st);
+
+// The same launch with the tasks (ntasks <= kInlineTasks, sorted by wg0, the first 0) in
+// the kernel arguments.
+hipError_t launch_grouped_step_inline(int precision, const TaskPack& pack, int ntasks, int64_t workgroups,
+                                      hipStream_t st);
 
 // The steps of one sample's sweep in order: op 0 forward (in = xi, out = s), 1 adjoint
 // (in = s_bar, out = xi_bar), 2 metric (in = v, out = L^T (w * L v) + v, w the weights

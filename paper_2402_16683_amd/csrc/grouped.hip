@@ -241,8 +241,10 @@ __device__ void adjoint_task(const GroupTask& t, int64_t u0) {
   }
 }
 
-template <typename TS>
-__global__ void __launch_bounds__(kGroupThreads) grouped_step(const GroupTask* __restrict__ tasks, int ntasks) {
+// One workgroup's share of a grouped step; `tasks` is the device table or the task pack
+// passed in the kernel arguments.
+template <typename TS, typename Tasks>
+__device__ __forceinline__ void group_step(const Tasks& tasks, int ntasks) {
   // the task of this workgroup: the last one whose first workgroup is <= blockIdx.x
   const int64_t wg = blockIdx.x;
   int lo = 0, hi = ntasks - 1;
@@ -269,6 +271,18 @@ __global__ void __launch_bounds__(kGroupThreads) grouped_step(const GroupTask* _
   }
 }
 
+template <typename TS>
+__global__ void __launch_bounds__(kGroupThreads) grouped_step(const GroupTask* __restrict__ tasks, int ntasks) {
+  group_step<TS>(tasks, ntasks);
+}
+
+// The same step with at most kInlineTasks tasks carried in the kernel arguments: no table
+// copy has to precede the launch.
+template <typename TS>
+__global__ void __launch_bounds__(kGroupThreads) grouped_step_inline(TaskPack pack, int ntasks) {
+  group_step<TS>(pack.t, ntasks);
+}
+
 }  // namespace
 
 int64_t task_workgroups(const GroupTask& t) {
@@ -285,6 +299,19 @@ hipError_t launch_grouped_step(int precision, const GroupTask* dev_tasks, int nt
     case ICR_F64: grouped_step<double><<<grid, kGroupThreads, 0, st>>>(dev_tasks, ntasks); break;
     case ICR_F32: grouped_step<float><<<grid, kGroupThreads, 0, st>>>(dev_tasks, ntasks); break;
     default: grouped_step<bf16_t><<<grid, kGroupThreads, 0, st>>>(dev_tasks, ntasks); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grouped_step_inline(int precision, const TaskPack& pack, int ntasks, int64_t workgroups,
+                                      hipStream_t st) {
+  if (ntasks <= 0 || workgroups <= 0) return hipSuccess;
+  if (ntasks > kInlineTasks || workgroups > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(workgroups));
+  switch (precision) {
+    case ICR_F64: grouped_step_inline<double><<<grid, kGroupThreads, 0, st>>>(pack, ntasks); break;
+    case ICR_F32: grouped_step_inline<float><<<grid, kGroupThreads, 0, st>>>(pack, ntasks); break;
+    default: grouped_step_inline<bf16_t><<<grid, kGroupThreads, 0, st>>>(pack, ntasks); break;
   }
   return hipGetLastError();
 }

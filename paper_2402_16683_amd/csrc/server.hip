@@ -9,9 +9,10 @@
 //   2. in grouped mode, gathers the pending requests whose refinement levels are all
 //      below the large-step size, of any prior and op, oldest first, into a group while
 //      fewer than group_streams groups run: every request's workspace comes from the
-//      arena, the steps of all sweeps go to the device in one table, and the k-th grouped
-//      launch applies the k-th step of every sweep; each request's completion event
-//      follows its own last step,
+//      arena, the steps of all sweeps go to the device in one table (a small group, at
+//      most eight tasks per launch, passes them in the kernel arguments instead), and the
+//      k-th grouped launch applies the k-th step of every sweep; each request's
+//      completion event follows its own last step,
 //   3. forms homogeneous batches from the other pending requests with the same
 //      (plan, op), oldest first, up to the largest power of two <= min(pending,
 //      max_batch), admits a batch only if its buffers fit in the fixed HBM arena (first
@@ -466,14 +467,25 @@ bool launch_group(icr_server* s, int si, std::vector<int64_t>& ids) {
       if (L.ntasks > 0) launches.push_back(L);
     }
   }
-  if (e == hipSuccess)
+  // small groups (every launch at most kInlineTasks tasks, a lone request's sweep among
+  // them) carry their tasks in the kernel arguments: no table copy precedes the launches
+  bool inline_tasks = true;
+  for (const Launch& L : launches) inline_tasks = inline_tasks && L.ntasks <= icr::kInlineTasks;
+  if (e == hipSuccess && !inline_tasks)
     e = hipMemcpyAsync(s->dev_tables[si], host, used * sizeof(icr::GroupTask), hipMemcpyHostToDevice, st);
   Group* g = new Group;
   g->ids = ids;
   g->stream = si;
   for (size_t li = 0; li < launches.size() && e == hipSuccess; ++li) {
     const Launch& L = launches[li];
-    e = icr::launch_grouped_step(L.precision, s->dev_tables[si] + L.first, L.ntasks, L.workgroups, st);
+    if (inline_tasks) {
+      icr::TaskPack pack;
+      std::memset(&pack, 0, sizeof(pack));
+      std::copy(host + L.first, host + L.first + L.ntasks, pack.t);
+      e = icr::launch_grouped_step_inline(L.precision, pack, L.ntasks, L.workgroups, st);
+    } else {
+      e = icr::launch_grouped_step(L.precision, s->dev_tables[si] + L.first, L.ntasks, L.workgroups, st);
+    }
     for (size_t i = 0; i < ids.size() && e == hipSuccess; ++i) {
       if (last_launch[i].first != li) continue;
       Request& r = s->requests[ids[i]];
