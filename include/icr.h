@@ -278,9 +278,14 @@ icr_status icr_cg_metric(const icr_plan* plan, int64_t batch, const void* w, int
  *   residual_norms  optional device double [batch][maxiter + 1]: |r_k|, a stopped sample's
  *                   last value repeated to the end.
  *   workspace       icr_cg_workspace_bytes(plan, batch) bytes, 256-byte aligned.
- * Every kernel of all maxiter iterations is enqueued at once (no host round trip); once
- * every sample has stopped, a flag in the workspace makes the remaining kernels return
- * at once. FP64 and FP32 plans only; asynchronous on hip_stream; allocates nothing.
+ * The iterations are enqueued without waiting on the device (no host round trip). Once
+ * every sample has stopped, a flag in the workspace makes the kernels still queued
+ * return at once, and the device raises a word of pinned host memory with it, which the
+ * host reads (never waits on) before enqueuing each iteration: from then on no further
+ * iteration is enqueued. FP64 and FP32 plans only; asynchronous on hip_stream. Allocates
+ * no device memory; a call takes a 64-byte pinned host word from a process-wide pool,
+ * allocating one when every word is still held by a call whose work has not finished
+ * (the words are kept until the process ends).
  */
 icr_status icr_cg_metric_sl(const icr_plan* plan, int64_t batch, const void* w, int64_t w_batch_stride,
                             const void* b, void* x, double absdelta, int32_t maxiter, int32_t* iterations_done,

@@ -21,8 +21,12 @@
 // sample whose step lowered E by less than absdelta keeps that step and is frozen (its x,
 // r, p no longer change). Every iteration up to the maximum is enqueued at once; when the
 // last sample freezes, a device flag makes the remaining kernels (metric sweeps included)
-// return at once, so nothing waits on the host.
+// return at once, so nothing waits on the host. The p update that raises the flag also
+// writes it to a word of pinned host memory, which the host reads (without waiting)
+// before it enqueues each iteration: once set, the rest are not enqueued at all.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "icr_internal.h"
 
@@ -242,7 +246,8 @@ template <typename T, int V, bool kPP>
 __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const T* __restrict__ r, int64_t n,
                                                         CgScalars* sc, const double* __restrict__ rr_partial, int par,
                                                         int iter, double absdelta, double* norms, int stride,
-                                                        int32_t* halt, double* __restrict__ pp_partial) {
+                                                        int32_t* halt, int32_t* host_halt,
+                                                        double* __restrict__ pp_partial) {
   __shared__ double sh[kDotThreads];
   if (halted(halt)) return;
   const int64_t b = blockIdx.y;
@@ -279,7 +284,10 @@ __global__ void __launch_bounds__(kDotThreads) update_p(T* __restrict__ p, const
     c.active[nx] = stop ? 0 : 1;
     c.iters += 1;
     if (norms) norms[b * stride + iter + 1] = sqrt(rr_new);
-    if (stop && halt && atomicSub(&halt[1], 1) == 1) halt[0] = 1;
+    if (stop && halt && atomicSub(&halt[1], 1) == 1) {
+      halt[0] = 1;
+      if (host_halt) __hip_atomic_store(host_halt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
   if (stop) return;
   const T bt = static_cast<T>(beta);
@@ -365,6 +373,66 @@ __global__ void cg_report(const CgScalars* sc, int32_t* iterations_done, int bat
   if (b < batch) iterations_done[b] = sc[b].iters;
 }
 
+// Pinned host words the p update raises with the halt flag, one per CG call in flight. A
+// word returns to the pool when its call's work is done (its event has fired), so a late
+// write from an earlier call never stops a later one.
+struct HostHalt {
+  int device = -1;
+  int32_t* word = nullptr;      // host address
+  int32_t* dev_word = nullptr;  // the same word as the device addresses it
+  hipEvent_t done = nullptr;    // recorded after the call's last kernel
+  bool in_use = false;
+};
+std::mutex g_halt_mu;
+std::vector<HostHalt*> g_halt_pool;
+
+HostHalt* acquire_host_halt(int device) {
+  std::lock_guard<std::mutex> lk(g_halt_mu);
+  for (HostHalt* h : g_halt_pool)
+    if (!h->in_use && h->device == device && hipEventQuery(h->done) == hipSuccess) {
+      h->in_use = true;
+      *h->word = 0;
+      return h;
+    }
+  HostHalt* h = new HostHalt;
+  h->device = device;
+  void* w = nullptr;
+  if (hipHostMalloc(&w, 64, hipHostMallocCoherent) != hipSuccess) {
+    delete h;
+    return nullptr;  // the call then runs without the host watch
+  }
+  h->word = static_cast<int32_t*>(w);
+  void* dw = nullptr;
+  if (hipHostGetDevicePointer(&dw, w, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(w);
+    delete h;
+    return nullptr;
+  }
+  h->dev_word = static_cast<int32_t*>(dw);
+  *h->word = 0;
+  h->in_use = true;
+  g_halt_pool.push_back(h);
+  return h;
+}
+
+void release_host_halt(HostHalt* h, hipStream_t st) {
+  const bool recorded = hipEventRecord(h->done, st) == hipSuccess;
+  std::lock_guard<std::mutex> lk(g_halt_mu);
+  // reusable once the event fires; if it could not be recorded, never (a word whose
+  // call may still be running must not be handed out)
+  h->in_use = !recorded;
+}
+
+// Releases a call's host word on every return path.
+struct HostHaltGuard {
+  HostHalt* h;
+  hipStream_t st;
+  ~HostHaltGuard() {
+    if (h) release_host_halt(h, st);
+  }
+};
+
 template <typename T, int V>
 hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs, const void* bvec, void* x,
                   int32_t iterations, double absdelta, int32_t* iterations_done, double* norms, void* mws, T* r,
@@ -377,6 +445,10 @@ hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs,
   const int nb = static_cast<int>(batch);
   // the halt flag only with early stopping: fixed-count runs pay nothing for it
   int32_t* halt = absdelta > 0.0 ? halt_flag : nullptr;
+  int dev = 0;
+  HostHalt* hh = halt && hipGetDevice(&dev) == hipSuccess ? acquire_host_halt(dev) : nullptr;
+  const HostHaltGuard guard{hh, st};
+  int32_t* host_halt = hh ? hh->dev_word : nullptr;
   T* xv = static_cast<T*>(x);
   cg_init<T, V><<<grid, kDotThreads, 0, st>>>(xv, r, pv, static_cast<const T*>(bvec), n, rr_partial, halt);
   hipError_t e = hipGetLastError();
@@ -385,6 +457,8 @@ hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   bool pp_ready = true;  // p.p is known for the current p (r.r at the start)
   for (int it = 0; it < iterations; ++it) {
+    // every sample has stopped: the remaining iterations would do nothing
+    if (hh && __atomic_load_n(hh->word, __ATOMIC_ACQUIRE) != 0) break;
     const int par = it & 1;
     int nlik = 0;
     if ((e = metric(p, batch, w, w_bs, pv, q, mws, halt, st, lik_partial, kMetricDots, &nlik)) != hipSuccess)
@@ -403,10 +477,10 @@ hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs,
     // the next iteration can split p.q only if this p update sums p.p
     if (nlik > 0)
       update_p<T, V, true><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride,
-                                                         halt, pp_partial);
+                                                         halt, host_halt, pp_partial);
     else
       update_p<T, V, false><<<grid, kDotThreads, 0, st>>>(pv, r, n, sc, rr_partial, par, it, absdelta, norms, stride,
-                                                          halt, nullptr);
+                                                          halt, host_halt, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     pp_ready = nlik > 0;
   }
@@ -423,6 +497,7 @@ hipError_t run_cg(const icr_plan* p, int64_t batch, const void* w, int64_t w_bs,
 }
 
 bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
+
 
 }  // namespace
 

@@ -342,12 +342,12 @@ def test_cg_energy_rule_matches_the_oracle():
 def test_cg_energy_rule_halts_the_remaining_kernels():
     """On the full charted workload (FP32) a threshold reached early stops CG on the
     device: the result equals a fixed-count run of that many steps bit for bit, and the
-    call takes far less time than the fixed-count run to the limit (the remaining sweep
-    kernels return at once). Eight copies of the right-hand side are solved together, so
-    that a step's work outweighs its launches: every iteration is enqueued at once, and a
-    halted step still costs the host its ~15 launches (36-80 us per step, depending on the
-    host's speed at the time), against ~113 us for a working step at three right-hand
-    sides and over twice that at eight."""
+    call takes far less time than the fixed-count run to the limit: kernels queued after
+    the halt return at once, and the host stops enqueuing once it reads the pinned word
+    the device raises with the flag. Eight copies of the right-hand side are solved
+    together, so that a working step (~113 us at three, over twice that at eight) clearly
+    outweighs the launches of the few halted steps the host enqueues before it sees the
+    word (36-80 us of host time each)."""
     import torch
     from paper_2402_16683_amd import icr as B
     plan, model, w, b = _workload_problem(CHART_FULL, "f32")
