@@ -384,3 +384,47 @@ def test_cg_energy_rule_halts_the_remaining_kernels():
     t_fix = timed(lambda: B.icr_cg_metric(plan, wd, bd, maxiter, workspace=ws))
     print(f"[timing] energy rule stopped after {steps} of {maxiter} steps: {t_sl:.2f} ms vs {t_fix:.2f} ms")
     assert t_sl < 0.8 * t_fix
+
+
+def test_cg_energy_rule_calls_back_to_back():
+    """Early-stopping solves enqueued back to back without synchronising, on one stream and
+    on two: a solve whose threshold stops it after one step, then one that stops by the
+    rule after more steps (two right-hand sides of different size: different counts).
+    Each result equals, bit for bit, the fixed-count run of the steps it took. So the
+    pinned host word that an earlier solve's device work raises never stops a later solve
+    early (each call holds its own word, handed out again only after its call's work has
+    finished), and the host, which stops enqueuing once it reads the word, never stops a
+    solve before it has finished."""
+    import torch
+    from paper_2402_16683_amd import icr as B
+    plan, _, w, b = _charted_problem("f32", sigma_n=math.sqrt(10.0))
+    n_xi = plan.info["n_xi"]
+    wd = torch.from_numpy(w).float().cuda()
+    bd = C.to_device(np.concatenate([b, 5.0 * b + W.standard_normal(n_xi, seed=8, batch=1)]), plan)
+    maxiter = 80
+    rule = 1e-4 * n_xi / 10.0                    # stops after 9 and 11 steps
+    thresholds = [1e30, rule, 1e30, rule]        # 1e30: every sample stops after its first step
+    ws_bytes = B.icr_cg_workspace_bytes(plan, 2)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()                   # default priority
+    runs = []
+    for k, ad in enumerate(thresholds):
+        st = main if k < 2 else side
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        x = torch.empty_like(bd)
+        done = torch.zeros(2, dtype=torch.int32, device="cuda")
+        if st is side:
+            side.wait_stream(main)
+        B.icr_cg_metric(plan, wd, bd, maxiter, x=x, workspace=ws, stream=st, absdelta=ad, iterations_done=done)
+        runs.append((ad, x, done, ws))
+    torch.cuda.synchronize()
+    counts = [r[2].cpu().numpy() for r in runs]
+    print(f"[steps] {[c.tolist() for c in counts]}")
+    assert np.all(counts[0] == 1) and np.all(counts[2] == 1)
+    for c in (counts[1], counts[3]):
+        assert c[0] != c[1] and np.all((c >= 2) & (c < maxiter)), c
+    for (ad, x, done, ws), c in zip(runs, counts):
+        for j in range(2):
+            x_fix = B.icr_cg_metric(plan, wd, bd, int(c[j]))
+            torch.cuda.synchronize()
+            assert torch.equal(x[j], x_fix[j]), (ad, j, int(c[j]))
