@@ -639,9 +639,14 @@ Mat2 mat2_of(const icr_plan* p, int level) {
 // 16384 (16 per SIMD over 1024 SIMDs: 2-D step 0.2447 ms at 8, 0.2405 at 16, 0.252 at
 // 32, 0.265 at 64 per SIMD for 1540^2 x 16); one sample gets 2048 (charted 1284^2
 // metric 57.6 us against 62.0 at 16384 and 57.1 at 1024), three get 4096 (76.2 us
-// against 93.7 at 16384).
+// against 93.7 at 16384). Levels of at most 400 rows get at most 2048 wavefronts, since
+// their short marches spent much of each chunk on its two halo rows: steps of the 2-D SE
+// prior at 1540^2 x 16 0.2307 ms against 0.2392 (the 388^2 -> 772^2 adjoint 19.1 against
+// 27.2 us; 3072, 4096 and 6144 in between), 196^2 x 1024 407 against 428 us, x 256 116
+// against 125 us, 388^2 x 64 84.5 against 91 us, 772^2 x 4 55.2 against 54.0 us; the
+// charted CG step at three right-hand sides 110.0 against 112.2 us.
 int pick_ychunk(int rows, int strips, int64_t batch) {
-  const int64_t budget = std::min<int64_t>(16384, 1024 * (batch + 1));
+  const int64_t budget = std::min<int64_t>(rows <= 400 ? 2048 : 16384, 1024 * (batch + 1));
   int64_t chunks = budget / (int64_t(strips) * batch);
   chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, rows));
   return static_cast<int>((rows + chunks - 1) / chunks);

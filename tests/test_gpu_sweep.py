@@ -19,19 +19,22 @@ CASES = [
     C.from_workload("icr2d_se_16to1540_b16", batch=2, name="2d_se_full_b2_f32"),
     C.from_workload("icr2d_se_16to1540_b16", batch=2, precision="bf16", name="2d_se_full_b2_bf16"),
     # the 2-D workload at its benchmarked batch of 16: the 2-D kernels size their row marches
-    # by the batch, so the last two levels march 6 and 2 rows per wavefront (batch 2 marches
-    # 4 and 2 rows there)
+    # by the batch and the level, so the last three levels march 6, 13 and 4 rows per
+    # wavefront (batch 2 marches 4, 2 and 1 rows there)
     C.from_workload("icr2d_se_16to1540_b16", name="2d_se_full_b16_f32"),
     C.from_workload("icr2d_se_16to1540_b16", precision="bf16", name="2d_se_full_b16_bf16"),
-    # a large batch of small grids: marches of 2 to 7 rows with a ragged last chunk
+    # a large batch of small grids: every level in two chunks per sample (marches of 7 to
+    # 50 rows); ragged last chunks are covered by the batch-16 case (770 rows in marches of
+    # 6, 386 in marches of 13)
     C.from_workload("icr2d_se_16to1540_b16", depth=4, batch=1024, name="2d_se_16to196_b1024_f32"),
     C.from_workload("icr2d_se_16to1540_b16", depth=5, precision="f64", name="2d_se_16to388_f64"),
     C.from_workload("icr3d_m52_10to388", depth=4, batch=2, name="3d_m52_10to100_b2_f32"),
     C.from_workload("icr3d_m52_10to388", depth=4, precision="bf16", name="3d_m52_10to100_bf16"),
     C.from_workload("icr2d_chart_24to1284", depth=4, name="2d_chart_24to324_f32"),
     # shell rows: marches of at most 10 block rows take their matrix rows from LDS, longer
-    # ones read the table row by row; at batch 4096 the 44^2 -> 84^2 level marches 11 rows
-    # per wavefront (forward, adjoint and the metric's fused level)
+    # ones read the table row by row; at batch 4096 the 44^2 -> 84^2 level marches all its
+    # 42 rows (44 in the adjoint) in one wavefront per sample (forward, adjoint and the
+    # metric's fused level)
     C.from_workload("icr2d_chart_24to1284", depth=2, batch=4096, name="2d_chart_24to84_b4096_f32"),
     C.from_workload("icr3d_chart_10to388", depth=4, batch=2, name="3d_chart_10to100_b2_f32"),
     C.from_workload("icr3d_chart_10to388", depth=3, precision="bf16", name="3d_chart_10to52_bf16"),
