@@ -765,8 +765,8 @@ hipError_t adj2_any(const icr_plan* p, int level, const RefineAdjArgs& a, hipStr
 }
 
 // Stationary or shell-charted 2-D levels in FP32 arithmetic with an even coarse row
-// length, vector-aligned fine rows and batch strides; everything else takes the generic
-// kernels.
+// length; everything else takes the generic kernels. Slices off a vector boundary (a
+// level-0 size that is not a multiple of 4) run the same kernels with element accesses.
 bool eligible2(const icr_plan* p, int level) {
   if (p->ndim != 2 || p->precision == ICR_F64) return false;
   if (p->charted && !(p->shell && p->lev[level].shell_tab)) return false;
@@ -781,28 +781,44 @@ bool eligible2(const icr_plan* p, int level) {
 bool try_refine2_fwd(const icr_plan* p, int level, const RefineFwdArgs& a, hipStream_t st, hipError_t* err) {
   if (!eligible2(p, level)) return false;
   const int el = p->elem_bytes;
-  if (!aligned2(a.xi, 4 * el) || !aligned2(a.s_out, 4 * el) || !aligned2(a.s_in, 2 * el)) return false;
-  if (a.xi_bs % 4 || a.s_out_bs % 4 || a.s_in_bs % 2) return false;
+  if (!aligned2(a.xi, el) || !aligned2(a.s_out, el) || !aligned2(a.s_in, el)) return false;
   if (a.w && (!aligned2(a.w, 16) || a.w_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? fwd2_any<float>(p, level, a, st) : fwd2_any<bf16_t>(p, level, a, st);
+  const bool vec_ok = aligned2(a.xi, 4 * el) && aligned2(a.s_out, 4 * el) && aligned2(a.s_in, 2 * el) &&
+                      a.xi_bs % 4 == 0 && a.s_out_bs % 4 == 0 && a.s_in_bs % 2 == 0;
+  if (p->precision == ICR_F32)
+    *err = vec_ok ? fwd2_any<float>(p, level, a, st) : fwd2_any<f32u>(p, level, a, st);
+  else
+    *err = vec_ok ? fwd2_any<bf16_t>(p, level, a, st) : fwd2_any<bf16u>(p, level, a, st);
   return true;
 }
 
 bool try_refine2_adj(const icr_plan* p, int level, const RefineAdjArgs& a, hipStream_t st, hipError_t* err) {
   if (!eligible2(p, level)) return false;
-  const int vec = 4 * p->elem_bytes;
-  if (!aligned2(a.y, vec) || !aligned2(a.xi_bar, vec) || (a.add && !aligned2(a.add, vec))) return false;
-  if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? adj2_any<float>(p, level, a, st) : adj2_any<bf16_t>(p, level, a, st);
+  const int el = p->elem_bytes;
+  const int vec = 4 * el;
+  if (!aligned2(a.y, el) || !aligned2(a.xi_bar, el) || !aligned2(a.s_bar, el) || (a.add && !aligned2(a.add, el)))
+    return false;
+  const bool vec_ok = aligned2(a.y, vec) && aligned2(a.xi_bar, vec) && (!a.add || aligned2(a.add, vec)) &&
+                      a.y_bs % 4 == 0 && a.xi_bar_bs % 4 == 0 && (!a.add || a.add_bs % 4 == 0);
+  if (p->precision == ICR_F32)
+    *err = vec_ok ? adj2_any<float>(p, level, a, st) : adj2_any<f32u>(p, level, a, st);
+  else
+    *err = vec_ok ? adj2_any<bf16_t>(p, level, a, st) : adj2_any<bf16u>(p, level, a, st);
   return true;
+}
+
+// the metric level's vector accesses are aligned (else it runs with element accesses)
+static bool metric2_vec_ok(const icr_plan* p, const RefineMetricArgs& a) {
+  const int el = p->elem_bytes;
+  return aligned2(a.v, 4 * el) && aligned2(a.out, 4 * el) && aligned2(a.s_in, 2 * el) && a.v_bs % 4 == 0 &&
+         a.out_bs % 4 == 0 && a.s_in_bs % 2 == 0;
 }
 
 bool refine2_metric_ok(const icr_plan* p, int level, const RefineMetricArgs& a) {
   if (!eligible2(p, level)) return false;
-  const int vec = 4 * p->elem_bytes;
-  if (!aligned2(a.v, vec) || !aligned2(a.out, vec) || !aligned2(a.s_in, 2 * p->elem_bytes) || !aligned2(a.w, 16))
-    return false;
-  return a.v_bs % 4 == 0 && a.out_bs % 4 == 0 && a.s_in_bs % 2 == 0 && a.w_bs % 4 == 0;
+  const int el = p->elem_bytes;
+  if (!aligned2(a.v, el) || !aligned2(a.out, el) || !aligned2(a.s_in, el) || !aligned2(a.s_bar, el)) return false;
+  return aligned2(a.w, 16) && a.w_bs % 4 == 0;
 }
 
 int64_t refine2_metric_partials(const icr_plan* p, int level, int64_t batch) {
@@ -810,7 +826,9 @@ int64_t refine2_metric_partials(const icr_plan* p, int level, int64_t batch) {
 }
 
 hipError_t launch_refine2_metric(const icr_plan* p, int level, const RefineMetricArgs& a, hipStream_t st) {
-  return p->precision == ICR_F32 ? metric2_any<float>(p, level, a, st) : metric2_any<bf16_t>(p, level, a, st);
+  const bool vec_ok = metric2_vec_ok(p, a);
+  if (p->precision == ICR_F32) return vec_ok ? metric2_any<float>(p, level, a, st) : metric2_any<f32u>(p, level, a, st);
+  return vec_ok ? metric2_any<bf16_t>(p, level, a, st) : metric2_any<bf16u>(p, level, a, st);
 }
 
 }  // namespace icr

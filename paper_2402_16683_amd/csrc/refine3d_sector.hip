@@ -695,7 +695,8 @@ __global__ void __launch_bounds__(kTP * kTR) refine3_adj_sector(Adj3Geom g, Refi
 bool aligned_to(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
 
 // Can this level run in the sector kernels? (3-D, FP32 arithmetic, stationary and
-// reflection-symmetric, an even coarse x extent, vector-aligned rows and batches.)
+// reflection-symmetric, an even coarse x extent; slices off a vector boundary take the
+// element-access storage forms.)
 bool sector_eligible(const icr_plan* p, int level) {
   if (p->ndim != 3 || p->precision == ICR_F64) return false;
   const bool stationary = !p->charted && p->lev[level].sector_ok;
@@ -833,7 +834,7 @@ hipError_t adj_launch(const icr_plan* p, int level, const RefineAdjArgs& a, hipS
   if (p->shell && p->shapes[level][1] <= 100) return adj_launch_tile<TS, 16, 16>(p, level, shell_mats(m), a, st);
   if (p->shell) return adj_launch_tile<TS, 16, 32>(p, level, shell_mats(m), a, st);
   if (p->shapes[level][1] <= 100) return adj_launch_tile<TS, 16, 16>(p, level, stationary_mats(m), a, st);
-  if (std::is_same<TS, float>::value) return adj_launch_tile<TS, 16, 24>(p, level, stationary_mats(m), a, st);
+  if (IsF32Storage<TS>::value) return adj_launch_tile<TS, 16, 24>(p, level, stationary_mats(m), a, st);
   return adj_launch_tile<TS, 16, 32>(p, level, stationary_mats(m), a, st);
 }
 template <typename TS>
@@ -928,10 +929,16 @@ bool try_refine3_fwd_sector(const icr_plan* p, int level, const RefineFwdArgs& a
   if (!sector_eligible(p, level)) return false;
   const int el = p->elem_bytes;
   const int vec = 4 * el;  // four fine values per vector access
-  if (!aligned_to(a.xi, vec) || !aligned_to(a.s_out, vec) || !aligned_to(a.s_in, 2 * el)) return false;
-  if (a.xi_bs % 4 || a.s_out_bs % 4 || a.s_in_bs % 2) return false;
+  if (!aligned_to(a.xi, el) || !aligned_to(a.s_out, el) || !aligned_to(a.s_in, el)) return false;
   if (a.w && (!aligned_to(a.w, 16) || a.w_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? fwd_launch<float>(p, level, a, st) : fwd_launch<bf16_t>(p, level, a, st);
+  // slices off a vector boundary (a level-0 size that is not a multiple of 4) run the same
+  // kernels with element accesses
+  const bool vec_ok = aligned_to(a.xi, vec) && aligned_to(a.s_out, vec) && aligned_to(a.s_in, 2 * el) &&
+                      a.xi_bs % 4 == 0 && a.s_out_bs % 4 == 0 && a.s_in_bs % 2 == 0;
+  if (p->precision == ICR_F32)
+    *err = vec_ok ? fwd_launch<float>(p, level, a, st) : fwd_launch<f32u>(p, level, a, st);
+  else
+    *err = vec_ok ? fwd_launch<bf16_t>(p, level, a, st) : fwd_launch<bf16u>(p, level, a, st);
   return true;
 }
 
@@ -940,9 +947,15 @@ bool try_refine3_adj_sector(const icr_plan* p, int level, const RefineAdjArgs& a
   if (!sector_eligible(p, level)) return false;
   const int el = p->elem_bytes;
   const int vec = 4 * el;
-  if (!aligned_to(a.y, vec) || !aligned_to(a.xi_bar, vec) || (a.add && !aligned_to(a.add, vec))) return false;
-  if (a.y_bs % 4 || a.xi_bar_bs % 4 || (a.add && a.add_bs % 4)) return false;
-  *err = p->precision == ICR_F32 ? adj_launch<float>(p, level, a, st) : adj_launch<bf16_t>(p, level, a, st);
+  if (!aligned_to(a.y, el) || !aligned_to(a.xi_bar, el) || !aligned_to(a.s_bar, el) ||
+      (a.add && !aligned_to(a.add, el)))
+    return false;
+  const bool vec_ok = aligned_to(a.y, vec) && aligned_to(a.xi_bar, vec) && (!a.add || aligned_to(a.add, vec)) &&
+                      a.y_bs % 4 == 0 && a.xi_bar_bs % 4 == 0 && (!a.add || a.add_bs % 4 == 0);
+  if (p->precision == ICR_F32)
+    *err = vec_ok ? adj_launch<float>(p, level, a, st) : adj_launch<f32u>(p, level, a, st);
+  else
+    *err = vec_ok ? adj_launch<bf16_t>(p, level, a, st) : adj_launch<bf16u>(p, level, a, st);
   return true;
 }
 

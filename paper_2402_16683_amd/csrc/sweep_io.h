@@ -41,6 +41,45 @@ template <> struct Io<bf16_t> {
   }
 };
 
+// Level slices that start off a vector boundary: a level-0 size n0^d that is not a
+// multiple of 4 shifts every later level's slice of a xi-shaped buffer (and every sample
+// of a batch) by 1-3 elements. These storage tags keep the layout and the element size but
+// read and write element by element instead of in vectors (still contiguous over a
+// wavefront), so such plans run the same kernels with the same arithmetic.
+struct f32u {
+  float v;
+};
+struct bf16u {
+  bf16_t v;
+};
+template <typename TS> struct IsF32Storage { static constexpr bool value = false; };
+template <> struct IsF32Storage<float> { static constexpr bool value = true; };
+template <> struct IsF32Storage<f32u> { static constexpr bool value = true; };
+
+template <> struct Io<f32u> {
+  static __device__ __forceinline__ float4 ld4(const f32u* p) { return make_float4(p[0].v, p[1].v, p[2].v, p[3].v); }
+  static __device__ __forceinline__ float2 ld2(const f32u* p) { return make_float2(p[0].v, p[1].v); }
+  static __device__ __forceinline__ void st4(f32u* p, float4 v) {
+    p[0].v = v.x; p[1].v = v.y; p[2].v = v.z; p[3].v = v.w;
+  }
+  static __device__ __forceinline__ void st1(f32u* p, float v) { p->v = v; }
+  static __device__ __forceinline__ void st2(f32u* p, float a, float b) { p[0].v = a; p[1].v = b; }
+};
+__device__ __forceinline__ float widen_bf16(bf16_t u) { return __uint_as_float(static_cast<uint32_t>(u) << 16); }
+template <> struct Io<bf16u> {
+  static __device__ __forceinline__ float4 ld4(const bf16u* p) {
+    return make_float4(widen_bf16(p[0].v), widen_bf16(p[1].v), widen_bf16(p[2].v), widen_bf16(p[3].v));
+  }
+  static __device__ __forceinline__ float2 ld2(const bf16u* p) { return make_float2(widen_bf16(p[0].v), widen_bf16(p[1].v)); }
+  static __device__ __forceinline__ void st4(bf16u* p, float4 v) {
+    p[0].v = f32_to_bf16(v.x); p[1].v = f32_to_bf16(v.y); p[2].v = f32_to_bf16(v.z); p[3].v = f32_to_bf16(v.w);
+  }
+  static __device__ __forceinline__ void st1(bf16u* p, float v) { p->v = f32_to_bf16(v); }
+  static __device__ __forceinline__ void st2(bf16u* p, float a, float b) {
+    p[0].v = f32_to_bf16(a); p[1].v = f32_to_bf16(b);
+  }
+};
+
 // Workgroups are handed to the 8 XCDs round-robin (workgroup w runs on XCD w % 8),
 // and each XCD has its own L2. Renumber so that XCD k works through a contiguous
 // range of logical tiles: neighbouring tiles, which read each other's halo, then
@@ -67,6 +106,16 @@ __device__ __forceinline__ float4 ld4_stream<bf16_t>(const bf16_t* p) {
   return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
+template <>
+__device__ __forceinline__ float4 ld4_stream<f32u>(const f32u* p) {
+  return make_float4(__builtin_nontemporal_load(&p[0].v), __builtin_nontemporal_load(&p[1].v),
+                     __builtin_nontemporal_load(&p[2].v), __builtin_nontemporal_load(&p[3].v));
+}
+template <>
+__device__ __forceinline__ float4 ld4_stream<bf16u>(const bf16u* p) {
+  return make_float4(widen_bf16(__builtin_nontemporal_load(&p[0].v)), widen_bf16(__builtin_nontemporal_load(&p[1].v)),
+                     widen_bf16(__builtin_nontemporal_load(&p[2].v)), widen_bf16(__builtin_nontemporal_load(&p[3].v)));
+}
 template <typename TS>
 __device__ __forceinline__ void st4_stream(TS* p, float4 v);
 template <>
@@ -78,6 +127,20 @@ template <>
 __device__ __forceinline__ void st4_stream<bf16_t>(bf16_t* p, float4 v) {
   const nt_u2 w = {pack_bf16(v.x, v.y), pack_bf16(v.z, v.w)};
   __builtin_nontemporal_store(w, reinterpret_cast<nt_u2*>(p));
+}
+template <>
+__device__ __forceinline__ void st4_stream<f32u>(f32u* p, float4 v) {
+  __builtin_nontemporal_store(v.x, &p[0].v);
+  __builtin_nontemporal_store(v.y, &p[1].v);
+  __builtin_nontemporal_store(v.z, &p[2].v);
+  __builtin_nontemporal_store(v.w, &p[3].v);
+}
+template <>
+__device__ __forceinline__ void st4_stream<bf16u>(bf16u* p, float4 v) {
+  __builtin_nontemporal_store(f32_to_bf16(v.x), &p[0].v);
+  __builtin_nontemporal_store(f32_to_bf16(v.y), &p[1].v);
+  __builtin_nontemporal_store(f32_to_bf16(v.z), &p[2].v);
+  __builtin_nontemporal_store(f32_to_bf16(v.w), &p[3].v);
 }
 
 // Cross-lane moves over the whole wavefront (DPP wave shifts); lane 0 (from_left) and

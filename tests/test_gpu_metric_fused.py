@@ -29,6 +29,8 @@ CASES = [
     # the forward stops where the one-launch smallest levels end (16^2 -> 28^2 in one launch,
     # then the fused 28^2 -> 52^2 level), and the adjoint starts there
     C.from_workload("icr2d_se_16to1540_b16", depth=2, batch=2, name="2d_se_16to52_b2_f32"),
+    # an odd level-0 size: the fused level (and the sweeps) with element accesses
+    C.case(2, (11, 11), 4, (0.04, 0.04), "matern32", 0.15, batch=2, name="2d_odd11_b2_f32"),
     # depth 1: level 0, then the fused 24^2 -> 44^2 level
     C.from_workload("icr2d_chart_24to1284", depth=1, batch=2, name="2d_chart_24to44_b2_f32"),
     # a 3-D plan takes the two sweeps (the same kernels with and without the w and +v

@@ -54,6 +54,15 @@ CASES = [
     C.from_workload("icr3d_chart_10to388", depth=2, precision="f64", name="3d_chart_10to28_f64"),
     C.case(3, (6, 7, 5), 2, (1 / 6, 1 / 7, 1 / 5), "matern52", 0.2, chart="logradial_cyl3d",
            chart_params=(0.2, 1.5, 1.2, 0.7), batch=2, name="3d_chart_ragged_f32"),
+    # odd level-0 sizes: every later level's slice (and every sample, the batch stride n_xi
+    # being odd) starts 1-3 elements off a vector boundary, so the fast 2-D and 3-D kernels
+    # run with element accesses (their level-0 refinement, of odd row length, is generic)
+    C.case(3, (9, 9, 9), 3, (0.06, 0.06, 0.06), "matern52", 0.2, batch=2, name="3d_odd9_b2_f32"),
+    C.case(3, (9, 9, 9), 3, (0.06, 0.06, 0.06), "matern52", 0.2, batch=2, precision="bf16", name="3d_odd9_b2_bf16"),
+    C.case(2, (11, 11), 4, (0.04, 0.04), "matern32", 0.15, batch=3, name="2d_odd11_b3_f32"),
+    C.case(2, (11, 13), 3, (0.05, 0.04), "matern52", 0.2, batch=2, precision="bf16", name="2d_odd11x13_b2_bf16"),
+    C.case(2, (11, 11), 3, (1 / 11, 1 / 11), "matern32", 0.1, chart="logradial2d", batch=2,
+           name="2d_chart_odd11_b2_f32"),
     C.case(2, (6, 6), 0, (0.2, 0.2), "matern52", 0.5, batch=2, name="2d_depth0_f32"),
     C.case(3, (3, 3, 3), 1, (0.2, 0.2, 0.2), "matern52", 0.5, precision="f64", name="3d_min_f64"),
 ]
