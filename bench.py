@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests in the served-mode stream (0: skip the served measurement)")
     ap.add_argument("--serve-priors", type=int, default=24)
+    ap.add_argument("--serve-large-step", type=int, default=0,
+                    help="grouped served form: fine pixels of a level from which a request runs its own kernels "
+                         "(0: the library default)")
     ap.add_argument("--bf16-steps", type=int, default=20,
                     help="timed steps of the same workload in BF16 storage (0: skip; f32 workloads only)")
     ap.add_argument("--cf-reps", type=int, default=11,
@@ -178,7 +181,7 @@ def cpu_baseline_parallel(key: str, workers: int, quiet: bool) -> dict:
                       f"numpy FP64, {wall:.1f} s wall (process start included)"}
 
 
-def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
+def served(n_requests: int, n_priors: int, quiet: bool, large_step: int = 0) -> dict:
     """Mixed 1-D/2-D/3-D forward/adjoint/metric requests over a pool of priors with random
     length scales, submitted by prior configuration: every server starts with an empty
     plan cache and builds each prior's plan when its first request arrives (inside that
@@ -194,7 +197,8 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
     priors = S.draw_priors(n_priors, seed=5)
     configs = [pr.config() for pr in priors]
     _, pool = S.build_pool(priors, slots=8, plans=False)
-    kinds = {"served": dict(max_batch=16, n_streams=8, use_graphs=False, grouped=True, group_streams=2),
+    kinds = {"served": dict(max_batch=16, n_streams=8, use_graphs=False, grouped=True, group_streams=2,
+                            large_step=large_step),
              "served_homogeneous": dict(max_batch=16, n_streams=8, use_graphs=True),
              "plain": dict(max_batch=1, n_streams=1, use_graphs=False)}
 
@@ -226,6 +230,9 @@ def served(n_requests: int, n_priors: int, quiet: bool) -> dict:
              "mean_batch": float(bs[ok].mean()), "launch_sequences": st["batches"] + st["groups"],
              "grouped_requests": st["grouped_requests"], "plans_built": st["plans_built"],
              "admissions_deferred": st["admissions_deferred"], "refused": int((~ok).sum())}
+        dims = np.array([priors[k].ndim for k in stream.prior])
+        r["p50_ms_by_dim"] = {str(d): float(np.percentile(lat[ok & (dims == d)], 50) * 1e3)
+                              for d in (1, 2, 3) if np.any(ok & (dims == d))}
         log(f"served: {name} at {rate:.0f} req/s: p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms "
             f"{r['fine_px_per_s']:.3g} px/s, mean batch {r['mean_batch']:.2f}, grouped {r['grouped_requests']}", quiet)
         return r
@@ -814,7 +821,7 @@ def main():
             charted = W.WORKLOADS[key]["chart"] != "regular"
             out["workloads"][key] = workload_leg(B, key, 20, args.quiet, cg_iters=200 if charted else 0)
     if args.serve_requests > 0 and not args.copy_probe:
-        out["served"] = served(args.serve_requests, args.serve_priors, args.quiet)
+        out["served"] = served(args.serve_requests, args.serve_priors, args.quiet, args.serve_large_step)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.quiet)
         out["cpu_baseline"]["host"] = host_info()
