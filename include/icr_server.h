@@ -12,7 +12,8 @@
  *    its own completion event follows its last step. At most group_streams groups run at
  *    once, so requests that arrive while groups run are gathered into the next one. A
  *    request with a refinement level of at least large_step fine pixels (bandwidth-bound,
- *    not launch-bound) runs as below instead, with the specialised kernels.
+ *    not launch-bound), or on a 1-D prior (whose own sweep runs its small levels in one
+ *    fused launch), runs as below instead, with the specialised kernels.
  *  - homogeneous batches: pending requests with the same (plan, op), oldest first, in
  *    batches of a power of two up to max_batch, admitted when the batch's buffers fit the
  *    arena (first fit): gather the inputs into a contiguous batch, run the batched sweep (a

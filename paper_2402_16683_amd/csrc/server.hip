@@ -6,13 +6,13 @@
 // thread
 //   1. retires work whose completion events have fired (records completion times, returns
 //      memory to the arena, marks captured graphs free),
-//   2. in grouped mode, gathers the pending requests whose refinement levels are all
-//      below the large-step size, of any prior and op, oldest first, into a group while
-//      fewer than group_streams groups run: every request's workspace comes from the
-//      arena, the steps of all sweeps go to the device in one table (a small group, at
-//      most eight tasks per launch, passes them in the kernel arguments instead), and the
-//      k-th grouped launch applies the k-th step of every sweep; each request's
-//      completion event follows its own last step,
+//   2. in grouped mode, gathers the pending requests on 2-D and 3-D priors whose
+//      refinement levels are all below the large-step size, of any prior and op, oldest
+//      first, into a group while fewer than group_streams groups run: every request's
+//      workspace comes from the arena, the steps of all sweeps go to the device in one
+//      table (a small group, at most eight tasks per launch, passes them in the kernel
+//      arguments instead), and the k-th grouped launch applies the k-th step of every
+//      sweep; each request's completion event follows its own last step,
 //   3. forms homogeneous batches from the other pending requests with the same
 //      (plan, op), oldest first, up to the largest power of two <= min(pending,
 //      max_batch), admits a batch only if its buffers fit in the fixed HBM arena (first
@@ -157,6 +157,10 @@ struct PlanEntry {
   int64_t n_xi, n_out;
   int elem, acc;
   bool large = false;   // a refinement level has at least large_step fine pixels
+  // requests run on their own kernels, never in groups: large plans, and 1-D plans (their
+  // own sweep runs the small levels in one fused launch where a group takes one launch
+  // per level, and a long 1-D sweep held its group stream through all its steps)
+  bool own = false;
   bool owned = false;   // built by the server for a prior configuration (destroyed with it)
   int64_t active = 0;   // requests pending or in flight
   double last_used = 0.0;
@@ -640,7 +644,7 @@ void retire(icr_server* s) {
 }
 
 bool groupable(const icr_server* s, const Request& r) {
-  return s->cfg.grouped && !s->plans[r.plan_id].large;
+  return s->cfg.grouped && !s->plans[r.plan_id].own;
 }
 
 void remove_pending(icr_server* s, const std::vector<int64_t>& ids) {
@@ -730,6 +734,7 @@ bool plan_is_large(const icr_plan* p, int64_t large) {
 int32_t add_plan(icr_server* s, const icr_plan* plan, bool owned, const std::string& key) {
   PlanEntry pe{plan, plan->n_xi, plan->n_out, plan->elem_bytes, plan->precision == ICR_F64 ? 8 : 4};
   pe.large = plan_is_large(plan, s->cfg.large_step);
+  pe.own = pe.large || plan->ndim == 1;
   pe.owned = owned;
   pe.key = key;
   pe.last_used = now_s();
