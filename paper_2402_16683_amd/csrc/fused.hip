@@ -86,6 +86,29 @@ __device__ __forceinline__ TA* level_lds(TA* base, const FusedArgs& g, int l) {
   return (l & 1) ? base + g.lds_even : base;
 }
 
+// Every fused level's R and sqrtD into LDS in one round: each thread loads its element
+// of every level before storing any (a loop over the levels waited for each level's
+// loads in turn). Levels past K reload the last one and are not stored.
+template <int NC, int NW, typename TA>
+__device__ __forceinline__ void copy_mats(TA* mats, const FusedArgs& g, int t) {
+  constexpr int kPer = NC * NW + NC * NC;
+  static_assert(kPer <= kFusedThreads, "one element of each level per thread");
+  if (t >= kPer || g.K < 1) return;
+  TA v[kMaxFused];
+#pragma unroll
+  for (int l = 0; l < kMaxFused; ++l) {
+    const int lc = l < g.K ? l : g.K - 1;
+    v[l] = t < NC * NW ? static_cast<const TA*>(g.r[lc])[t] : static_cast<const TA*>(g.s[lc])[t - NC * NW];
+  }
+#pragma unroll
+  for (int l = 0; l < kMaxFused; ++l)
+    if (l < g.K) mats[l * kPer + t] = v[l];
+}
+
+// rows of the level-0 factor a wavefront reduces (n0 <= kMaxLevel0, one row per wavefront
+// of the workgroup at a time)
+constexpr int kLevel0Rows = (kMaxLevel0 + kFusedThreads / 64 - 1) / (kFusedThreads / 64);
+
 template <int D, typename TS>
 __global__ void __launch_bounds__(kFusedThreads) fused_fwd(FusedArgs g) {
   using TA = typename Acc<TS>::type;
@@ -100,21 +123,25 @@ __global__ void __launch_bounds__(kFusedThreads) fused_fwd(FusedArgs g) {
   const TS* xi = static_cast<const TS*>(g.xi) + b * g.n_xi;
   TS* ws = static_cast<TS*>(g.ws) + b * g.ws_bs;
   // every input is fetched in one round before any level is computed
-  copy_widen(xl, xi, g.pre, t, kFusedThreads);
-  for (int l = 0; l < g.K; ++l) {
-    for (int e = t; e < NC * NW; e += kFusedThreads) mats[l * (NC * NW + NC * NC) + e] = static_cast<const TA*>(g.r[l])[e];
-    for (int e = t; e < NC * NC; e += kFusedThreads)
-      mats[l * (NC * NW + NC * NC) + NC * NW + e] = static_cast<const TA*>(g.s[l])[e];
-  }
+  copy_widen<16>(xl, xi, g.pre, t, kFusedThreads);
+  copy_mats<NC, NW>(mats, g, t);
   // level 0
   TA* s0 = level_lds(fields, g, 0);
-  if (g.level0) {  // one wavefront per row of L00, lanes stride the row
-    __syncthreads();  // the prefetched xi_0
+  if (g.level0) {  // one wavefront per row of L00 (n0 <= 64: a lane per column)
     const TA* L = static_cast<const TA*>(g.l0);
     const int lane = t % 64, wv = t / 64;
-    for (int i = wv; i < g.n0; i += kFusedThreads / 64) {
-      TA acc = 0;
-      for (int j = lane; j <= i; j += 64) acc += L[int64_t(i) * g.n0 + j] * xl[j];
+    TA lrow[kLevel0Rows];  // this wavefront's rows, loaded with the other inputs
+#pragma unroll
+    for (int r = 0; r < kLevel0Rows; ++r) {
+      const int i = min(wv + r * (kFusedThreads / 64), g.n0 - 1);
+      lrow[r] = L[int64_t(i) * g.n0 + min(lane, g.n0 - 1)];
+    }
+    __syncthreads();  // the prefetched xi_0
+#pragma unroll
+    for (int r = 0; r < kLevel0Rows; ++r) {
+      const int i = wv + r * (kFusedThreads / 64);
+      if (i >= g.n0) break;  // uniform over the wavefront
+      TA acc = lane <= i ? lrow[r] * xl[lane] : TA(0);
       acc = wave_total(acc);
       if (lane == 0) {
         s0[i] = as_stored<TS>(acc);
@@ -195,18 +222,25 @@ __global__ void __launch_bounds__(kFusedThreads) fused_adj(FusedArgs g) {
   const bool add = g.add != nullptr;
   if (add) {  // fetched with the cotangent, in one round
     const TS* ag = static_cast<const TS*>(g.add) + b * g.n_xi;
-    copy_widen(al, ag, g.pre, t, kFusedThreads);
+    copy_widen<16>(al, ag, g.pre, t, kFusedThreads);
   }
   TS* ws = static_cast<TS*>(g.ws) + b * g.ws_bs;
-  for (int l = 0; l < g.K; ++l) {
-    for (int e = t; e < NC * NW; e += kFusedThreads) mats[l * (NC * NW + NC * NC) + e] = static_cast<const TA*>(g.r[l])[e];
-    for (int e = t; e < NC * NC; e += kFusedThreads)
-      mats[l * (NC * NW + NC * NC) + NC * NW + e] = static_cast<const TA*>(g.s[l])[e];
-  }
+  copy_mats<NC, NW>(mats, g, t);
   {  // the cotangent of level K
     const TS* y = static_cast<const TS*>(g.y) + b * g.y_bs;
     TA* yk = level_lds(fields, g, g.K);
-    copy_widen(yk, y, g.size[g.K], t, kFusedThreads);
+    copy_widen<16>(yk, y, g.size[g.K], t, kFusedThreads);
+  }
+  // this wavefront's rows of U00 (n0 <= 64: a lane per column), loaded with the other inputs
+  const int lane = t % 64, wv = t / 64;
+  TA urow[kLevel0Rows];
+  if (g.level0) {
+    const TA* U = static_cast<const TA*>(g.l0);
+#pragma unroll
+    for (int r = 0; r < kLevel0Rows; ++r) {
+      const int i = min(wv + r * (kFusedThreads / 64), g.n0 - 1);
+      urow[r] = U[int64_t(i) * g.n0 + min(i + lane, g.n0 - 1)];
+    }
   }
   __syncthreads();
   for (int l = g.K - 1; l >= 0; --l) {
@@ -283,12 +317,12 @@ __global__ void __launch_bounds__(kFusedThreads) fused_adj(FusedArgs g) {
     __syncthreads();
   }
   if (g.level0) {  // xi_bar_0 = U00 s_bar_0 (+ add): one wavefront per row
-    const TA* U = static_cast<const TA*>(g.l0);
     const TA* s0 = level_lds(fields, g, 0);
-    const int lane = t % 64, wv = t / 64;
-    for (int i = wv; i < g.n0; i += kFusedThreads / 64) {
-      TA acc = 0;
-      for (int j = i + lane; j < g.n0; j += 64) acc += U[int64_t(i) * g.n0 + j] * s0[j];
+#pragma unroll
+    for (int r = 0; r < kLevel0Rows; ++r) {
+      const int i = wv + r * (kFusedThreads / 64);
+      if (i >= g.n0) break;  // uniform over the wavefront
+      TA acc = i + lane < g.n0 ? urow[r] * s0[i + lane] : TA(0);
       acc = wave_total(acc);
       if (lane == 0) {
         if (add) acc += al[i];

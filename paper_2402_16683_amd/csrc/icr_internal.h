@@ -41,11 +41,10 @@ __device__ __forceinline__ bf16_t f32_to_bf16(float v) {
 __device__ __forceinline__ void store_acc(bf16_t* p, float v) { *p = f32_to_bf16(v); }
 
 // dst[0 .. n) = src[0 .. n) widened to the arithmetic type, by `threads` threads with
-// eight loads per thread in flight (a load-then-store loop would wait for every load in
+// kU loads per thread in flight (a load-then-store loop would wait for every load in
 // turn); reads use clamped in-bounds indices, only the stores are predicated.
-template <typename TA, typename TS>
+template <int kU = 8, typename TA, typename TS>
 __device__ __forceinline__ void copy_widen(TA* dst, const TS* src, int64_t n, int t, int threads) {
-  constexpr int kU = 8;
   for (int64_t base = t; base < n; base += int64_t(kU) * threads) {
     TA v[kU];
 #pragma unroll
