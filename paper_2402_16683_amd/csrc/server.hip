@@ -20,8 +20,8 @@
 //      run the batched sweep (replaying a hipGraph captured once per (plan, op, batch
 //      size) when graphs are enabled and the batch needs at most 1/32 of the arena;
 //      larger batches launch eagerly), scatter the outputs, record an event. A single
-//      request without a graph runs the sweep on its own buffers (only its workspace
-//      comes from the arena).
+//      request without a graph, or with input rows of 16 MiB or more, runs the sweep on
+//      its own buffers (only its workspace comes from the arena).
 // Requests that arrive while others run join the queue and are admitted as streams and
 // memory free up, so work of different priors overlaps on the device. With max_batch = 1,
 // one stream, no graphs and no grouping the same server is the one-launch-per-request
@@ -264,6 +264,9 @@ struct icr_server {
 namespace {
 
 size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// input rows of at least this size are never gathered for a batch of one
+constexpr size_t kDirectRowBytes = size_t(16) << 20;
 
 int64_t in_elems(const PlanEntry& pe, int op) { return op == ICR_OP_ADJOINT ? pe.n_out : pe.n_xi; }
 int64_t out_elems(const PlanEntry& pe, int op) { return op == ICR_OP_FORWARD ? pe.n_out : pe.n_xi; }
@@ -556,7 +559,11 @@ bool launch_batch(icr_server* s, int si, std::vector<int64_t>& ids) {
   // graphs pay off for small, launch-bound batches; a batch larger than 1/32 of the
   // arena runs eagerly so captured graphs never crowd the arena (evicting and
   // recapturing them would cost more host time than the launches they save)
-  const bool use_graph = s->cfg.use_graphs && batch_bytes(pe, op, k) * 32 <= s->arena.capacity();
+  // a lone request with large rows runs on its own buffers even with graphs on: the
+  // gather and scatter around a replay would move its rows twice more, which costs the
+  // device more time than the launches a replay saves the host
+  const bool direct = k == 1 && size_t(in_elems(pe, op)) * pe.elem >= kDirectRowBytes;
+  const bool use_graph = s->cfg.use_graphs && !direct && batch_bytes(pe, op, k) * 32 <= s->arena.capacity();
   if (use_graph) {
     bool oom = false;
     b->graph = find_graph(s, pe, r0.plan_id, op, k, st, &oom);
