@@ -20,7 +20,7 @@
  *    hipGraph captured once per (plan, op, batch size) when use_graphs is set and the
  *    batch needs at most 1/32 of the arena; larger batches launch eagerly), scatter the
  *    outputs, record a completion event (a single request without a graph, or with input
- *    rows of 16 MiB or more, sweeps its own buffers, only its workspace taken from the
+ *    rows of 1 MiB or more, sweeps its own buffers, only its workspace taken from the
  *    arena).
  * Requests that arrive while others run are admitted as streams and memory free up, so
  * work of different priors overlaps on the device. max_batch = 1, n_streams = 1,

@@ -20,7 +20,7 @@
 //      run the batched sweep (replaying a hipGraph captured once per (plan, op, batch
 //      size) when graphs are enabled and the batch needs at most 1/32 of the arena;
 //      larger batches launch eagerly), scatter the outputs, record an event. A single
-//      request without a graph, or with input rows of 16 MiB or more, runs the sweep on
+//      request without a graph, or with input rows of 1 MiB or more, runs the sweep on
 //      its own buffers (only its workspace comes from the arena).
 // Requests that arrive while others run join the queue and are admitted as streams and
 // memory free up, so work of different priors overlaps on the device. With max_batch = 1,
@@ -266,7 +266,7 @@ namespace {
 size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 // input rows of at least this size are never gathered for a batch of one
-constexpr size_t kDirectRowBytes = size_t(16) << 20;
+constexpr size_t kDirectRowBytes = size_t(1) << 20;
 
 int64_t in_elems(const PlanEntry& pe, int op) { return op == ICR_OP_ADJOINT ? pe.n_out : pe.n_xi; }
 int64_t out_elems(const PlanEntry& pe, int op) { return op == ICR_OP_FORWARD ? pe.n_out : pe.n_xi; }

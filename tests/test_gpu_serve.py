@@ -217,6 +217,48 @@ def test_idle_graphs_are_evicted_for_a_large_request():
     server.close()
 
 
+def test_a_lone_request_with_large_rows_skips_the_graph():
+    """With graphs on, a batch of one whose input rows reach 1 MiB sweeps its own buffers
+    (no capture, no gather or scatter) and gives the direct call's bits; a small lone
+    request is still captured."""
+    import torch
+    from paper_2402_16683_amd.serve import Server
+    from paper_2402_16683_amd import icr as B
+    big = C.gpu_plan(C.case(3, (8, 8, 8), 4, (0.06, 0.06, 0.06), "matern52", 0.2, name="big_rows"))
+    small = _plans()[0]
+    assert big.info["n_xi"] * big.info["elem_bytes"] >= 1 << 20
+    assert big.info["n_out"] * big.info["elem_bytes"] >= 1 << 20
+    assert small.info["n_xi"] * small.info["elem_bytes"] < 1 << 20
+    server = Server(hbm_budget_bytes=1 << 30, max_batch=1, n_streams=1, use_graphs=True)
+    bid, sid = server.register(big), server.register(small)
+    for op in ("forward", "adjoint", "metric"):
+        n_in = big.info["n_out"] if op == "adjoint" else big.info["n_xi"]
+        n_out = big.info["n_out"] if op == "forward" else big.info["n_xi"]
+        x = torch.randn(n_in, device="cuda")
+        w = (torch.rand(big.info["n_out"], device="cuda") < 0.7).float() * 10.0
+        out = torch.full((n_out,), float("nan"), device="cuda")
+        torch.cuda.synchronize()
+        rid = server.submit(bid, op, x, out, w if op == "metric" else None)
+        server.drain(30.0)
+        assert server.query(rid)[0]
+        if op == "forward":
+            ref = B.icr_forward(big, x[None])[0]
+        elif op == "adjoint":
+            ref = B.icr_adjoint(big, x[None])[0]
+        else:
+            ref = B.icr_metric_apply(big, w, x[None])[0]
+        assert torch.equal(out, ref), op
+    assert server.stats()["graph_captures"] == 0
+    xs = torch.randn(small.info["n_xi"], device="cuda")
+    out_s = torch.empty(small.info["n_out"], device="cuda")
+    torch.cuda.synchronize()
+    server.submit(sid, "forward", xs, out_s)
+    server.drain(30.0)
+    assert server.stats()["graph_captures"] == 1
+    assert torch.equal(out_s, B.icr_forward(small, xs[None])[0])
+    server.close()
+
+
 # --- grouped mode: requests of any prior and op share launches ----------------------
 
 def _serve_one_at_a_time(server, ids, r):
